@@ -1,0 +1,168 @@
+"""Pins of the oracle's Krylov-Schwarz reference routines (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import scheme as S
+from oracle import schwarz as W
+
+
+def _state(shape, seed=0):
+    g = np.random.default_rng(seed)
+    phi = -0.285 + 0.05 * g.uniform(-1, 1, shape)
+    Phi = phi + 0.01 * g.standard_normal(shape)
+    return Phi, phi
+
+
+def test_decomposition_partitions_grid():
+    shape = (30, 22)
+    doms = W.decompose(shape, (3, 4), 2)
+    cover = np.zeros(shape, int)
+    for d in doms:
+        idx = d.ext_global_indices()
+        own = d.owned_mask_local()
+        cover.ravel()[idx[own]] += 1
+        assert idx.size == np.prod(d.ext_n)
+        assert len(np.unique(idx)) == idx.size
+    assert (cover == 1).all()
+    with pytest.raises(ValueError):
+        W.decompose((16, 16), (1, 4), 1)
+    with pytest.raises(ValueError):
+        W.decompose((16, 16), (2, 2), 3)        # 8 + 6 > 16 - 3
+
+
+@pytest.mark.parametrize("shape,sub,ov", [((16, 14), (2, 2), 2), ((12, 12, 12), (2, 2, 2), 1)])
+def test_subdomain_matrix_equals_zero_ring_problem(shape, sub, ov):
+    # Eq. (25) (restriction of the global Jacobian) and Eq. (26) (subdomain problem
+    # with phi = 0 on the three-layer ring) give the same matrix.
+    h = tuple(0.6 + 0.1 * a for a in range(len(shape)))
+    Phi, phi = _state(shape, 1)
+    dt, g = 0.7, 0.25
+    J = S.jacobian_csr(Phi, phi, dt, g, h)
+    for d in W.decompose(shape, sub, ov)[:3]:
+        A1 = W.subdomain_matrix(J, d).toarray()
+        A2 = W.subdomain_matrix_zero_ring(Phi, phi, dt, g, h, d)
+        np.testing.assert_allclose(A1, A2, atol=1e-12 * np.abs(A1).max())
+        # structural pattern = stencil couplings inside the box
+        pat = W.subdomain_pattern(d.ext_n)
+        for i in range(0, A1.shape[0], 7):
+            assert sorted(np.nonzero(A1[i])[0].tolist()) == pat[i]
+
+
+def test_ilu0_defining_property():
+    shape, h = (16, 16), (np.pi / 2, np.pi / 2)
+    Phi, phi = _state(shape, 2)
+    J = S.jacobian_csr(Phi, phi, 0.1, 0.25, h)
+    d = W.decompose(shape, (2, 2), 2)[3]
+    A = W.subdomain_matrix(J, d).toarray()
+    pat = W.subdomain_pattern(d.ext_n)
+    rows = W.ilu0(A, pat)
+    L, U = W.ilu0_dense_factors(rows)
+    LU = L @ U
+    for i, p in enumerate(pat):
+        np.testing.assert_allclose(LU[i, p], A[i, p], atol=1e-12 * np.abs(A).max())
+        # no entry outside the pattern
+        outside = np.setdiff1d(np.arange(A.shape[0]), p)
+        assert np.all(L[i, outside[outside < i]] == 0) and np.all(U[i, outside[outside > i]] == 0)
+    b = np.random.default_rng(3).standard_normal(A.shape[0])
+    np.testing.assert_allclose(W.ilu0_solve(rows, b), np.linalg.solve(LU, b), rtol=1e-10, atol=1e-12)
+
+
+def test_ilu0_is_exact_when_pattern_is_full():
+    # in a 2x3 box every pair of cells is within |dx|+|dy| <= 3, so the pattern is
+    # full, no fill is dropped and ILU(0) is the exact LU factorisation.
+    rng = np.random.default_rng(4)
+    ext = (2, 3)
+    pat = W.subdomain_pattern(ext)
+    assert all(len(p) == 6 for p in pat)
+    A = rng.standard_normal((6, 6)) + 8 * np.eye(6)
+    rows = W.ilu0(A, pat)
+    b = rng.standard_normal(6)
+    np.testing.assert_allclose(W.ilu0_solve(rows, b), np.linalg.solve(A, b), rtol=1e-12)
+
+
+def test_ilu0_tridiagonal_no_fill_is_exact():
+    n = 12
+    rng = np.random.default_rng(5)
+    A = np.diag(4 + rng.uniform(size=n)) + np.diag(rng.uniform(size=n - 1), 1) + np.diag(rng.uniform(size=n - 1), -1)
+    pat = [[j for j in (i - 1, i, i + 1) if 0 <= j < n] for i in range(n)]
+    rows = W.ilu0(A, pat)
+    b = rng.standard_normal(n)
+    np.testing.assert_allclose(W.ilu0_solve(rows, b), np.linalg.solve(A, b), rtol=1e-12)
+
+
+def test_schwarz_overlap0_is_block_jacobi_and_variants_agree():
+    shape, h = (16, 16), (0.8, 0.8)
+    Phi, phi = _state(shape, 6)
+    J = S.jacobian_csr(Phi, phi, 0.5, 0.25, h)
+    doms = W.decompose(shape, (2, 2), 0)
+    sol = W.schwarz_setup(J, doms, "lu")
+    r = np.random.default_rng(7).standard_normal(shape)
+    Jd = J.toarray()
+    expect = np.zeros(r.size)
+    for d in doms:
+        idx = d.ext_global_indices()
+        expect[idx] = np.linalg.solve(Jd[np.ix_(idx, idx)], r.ravel()[idx])
+    for var in ("left", "right", "as"):
+        np.testing.assert_allclose(W.schwarz_apply(r, doms, sol, var).ravel(), expect, rtol=1e-10, atol=1e-12)
+
+
+def test_left_ras_matches_dense_definition():
+    # Eq. (23) written with dense solves of the zero-ring subdomain problems (Eq. (26))
+    shape, h = (20, 18), (0.9, 0.9)
+    Phi, phi = _state(shape, 8)
+    dt, g = 1.0, 0.25
+    J = S.jacobian_csr(Phi, phi, dt, g, h)
+    doms = W.decompose(shape, (2, 3), 2)
+    sol = W.schwarz_setup(J, doms, "lu")
+    r = np.random.default_rng(9).standard_normal(shape)
+    z = W.schwarz_apply(r, doms, sol, "left").ravel()
+    expect = np.zeros(r.size)
+    for d in doms:
+        A = W.subdomain_matrix_zero_ring(Phi, phi, dt, g, h, d)
+        idx = d.ext_global_indices()
+        y = np.linalg.solve(A, r.ravel()[idx])
+        own = d.owned_mask_local()
+        expect[idx[own]] = y[own]
+    np.testing.assert_allclose(z, expect, rtol=1e-10, atol=1e-12)
+    # AS adds the overlapped parts: its owned part differs, its total is the sum of all extensions
+    z_as = W.schwarz_apply(r, doms, sol, "as").ravel()
+    tot = 0.0
+    for d in doms:
+        A = W.subdomain_matrix_zero_ring(Phi, phi, dt, g, h, d)
+        tot += np.linalg.solve(A, r.ravel()[d.ext_global_indices()]).sum()
+    assert abs(z_as.sum() - tot) < 1e-9 * np.abs(z_as).sum()
+
+
+def test_fgmres_identity_full_restart_is_direct_solve():
+    rng = np.random.default_rng(10)
+    n = 40
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) / np.sqrt(n)
+    b = rng.standard_normal(n)
+    res = W.fgmres(lambda x: A @ x, lambda v: v, b, 1e-14, 0.0, restart=n, maxit=n)
+    np.testing.assert_allclose(res.x, np.linalg.solve(A, b), rtol=1e-10)
+    # monitored residual is non-increasing and is the true residual at the end
+    assert all(b2 <= b1 * (1 + 1e-12) for b1, b2 in zip(res.res_history, res.res_history[1:]))
+
+
+def test_arnoldi_relation_and_orthonormality():
+    rng = np.random.default_rng(11)
+    n, m = 60, 12
+    A = np.eye(n) + rng.standard_normal((n, n)) / np.sqrt(n)
+    P = np.diag(1 + rng.uniform(size=n))
+    V, Z, H = W.arnoldi_mgs(lambda x: A @ x, lambda v: P @ v, rng.standard_normal(n), m)
+    np.testing.assert_allclose(A @ Z.T, V.T @ H, atol=1e-12)
+    np.testing.assert_allclose(V @ V.T, np.eye(m + 1), atol=1e-12)
+
+
+def test_fgmres_stopping_rule_with_ras():
+    # the linear test of Sec. 4: ||J S + F|| <= max(xi_r ||F||, xi_a) at exit
+    shape, h = (24, 24), (np.pi / 2, np.pi / 2)
+    Phi, phi = _state(shape, 12)
+    J = S.jacobian_csr(Phi, phi, 0.1, 0.25, h)
+    doms = W.decompose(shape, (2, 2), 2)
+    sol = W.schwarz_setup(J, doms, "ilu0")
+    F = S.residual(Phi, phi, 0.1, 0.25, h).ravel()
+    res = W.fgmres(lambda x: J @ x, lambda r: W.schwarz_apply(r, doms, sol, "left"), -F, 1e-3, 1e-11)
+    true = np.linalg.norm(J @ res.x + F)
+    assert true <= 1.0001 * max(1e-3 * np.linalg.norm(F), 1e-11)
+    assert res.iterations <= 5      # ILU(0)-RAS is an excellent preconditioner at h = pi/2

@@ -1,0 +1,181 @@
+"""Benchmark: PFC time steps per second on the 1024^2 crystal-growth workload.
+
+One "step" is one time step of the scheme: adaptive dt, initial guess, the full
+Newton-Krylov-Schwarz solve and the energy/mass evaluation of the accepted state.
+Workload: 1024^2 periodic grid on [0, 400]^2, gamma = 0.25, mean density -0.285 with
+three hexagonal crystallites (disks of radius 10 cells), adaptive dt in [1e-2, 10]
+with eta = 5000, tolerances eps_r = 1e-8, eps_a = 1e-10, xi_r = 1e-3, xi_a = 1e-11.
+
+Warm-up steps run from the initial state, then the solver history is reset and the
+timed steps run from the initial state again (the timed region is the first K steps
+of the trajectory).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+
+VARIANTS = {
+    # the paper's method as configured: FP64 everywhere, 16 x 16 subdomains, overlap 4,
+    # exact subdomain LU factored once per step, previous solution as initial guess
+    "plain": dict(sub=(16, 16), overlap=4, sub_solver="lu", precond_fp32=False, guess="previous"),
+    # FP32 subdomain factors inside flexible GMRES, 24-cell-wide boxes (64 x 16 owned,
+    # overlap 4), extrapolated initial guess; residual, Arnoldi and energy stay FP64
+    "fast": dict(sub=(16, 64), overlap=4, sub_solver="lu", precond_fp32=True, guess="extrap"),
+}
+
+
+def apply_bytes(shape, sub, overlap, sub_solver, fp32):
+    """Algorithmic HBM bytes of one preconditioner apply (factor reads + r gather + z write)."""
+    ny, nx = shape
+    esz = 4 if fp32 else 8
+    oy, ox = ny // sub[0], nx // sub[1]
+    ey, ex = oy + 2 * overlap, ox + 2 * overlap
+    nsub = sub[0] * sub[1]
+    if sub_solver == "lu":
+        W, H = ex, ey
+        fac = H * (7 * W * W + W)           # nonzeros of the stored block rows
+    else:
+        fac = 0
+        for y in range(ey):
+            for x in range(ex):
+                fac += sum(1 for dy in range(-3, 4) for dx in range(-3, 4)
+                           if abs(dx) + abs(dy) <= 3 and 0 <= x + dx < ex and 0 <= y + dy < ey)
+    return nsub * (fac * esz + ex * ey * 8) + nx * ny * 8
+
+
+def cpu_baseline(nsteps=2):
+    """The FP64 oracle on the first ``nsteps`` steps of the same workload (host cores)."""
+    import numpy as np  # noqa: F401
+    import pfc_inputs as I
+    from oracle import scheme as S
+    w = I.crystal_growth_1024()
+    h = S.spacing(w.shape, w.lengths)
+    phi = w.initial()
+    t0 = time.perf_counter()
+    tr = S.run(phi, nsteps, w.gamma, h, w.dt_min, w.dt_max, w.eta, linear="fftgmres", keep_all=False)
+    el = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": nsteps / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {nsteps} steps of the 1024^2 crystal trajectory (dt = {tr.dts}), "
+                      f"Newton + FFT-preconditioned GMRES, scipy/numpy FP64, {el:.1f} s"}
+
+
+def run_variant(name, steps, warmup, timing=True):
+    import torch
+    import paper_1703_01202_amd as pfc
+    import pfc_inputs as I
+    w = I.crystal_growth_1024()
+    v = VARIANTS[name]
+    phi0 = torch.tensor(w.initial(), dtype=torch.float64, device="cuda")
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, v["sub"], v["overlap"], sub_solver=v["sub_solver"],
+                   precond_fp32=v["precond_fp32"], guess=v["guess"], dt_min=w.dt_min, dt_max=w.dt_max,
+                   eta=w.eta, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol, lin_rtol=w.lin_rtol,
+                   lin_atol=w.lin_atol, timing=timing)
+    phi = phi0.clone()
+    for i in range(warmup):
+        s.step(phi)
+        print(f"[bench] {name} warmup step {i} done", file=sys.stderr, flush=True)
+    s.reset()
+    phi.copy_(phi0)
+    torch.cuda.synchronize()
+    newton = gmres = rejected = 0
+    t0 = time.perf_counter()
+    last = {}
+    for i in range(steps):
+        st = s.step(phi)
+        newton += st["newton_its"]
+        gmres += st["gmres_its"]
+        rejected += st["rejected"]
+        last = st
+        if steps <= 50 or (i + 1) % 25 == 0:
+            print(f"[bench] {name} step {i + 1}/{steps} t={st['t']:.2f} dt={st['dt']:.3g} "
+                  f"newton={st['newton_its']} gmres={st['gmres_its']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {k: s.kernel_time(k) for k in range(4)}
+    s.close()
+    N = w.shape[0] * w.shape[1]
+    res = {"steps": steps, "seconds": el, "steps_per_s": steps / el, "dof_steps_per_s": N * steps / el,
+           "newton_its": newton, "gmres_its": gmres, "gmres_per_newton": gmres / max(newton, 1),
+           "rejected": rejected, "t_end": last.get("t"), "energy_end": last.get("energy"),
+           "mass_end": last.get("mass"), "kernels": kt, "variant": v}
+    # roofline of the dominant kernel (largest summed event time)
+    names = {0: "ras_apply", 1: "residual", 2: "jacobian_action", 3: "factorisation"}
+    bytes_per = {0: apply_bytes(w.shape, v["sub"], v["overlap"], v["sub_solver"], v["precond_fp32"]),
+                 1: 24 * N, 2: 24 * N}
+    dom = max((k for k in (0, 1, 2)), key=lambda k: kt[k][1])
+    cnt, ms = kt[dom]
+    avg_s = ms / 1e3 / max(cnt, 1)
+    gbs = bytes_per[dom] / avg_s / 1e9 if cnt else 0.0
+    res["roofline"] = {"kernel": names[dom], "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                       "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                       "bytes_per_launch": bytes_per[dom], "avg_launch_us": avg_s * 1e6, "launches": cnt,
+                       "factorisation_ms_total": kt[3][1]}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variant", default="fast", choices=sorted(VARIANTS))
+    ap.add_argument("--compare", default="plain", help="second variant timed beside (or 'none')")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    main_res = run_variant(args.variant, args.steps, args.warmup)
+    cmp_res = None
+    if args.compare != "none" and args.compare != args.variant:
+        cmp_res = run_variant(args.compare, args.steps, args.warmup)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
+    out = {
+        "metric": "PFC time steps/s, 2D 1024^2 NKS",
+        "value": main_res["steps_per_s"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * main_res["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if not VARIANTS[args.variant]["precond_fp32"] else "f64 (f32 preconditioner)",
+        "data": "synthetic",
+        "config": {"workload": "pfc2d_1024_crystal: 1024^2 periodic, [0,400]^2, gamma 0.25, mean -0.285, "
+                               "3 hex crystallites r=10 cells, adaptive dt 1e-2..10 eta 5000",
+                   "variant": args.variant, "dof": 1024 * 1024},
+        "dof_steps_per_s": main_res["dof_steps_per_s"],
+        "newton_its": main_res["newton_its"],
+        "gmres_per_newton": main_res["gmres_per_newton"],
+        "roofline": main_res["roofline"],
+        "cpu_baseline": cpu,
+        "detail": {args.variant: main_res},
+    }
+    if cmp_res is not None:
+        out["compare"] = {"variant": args.compare, "steps_per_s": cmp_res["steps_per_s"],
+                          "newton_its": cmp_res["newton_its"], "gmres_per_newton": cmp_res["gmres_per_newton"],
+                          "roofline": cmp_res["roofline"],
+                          "speedup": main_res["steps_per_s"] / cmp_res["steps_per_s"]}
+        out["detail"][args.compare] = cmp_res
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+"""MI355X (gfx950) Newton-Krylov-Schwarz solver for the energy-stable PFC scheme.
+
+Python face of ``libpfc.so``: the ``Solver`` methods map one to one onto the C entry
+points of ``include/pfc.h`` (``pfc_residual``, ``pfc_jv``, ``pfc_ras_setup``,
+``pfc_ras_apply``, ``pfc_energy``, ``pfc_gmres``, ``pfc_newton``, ``pfc_step``).
+Fields are torch float64 tensors on the GPU with the array layout (ny, nx) or
+(nz, ny, nx); every computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import PfcError, PfcStepStats
+
+__all__ = ["Solver", "PfcError", "PfcStepStats", "load"]
+
+load = _lib.load
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One PFC grid with its solver workspace (a ``pfc_ctx``).
+
+    ``shape`` and ``lengths`` follow the array axes, (ny, nx) or (nz, ny, nx);
+    ``sub`` (subdomains per axis) too.  ``overlap`` is in mesh layers.
+    """
+
+    def __init__(self, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precond_fp32=False,
+                 dt_min=0.1, dt_max=None, eta=0.0, newton_rtol=1e-8, newton_atol=1e-10,
+                 lin_rtol=1e-3, lin_atol=1e-11, gmres_restart=30, gmres_maxit=300, newton_maxit=50,
+                 guess="previous", mass_project=True, max_retries=4, timing=False, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = _lib.load()
+        self.shape = tuple(int(s) for s in shape)
+        dim = len(self.shape)
+        if dim not in (2, 3):
+            raise ValueError("shape must be 2-D or 3-D")
+        g = _lib.PfcGrid()
+        g.dim = dim
+        rev = list(reversed(self.shape))
+        revL = list(reversed([float(x) for x in lengths]))
+        revS = list(reversed([int(x) for x in sub]))
+        for a in range(3):
+            g.n[a] = rev[a] if a < dim else 1
+            g.L[a] = revL[a] if a < dim else 1.0
+        m = _lib.PfcModel()
+        m.gamma = float(gamma)
+        m.mobility = 0
+        o = _lib.PfcOpts()
+        self.lib.pfc_default_opts(ctypes.byref(o))
+        o.newton_rtol, o.newton_atol = newton_rtol, newton_atol
+        o.lin_rtol, o.lin_atol = lin_rtol, lin_atol
+        o.newton_maxit, o.gmres_restart, o.gmres_maxit = newton_maxit, gmres_restart, gmres_maxit
+        for a in range(3):
+            o.sub[a] = revS[a] if a < dim else 1
+        o.overlap = int(overlap)
+        o.sub_solver = _lib.SUB_SOLVERS[sub_solver]
+        o.precond_fp32 = int(bool(precond_fp32))
+        o.mass_project = int(bool(mass_project))
+        o.guess = _lib.GUESS[guess]
+        o.dt_min = float(dt_min)
+        o.dt_max = float(dt_max if dt_max is not None else dt_min)
+        o.eta = float(eta)
+        o.max_retries = int(max_retries)
+        o.timing = int(bool(timing))
+        self.opts = o
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        ctx = ctypes.c_void_p()
+        st = self.lib.pfc_create(ctypes.byref(g), ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(stream),
+                                 ctypes.byref(ctx))
+        if st != _lib.PFC_OK:
+            raise PfcError(st, "pfc_create failed (see stderr)")
+        self.ctx = ctx
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, status):
+        if status != _lib.PFC_OK:
+            raise PfcError(status, self.lib.pfc_last_error(self.ctx).decode())
+
+    def _field(self, t, name):
+        torch = self._torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and tuple(t.shape) == self.shape):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {self.shape}")
+        return _ptr(t)
+
+    def _empty(self):
+        return self._torch.empty(self.shape, dtype=self._torch.float64, device="cuda")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pfc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C entry points -------------------------------------------------------
+    def residual(self, Phi, phi, dt, src=None, out=None, want_norm=True):
+        F = out if out is not None else self._empty()
+        nrm = ctypes.c_double(0.0)
+        self._check(self.lib.pfc_residual(self.ctx, self._field(Phi, "Phi"), self._field(phi, "phi"), float(dt),
+                                          self._field(src, "src") if src is not None else None,
+                                          self._field(F, "F"), ctypes.byref(nrm) if want_norm else None))
+        return F, nrm.value
+
+    def jv(self, Phi, phi, dt, v, out=None):
+        J = out if out is not None else self._empty()
+        self._check(self.lib.pfc_jv(self.ctx, self._field(Phi, "Phi"), self._field(phi, "phi"), float(dt),
+                                    self._field(v, "v"), self._field(J, "Jv")))
+        return J
+
+    def ras_setup(self, Phi, phi, dt):
+        self._check(self.lib.pfc_ras_setup(self.ctx, self._field(Phi, "Phi"), self._field(phi, "phi"), float(dt)))
+
+    def ras_apply(self, r, out=None):
+        z = out if out is not None else self._empty()
+        self._check(self.lib.pfc_ras_apply(self.ctx, self._field(r, "r"), self._field(z, "z")))
+        return z
+
+    def energy(self, phi):
+        e, m = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(self.lib.pfc_energy(self.ctx, self._field(phi, "phi"), ctypes.byref(e), ctypes.byref(m)))
+        return e.value, m.value
+
+    def gmres(self, Phi, phi, dt, b, rtol, atol):
+        x = self._empty()
+        its, res = ctypes.c_int(0), ctypes.c_double(0.0)
+        self._check(self.lib.pfc_gmres(self.ctx, self._field(Phi, "Phi"), self._field(phi, "phi"), float(dt),
+                                       self._field(b, "b"), self._field(x, "x"), float(rtol), float(atol),
+                                       ctypes.byref(its), ctypes.byref(res)))
+        return x, its.value, res.value
+
+    def newton(self, phi, dt, Phi0=None):
+        Phi = (Phi0 if Phi0 is not None else phi).clone()
+        st = PfcStepStats()
+        self._check(self.lib.pfc_newton(self.ctx, self._field(phi, "phi"), float(dt), self._field(Phi, "Phi"),
+                                        ctypes.byref(st)))
+        return Phi, st.as_dict()
+
+    def step(self, phi):
+        st = PfcStepStats()
+        self._check(self.lib.pfc_step(self.ctx, self._field(phi, "phi"), ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset(self):
+        self._check(self.lib.pfc_reset(self.ctx))
+
+    def kernel_time(self, which):
+        cnt, ms = ctypes.c_long(0), ctypes.c_double(0.0)
+        self._check(self.lib.pfc_kernel_time(self.ctx, int(which), ctypes.byref(cnt), ctypes.byref(ms)))
+        return cnt.value, ms.value

@@ -1,0 +1,104 @@
+"""ctypes binding of ``libpfc.so`` (argument marshalling only; all work runs in HIP).
+
+The names mirror the C ABI of ``include/pfc.h``.  Fields are torch float64 CUDA
+tensors; the library works on their device pointers and on the current torch
+stream.  There is no fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfc.so")
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+
+PFC_OK = 0
+STATUS = {0: "PFC_OK", -1: "PFC_EINVAL", -2: "PFC_ENOMEM", -3: "PFC_EHIP", -4: "PFC_ENAN",
+          -5: "PFC_ENOTCONV", -6: "PFC_EKRYLOV", -7: "PFC_EPIVOT", -8: "PFC_EUNSUP"}
+SUB_SOLVERS = {"ilu0": 0, "lu": 1}
+GUESS = {"previous": 0, "extrap": 1, "learned": 2}
+
+
+class PfcGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3)]
+
+
+class PfcModel(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("mobility", ctypes.c_int)]
+
+
+class PfcOpts(ctypes.Structure):
+    _fields_ = [
+        ("newton_rtol", ctypes.c_double), ("newton_atol", ctypes.c_double),
+        ("lin_rtol", ctypes.c_double), ("lin_atol", ctypes.c_double),
+        ("newton_maxit", ctypes.c_int), ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int),
+        ("sub", ctypes.c_int * 3), ("overlap", ctypes.c_int), ("ras_kind", ctypes.c_int),
+        ("sub_solver", ctypes.c_int), ("precond_fp32", ctypes.c_int), ("mass_project", ctypes.c_int),
+        ("guess", ctypes.c_int),
+        ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double), ("eta", ctypes.c_double),
+        ("max_retries", ctypes.c_int), ("timing", ctypes.c_int),
+    ]
+
+
+class PfcStepStats(ctypes.Structure):
+    _fields_ = [
+        ("newton_its", ctypes.c_int), ("gmres_its", ctypes.c_int), ("ls_cuts", ctypes.c_int),
+        ("rejected", ctypes.c_int), ("guess_used", ctypes.c_int),
+        ("dt", ctypes.c_double), ("t", ctypes.c_double), ("energy", ctypes.c_double),
+        ("mass", ctypes.c_double), ("res0", ctypes.c_double), ("res_final", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# symbol -> (restype, argtypes)
+SIGNATURES = {
+    "pfc_default_opts": (None, [ctypes.POINTER(PfcOpts)]),
+    "pfc_create": (ctypes.c_int, [ctypes.POINTER(PfcGrid), ctypes.POINTER(PfcModel), ctypes.POINTER(PfcOpts),
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pfc_destroy": (None, [ctypes.c_void_p]),
+    "pfc_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pfc_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.c_void_p, ctypes.c_void_p, c_double_p]),
+    "pfc_jv": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                              ctypes.c_void_p, ctypes.c_void_p]),
+    "pfc_ras_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
+    "pfc_ras_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pfc_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_double_p]),
+    "pfc_gmres": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_int), c_double_p]),
+    "pfc_newton": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                  ctypes.POINTER(PfcStepStats)]),
+    "pfc_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PfcStepStats)]),
+    "pfc_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "pfc_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_long), c_double_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libpfc.so once; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpfc.so not found at {LIB_PATH}: run paper_1703_01202_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PfcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status

@@ -1,0 +1,142 @@
+// Internal declarations of libpfc (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pfc.h"
+
+namespace pfc {
+
+constexpr int kMaxStencil = 63;        // composite stencil |dx|+|dy|+|dz| <= 3 in 3-D
+constexpr int kRedBlocks = 512;        // fixed reduction grid: deterministic partial sums
+constexpr int kRedThreads = 256;
+
+// Mesh: n[0] = nx (fastest), spacing h[a] = L[a]/n[a].
+struct Geom {
+    int dim;
+    int nx, ny, nz;
+    long N;
+    double ihx2, ihy2, ihz2;           // 1/h^2 per axis (ihz2 = 0 in 2-D)
+    double cell_volume;
+};
+
+// Constant-coefficient stencil of the Jacobian in one subdomain row, in natural
+// (z, y, x lexicographic) order of the offsets.  J_ij = kconst[s] - d1[s] * c_j with
+// j = i + offset s (Sec. 4, Eq. (19) written entry by entry).
+struct StencilTable {
+    int S;                             // 25 (2-D) or 63 (3-D)
+    int diag;                          // index of the zero offset
+    int8_t dx[kMaxStencil], dy[kMaxStencil], dz[kMaxStencil];
+    double kconst[kMaxStencil];
+    double d1[kMaxStencil];
+};
+
+// Overlapping decomposition: equal boxes of own[a] cells, extended by `ov` layers.
+struct Decomp {
+    int sub[3];
+    int own[3];
+    int ext[3];
+    int ov;
+    int nsub;
+    int next;                          // cells per extended box
+};
+
+// Event-pair timer for per-kernel durations on the context stream.
+struct KernelTimer {
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, int>> pending;   // (start idx, kind)
+    int used = 0;
+    long count[4] = {0, 0, 0, 0};
+    double total_ms[4] = {0, 0, 0, 0};
+};
+
+}  // namespace pfc
+
+struct pfc_ctx {
+    pfc_grid grid;
+    pfc_model model;
+    pfc_opts opts;
+    hipStream_t stream = nullptr;
+    pfc::Geom g;
+    pfc::Decomp dec;
+    pfc::StencilTable st;              // Jacobian stencil at the last factorisation (offsets fixed)
+    std::string err;
+
+    // ILU(0) level schedule, shared by all boxes (same shape): points sorted by level
+    int nlev = 0;
+    int* d_level_ptr = nullptr;        // [nlev + 1]
+    int* d_level_pts = nullptr;        // [next], packed coords x | y << 8 | z << 16
+    int8_t* d_pair = nullptr;          // [S*S] index of offset(t) - offset(s), or -1
+
+    // factors
+    double* d_work = nullptr;          // ILU natural-layout workspace / LU window (FP64)
+    void* d_fac = nullptr;             // packed factors (double or float)
+    size_t fac_elems = 0;
+    int* d_flag = nullptr;             // pivot failure flag
+    int lu_W = 0, lu_H = 0;            // exact LU: block size (box x-extent) and block rows
+
+    // vectors (N doubles each)
+    double* d_c = nullptr;             // Jacobian coefficient at the current iterate
+    double* d_F = nullptr;
+    double* d_X = nullptr;             // Newton iterate
+    double* d_T = nullptr;             // line-search trial
+    double* d_S = nullptr;             // Newton direction
+    double* d_w = nullptr;
+    double* d_r = nullptr;
+    double* d_V = nullptr;             // (restart+1) * N
+    double* d_Z = nullptr;             // restart * N
+    double* d_prev = nullptr;          // phi^(n-1) for extrapolation
+    double* d_tmp3 = nullptr;          // 3-D multi-pass temporaries (2 * N)
+
+    // reductions
+    double* d_part = nullptr;          // kRedBlocks * 64 partials
+    double* d_scal = nullptr;          // 256 device scalars
+    double* h_pin = nullptr;           // pinned host mirror (256 doubles)
+
+    // time history
+    long step = 0;
+    double F_n = 0, F_nm1 = 0, dt_nm1 = 0, t = 0;
+    bool have_prev = false, have_energy = false;
+
+    pfc::KernelTimer timer;
+};
+
+namespace pfc {
+
+// ---- stencil kernels (stencil.hip) ----
+hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
+                           const double* src, double* F, double* partials);
+hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, double* cbuf);
+hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt,
+                     const double* vshift, double* Jv);
+hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* partials);
+
+// ---- BLAS-1 and reductions (blas.hip) ----
+hipError_t launch_dot_partials(hipStream_t s, const double* x, const double* y, long n,
+                               double* partials);
+hipError_t launch_sum_partials(hipStream_t s, const double* x, long n, double* partials);
+hipError_t launch_reduce_rows(hipStream_t s, const double* partials, int rows, double* out,
+                              double scale);
+hipError_t launch_multidot(hipStream_t s, const double* V, long ld, int k, const double* w,
+                           long n, double* partials);
+hipError_t launch_maxpy(hipStream_t s, const double* V, long ld, int k, const double* coef,
+                        double sign, double* w, long n, double* norm_partials);
+hipError_t launch_axpby(hipStream_t s, double a, const double* x, double b, const double* y,
+                        double* out, long n);
+hipError_t launch_scale(hipStream_t s, const double* x, double a, double* out, long n);
+hipError_t launch_shift(hipStream_t s, double* x, const double* dev_scalar, double sign, long n);
+hipError_t launch_extrap(hipStream_t s, const double* phi, const double* prev, double ratio,
+                         double* out, long n);
+
+// ---- Schwarz preconditioner (ras_ilu.hip, ras_lu.hip) ----
+void build_stencil_table(const Geom& g, double gamma, double dt, StencilTable* t);
+hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& t);
+hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z);
+hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& t);
+hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z);
+
+}  // namespace pfc

@@ -1,0 +1,313 @@
+// Restricted additive Schwarz with ILU(0) subdomain solves (Sec. 4, Eqs. (23), (25), (26)).
+//
+// Subdomain matrix: A_k = R_k J R_k^T, which is the Jacobian of the subdomain problem
+// with phi = 0 on the three-layer ring around the extended box.  Row i of A_k has one
+// entry per composite-stencil offset o with i + o inside the box:
+//     A(i, i+o) = kconst(o) - d1(o) * c(i+o)
+// (kconst: I/dt - (1-gamma)/2 Delta - Delta^2 - 1/2 Delta^3, d1: Delta; c from Eq. (19)).
+//
+// ILU(0) keeps exactly that pattern, natural (z, y, x) order, IKJ elimination.  Rows
+// are scheduled by the wavefront level x + 3y (2-D) / x + 3y + 7z (3-D): every
+// lower-triangular neighbour of a cell has a strictly smaller level, so all cells of
+// one level factor and solve independently.  One workgroup per subdomain; the solve
+// keeps the box vector in LDS and streams the factors, packed level by level with the
+// stencil index outermost so that the lanes of a level read consecutive addresses.
+#include <algorithm>
+#include <map>
+
+#include "pfc_internal.h"
+
+namespace pfc {
+
+void build_stencil_table(const Geom& g, double gamma, double dt, StencilTable* t) {
+    // D1 = Delta_d, D2 = D1 * D1, D3 = D2 * D1 as 7x7x7 offset maps (index (dz+3, dy+3, dx+3)).
+    static thread_local double d1[7][7][7], d2[7][7][7], d3[7][7][7];
+    for (int a = 0; a < 7; ++a)
+        for (int b = 0; b < 7; ++b)
+            for (int c = 0; c < 7; ++c) d1[a][b][c] = d2[a][b][c] = d3[a][b][c] = 0.0;
+    d1[3][3][3] = -2.0 * (g.ihx2 + g.ihy2 + (g.dim == 3 ? g.ihz2 : 0.0));
+    d1[3][3][4] += g.ihx2;
+    d1[3][3][2] += g.ihx2;
+    d1[3][4][3] += g.ihy2;
+    d1[3][2][3] += g.ihy2;
+    if (g.dim == 3) {
+        d1[4][3][3] += g.ihz2;
+        d1[2][3][3] += g.ihz2;
+    }
+    auto conv = [](double (*a)[7][7], double (*b)[7][7], double (*out)[7][7]) {
+        for (int z = 0; z < 7; ++z)
+            for (int y = 0; y < 7; ++y)
+                for (int x = 0; x < 7; ++x) {
+                    if (a[z][y][x] == 0.0) continue;
+                    for (int dz = -1; dz <= 1; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const double bv = b[3 + dz][3 + dy][3 + dx];
+                                if (bv == 0.0) continue;
+                                const int zz = z + dz, yy = y + dy, xx = x + dx;
+                                if (zz < 0 || zz > 6 || yy < 0 || yy > 6 || xx < 0 || xx > 6) continue;
+                                out[zz][yy][xx] += a[z][y][x] * bv;
+                            }
+                }
+    };
+    conv(d1, d1, d2);
+    conv(d2, d1, d3);
+    int s = 0;
+    const int zr = g.dim == 3 ? 3 : 0;
+    for (int dz = -zr; dz <= zr; ++dz)
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dx = -3; dx <= 3; ++dx) {
+                if (std::abs(dx) + std::abs(dy) + std::abs(dz) > 3) continue;
+                t->dx[s] = (int8_t)dx;
+                t->dy[s] = (int8_t)dy;
+                t->dz[s] = (int8_t)dz;
+                const double k1 = d1[3 + dz][3 + dy][3 + dx];
+                const double k2 = d2[3 + dz][3 + dy][3 + dx];
+                const double k3 = d3[3 + dz][3 + dy][3 + dx];
+                double kc = -0.5 * (1.0 - gamma) * k1 - k2 - 0.5 * k3;
+                if (dx == 0 && dy == 0 && dz == 0) {
+                    kc += 1.0 / dt;
+                    t->diag = s;
+                }
+                t->kconst[s] = kc;
+                t->d1[s] = k1;
+                ++s;
+            }
+    t->S = s;
+}
+
+namespace {
+
+struct Box {
+    int ex, ey, ez, next;
+    int subx, suby, ownx, owny, ownz, ov;
+    int nx, ny, nz;
+};
+
+__device__ __forceinline__ int wrapg(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+__device__ __forceinline__ void box_origin(const Box& b, int k, int* ox, int* oy, int* oz) {
+    const int kx = k % b.subx, ky = (k / b.subx) % b.suby, kz = k / (b.subx * b.suby);
+    *ox = kx * b.ownx - b.ov;
+    *oy = ky * b.owny - b.ov;
+    *oz = b.nz > 1 ? kz * b.ownz - b.ov : 0;
+}
+
+__device__ __forceinline__ long gidx(const Box& b, int ox, int oy, int oz, int x, int y, int z) {
+    const int gx = wrapg(ox + x, b.nx), gy = wrapg(oy + y, b.ny), gz = b.nz > 1 ? wrapg(oz + z, b.nz) : 0;
+    return ((long)gz * b.ny + gy) * b.nx + gx;
+}
+
+__device__ __forceinline__ bool inbox(const Box& b, int x, int y, int z) {
+    return x >= 0 && x < b.ex && y >= 0 && y < b.ey && z >= 0 && z < b.ez;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ cc,
+                                                    const int* __restrict__ lptr,
+                                                    const int* __restrict__ lpts,
+                                                    const int8_t* __restrict__ pair, double* __restrict__ work,
+                                                    T* __restrict__ fac, int* __restrict__ flag, Box b,
+                                                    StencilTable st, int nlev) {
+    __shared__ int8_t spair[kMaxStencil * kMaxStencil];
+    const int S = st.S, D = st.diag;
+    const int k = blockIdx.x;
+    int ox, oy, oz;
+    box_origin(b, k, &ox, &oy, &oz);
+    double* W = work + (long)k * b.next * S;
+    for (int e = threadIdx.x; e < S * S; e += blockDim.x) spair[e] = pair[e];
+    // assemble A_k row by row
+    for (int i = threadIdx.x; i < b.next; i += blockDim.x) {
+        const int x = i % b.ex, y = (i / b.ex) % b.ey, z = i / (b.ex * b.ey);
+        for (int s = 0; s < S; ++s) {
+            const int xx = x + st.dx[s], yy = y + st.dy[s], zz = z + st.dz[s];
+            double v = 0.0;
+            if (inbox(b, xx, yy, zz)) v = st.kconst[s] - st.d1[s] * cc[gidx(b, ox, oy, oz, xx, yy, zz)];
+            W[(long)i * S + s] = v;
+        }
+    }
+    __syncthreads();
+    for (int lev = 0; lev < nlev; ++lev) {
+        for (int p = lptr[lev] + threadIdx.x; p < lptr[lev + 1]; p += blockDim.x) {
+            const int pk = lpts[p];
+            const int x = pk & 255, y = (pk >> 8) & 255, z = pk >> 16;
+            const long i = ((long)z * b.ey + y) * b.ex + x;
+            double* row = W + i * S;
+            for (int s = 0; s < D; ++s) {
+                if (!inbox(b, x + st.dx[s], y + st.dy[s], z + st.dz[s])) continue;
+                const long kk = i + ((long)st.dz[s] * b.ey + st.dy[s]) * b.ex + st.dx[s];
+                const double* rk = W + kk * S;
+                const double aik = row[s] / rk[D];
+                row[s] = aik;
+                for (int t = s + 1; t < S; ++t) {
+                    const int u = spair[s * S + t];
+                    if (u < 0) continue;
+                    if (!inbox(b, x + st.dx[t], y + st.dy[t], z + st.dz[t])) continue;
+                    row[t] -= aik * rk[u];
+                }
+            }
+            const double piv = row[D];
+            if (!(piv != 0.0) || !isfinite(piv)) *flag = 1;
+        }
+        __syncthreads();
+    }
+    // pack level-major: factor s of the p-th cell of level l at lptr[l]*S + s*n_l + p
+    T* out = fac + (long)k * b.next * S;
+    for (int lev = 0; lev < nlev; ++lev) {
+        const int p0 = lptr[lev], nl = lptr[lev + 1] - p0;
+        for (int p = threadIdx.x; p < nl; p += blockDim.x) {
+            const int pk = lpts[p0 + p];
+            const int x = pk & 255, y = (pk >> 8) & 255, z = pk >> 16;
+            const long i = ((long)z * b.ey + y) * b.ex + x;
+            for (int s = 0; s < S; ++s) {
+                const double v = W[i * S + s];
+                out[(long)p0 * S + (long)s * nl + p] = (T)(s == D ? 1.0 / v : v);
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, double* __restrict__ z,
+                                                  const T* __restrict__ fac, const int* __restrict__ lptr,
+                                                  const int* __restrict__ lpts, Box b, StencilTable st,
+                                                  int nlev) {
+    extern __shared__ unsigned char smem_raw[];
+    T* yv = reinterpret_cast<T*>(smem_raw);
+    const int S = st.S, D = st.diag;
+    const int k = blockIdx.x;
+    int ox, oy, oz;
+    box_origin(b, k, &ox, &oy, &oz);
+    for (int i = threadIdx.x; i < b.next; i += blockDim.x) {
+        const int x = i % b.ex, y = (i / b.ex) % b.ey, zz = i / (b.ex * b.ey);
+        yv[i] = (T)r[gidx(b, ox, oy, oz, x, y, zz)];
+    }
+    __syncthreads();
+    const T* F = fac + (long)k * b.next * S;
+    for (int lev = 0; lev < nlev; ++lev) {
+        const int p0 = lptr[lev], nl = lptr[lev + 1] - p0;
+        const T* base = F + (long)p0 * S;
+        for (int p = threadIdx.x; p < nl; p += blockDim.x) {
+            const int pk = lpts[p0 + p];
+            const int x = pk & 255, y = (pk >> 8) & 255, zc = pk >> 16;
+            const int i = (zc * b.ey + y) * b.ex + x;
+            T acc = yv[i];
+            for (int s = 0; s < D; ++s) {
+                const int xx = x + st.dx[s], yy = y + st.dy[s], zz = zc + st.dz[s];
+                const int j = inbox(b, xx, yy, zz) ? (zz * b.ey + yy) * b.ex + xx : i;
+                acc -= base[s * nl + p] * yv[j];
+            }
+            yv[i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int lev = nlev - 1; lev >= 0; --lev) {
+        const int p0 = lptr[lev], nl = lptr[lev + 1] - p0;
+        const T* base = F + (long)p0 * S;
+        for (int p = threadIdx.x; p < nl; p += blockDim.x) {
+            const int pk = lpts[p0 + p];
+            const int x = pk & 255, y = (pk >> 8) & 255, zc = pk >> 16;
+            const int i = (zc * b.ey + y) * b.ex + x;
+            T acc = yv[i];
+            for (int s = D + 1; s < S; ++s) {
+                const int xx = x + st.dx[s], yy = y + st.dy[s], zz = zc + st.dz[s];
+                const int j = inbox(b, xx, yy, zz) ? (zz * b.ey + yy) * b.ex + xx : i;
+                acc -= base[s * nl + p] * yv[j];
+            }
+            yv[i] = acc * base[D * nl + p];
+        }
+        __syncthreads();
+    }
+    // restricted extension: write only the owned cells
+    const int owx = b.ownx, owy = b.owny, owz = b.nz > 1 ? b.ownz : 1;
+    const int zoff = b.nz > 1 ? b.ov : 0;
+    for (int e = threadIdx.x; e < owx * owy * owz; e += blockDim.x) {
+        const int x = e % owx + b.ov, y = (e / owx) % owy + b.ov, zz = e / (owx * owy) + zoff;
+        z[gidx(b, ox, oy, oz, x, y, zz)] = (double)yv[(zz * b.ey + y) * b.ex + x];
+    }
+}
+
+Box make_box(const pfc_ctx* c) {
+    Box b;
+    b.ex = c->dec.ext[0];
+    b.ey = c->dec.ext[1];
+    b.ez = c->g.dim == 3 ? c->dec.ext[2] : 1;
+    b.next = c->dec.next;
+    b.subx = c->dec.sub[0];
+    b.suby = c->dec.sub[1];
+    b.ownx = c->dec.own[0];
+    b.owny = c->dec.own[1];
+    b.ownz = c->dec.own[2];
+    b.ov = c->dec.ov;
+    b.nx = c->g.nx;
+    b.ny = c->g.ny;
+    b.nz = c->g.nz;
+    return b;
+}
+
+}  // namespace
+
+// Host-side level schedule and offset-pair table for the box shape of the context.
+void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<int>* lptr,
+                        std::vector<int>* lpts, std::vector<int8_t>* pair) {
+    const int ex = c->dec.ext[0], ey = c->dec.ext[1], ez = c->g.dim == 3 ? c->dec.ext[2] : 1;
+    const int maxlev = (ex - 1) + 3 * (ey - 1) + 7 * (ez - 1) + 1;
+    std::vector<std::vector<int>> by(maxlev);
+    for (int z = 0; z < ez; ++z)
+        for (int y = 0; y < ey; ++y)
+            for (int x = 0; x < ex; ++x) by[x + 3 * y + 7 * z].push_back(x | (y << 8) | (z << 16));
+    lptr->assign(1, 0);
+    lpts->clear();
+    for (auto& v : by) {
+        for (int p : v) lpts->push_back(p);
+        lptr->push_back((int)lpts->size());
+    }
+    const int S = st.S;
+    pair->assign(S * S, -1);
+    std::map<std::tuple<int, int, int>, int> idx;
+    for (int s = 0; s < S; ++s) idx[{st.dx[s], st.dy[s], st.dz[s]}] = s;
+    for (int s = 0; s < S; ++s)
+        for (int t = 0; t < S; ++t) {
+            auto it = idx.find({st.dx[t] - st.dx[s], st.dy[t] - st.dy[s], st.dz[t] - st.dz[s]});
+            if (it != idx.end()) (*pair)[s * S + t] = (int8_t)it->second;
+        }
+}
+
+hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& st) {
+    const Box b = make_box(c);
+    if (c->opts.precond_fp32)
+        hipLaunchKernelGGL(k_ilu_factor<float>, dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c, c->d_level_ptr,
+                           c->d_level_pts, c->d_pair, c->d_work, (float*)c->d_fac, c->d_flag, b, st, c->nlev);
+    else
+        hipLaunchKernelGGL(k_ilu_factor<double>, dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c, c->d_level_ptr,
+                           c->d_level_pts, c->d_pair, c->d_work, (double*)c->d_fac, c->d_flag, b, st, c->nlev);
+    return hipGetLastError();
+}
+
+hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z) {
+    const Box b = make_box(c);
+    const StencilTable& st = c->st;
+    if (c->opts.precond_fp32) {
+        const size_t sh = sizeof(float) * b.next;
+        hipLaunchKernelGGL(k_ilu_apply<float>, dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
+                           (const float*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev);
+    } else {
+        const size_t sh = sizeof(double) * b.next;
+        hipLaunchKernelGGL(k_ilu_apply<double>, dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
+                           (const double*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev);
+    }
+    return hipGetLastError();
+}
+
+hipError_t set_ilu_lds_limits() {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ilu_apply<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_ilu_apply<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024);
+}
+
+}  // namespace pfc

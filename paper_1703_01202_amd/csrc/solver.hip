@@ -1,0 +1,675 @@
+// Host driver of the Newton-Krylov-Schwarz solve (Sec. 4) and the time loop with
+// adaptive steps (Sec. 3, Eq. (16)), behind the C ABI of include/pfc.h.
+//
+// Device work is enqueued on the context stream; the host reads back one small
+// vector per Arnoldi step (Hessenberg column and norm) and one norm per Newton or
+// line-search evaluation, and keeps the Hessenberg matrix and Givens rotations.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "pfc_internal.h"
+
+namespace pfc {
+int residual_partial_count(const pfc_ctx* c);
+int energy_partial_count(const pfc_ctx* c);
+hipError_t launch_reduce_rows_n(hipStream_t s, const double* partials, int rows, int count, double* out,
+                                double scale);
+void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<int>* lptr,
+                        std::vector<int>* lpts, std::vector<int8_t>* pair);
+hipError_t set_ilu_lds_limits();
+hipError_t set_lu_lds_limits();
+size_t lu_factor_lds_bytes(int W);
+}  // namespace pfc
+
+using namespace pfc;
+
+namespace {
+
+constexpr int kScal = 256;      // device scalar slots
+// slots in d_scal
+constexpr int SC_NORM = 0;      // norm^2 / generic reduction result
+constexpr int SC_MEAN = 1;      // mean for projections
+constexpr int SC_H = 8;         // first Gram-Schmidt coefficients (64)
+constexpr int SC_H2 = 80;       // second pass coefficients (64)
+constexpr int SC_Y = 160;       // update coefficients (64)
+constexpr int SC_E = 240;       // energy, mass
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            c->err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+            return PFC_EHIP;                                                             \
+        }                                                                                \
+    } while (0)
+
+#define CHK(expr)                          \
+    do {                                   \
+        pfc_status s_ = (expr);            \
+        if (s_ != PFC_OK) return s_;       \
+    } while (0)
+
+pfc_status fail(pfc_ctx* c, pfc_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+// ---- per-kernel timing ----
+void timer_begin(pfc_ctx* c, int kind, int* slot) {
+    *slot = -1;
+    if (!c->opts.timing) return;
+    auto& T = c->timer;
+    if (T.used + 2 > (int)T.pool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            T.pool.push_back(e);
+        }
+    }
+    *slot = T.used;
+    T.used += 2;
+    hipEventRecord(T.pool[*slot], c->stream);
+    T.pending.push_back({*slot, kind});
+}
+
+void timer_end(pfc_ctx* c, int slot) {
+    if (slot < 0) return;
+    hipEventRecord(c->timer.pool[slot + 1], c->stream);
+}
+
+void timer_flush(pfc_ctx* c) {   // call after a stream synchronisation
+    auto& T = c->timer;
+    for (auto& pr : T.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, T.pool[pr.first], T.pool[pr.first + 1]) == hipSuccess) {
+            T.total_ms[pr.second] += ms;
+            T.count[pr.second] += 1;
+        }
+    }
+    T.pending.clear();
+    T.used = 0;
+}
+
+pfc_status sync(pfc_ctx* c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    timer_flush(c);
+    return PFC_OK;
+}
+
+// Euclidean norm of a device vector (synchronises).
+pfc_status norm2(pfc_ctx* c, const double* x, double* out) {
+    HIPCHK(launch_dot_partials(c->stream, x, x, c->g.N, c->d_part));
+    HIPCHK(launch_reduce_rows(c->stream, c->d_part, 1, c->d_scal + SC_NORM, 1.0));
+    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + SC_NORM, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    *out = std::sqrt(c->h_pin[0]);
+    if (!std::isfinite(*out)) return fail(c, PFC_ENAN, "non-finite norm");
+    return PFC_OK;
+}
+
+// mean of x into d_scal[SC_MEAN] (device only)
+pfc_status mean_to_device(pfc_ctx* c, const double* x) {
+    HIPCHK(launch_sum_partials(c->stream, x, c->g.N, c->d_part));
+    HIPCHK(launch_reduce_rows(c->stream, c->d_part, 1, c->d_scal + SC_MEAN, 1.0 / (double)c->g.N));
+    return PFC_OK;
+}
+
+pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* src,
+                         double* F, double* nrm) {
+    int ts;
+    timer_begin(c, 1, &ts);
+    HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_part : nullptr));
+    timer_end(c, ts);
+    if (!nrm) return PFC_OK;
+    HIPCHK(launch_reduce_rows_n(c->stream, c->d_part, 1, residual_partial_count(c), c->d_scal + SC_NORM, 1.0));
+    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + SC_NORM, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    *nrm = std::sqrt(c->h_pin[0]);
+    if (!std::isfinite(*nrm)) return fail(c, PFC_ENAN, "non-finite residual norm");
+    return PFC_OK;
+}
+
+pfc_status jv_impl(pfc_ctx* c, const double* v, double dt, const double* vshift, double* out) {
+    int ts;
+    timer_begin(c, 2, &ts);
+    HIPCHK(launch_jv(c, v, c->d_c, dt, vshift, out));
+    timer_end(c, ts);
+    return PFC_OK;
+}
+
+pfc_status setup_impl(pfc_ctx* c, const double* Phi, const double* phi, double dt) {
+    HIPCHK(launch_coef(c, Phi, phi, c->d_c));
+    StencilTable st;
+    build_stencil_table(c->g, c->model.gamma, dt, &st);
+    c->st = st;
+    HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    int ts;
+    timer_begin(c, 3, &ts);
+    if (c->opts.sub_solver == PFC_SUB_LU)
+        HIPCHK(launch_lu_factor(c, st));
+    else
+        HIPCHK(launch_ilu_factor(c, st));
+    timer_end(c, ts);
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    std::memcpy(&flag, c->h_pin, sizeof(int));
+    if (flag) return fail(c, PFC_EPIVOT, "zero or non-finite pivot in a subdomain factorisation");
+    return PFC_OK;
+}
+
+pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
+    int ts;
+    timer_begin(c, 0, &ts);
+    if (c->opts.sub_solver == PFC_SUB_LU)
+        HIPCHK(launch_lu_apply(c, r, z));
+    else
+        HIPCHK(launch_ilu_apply(c, r, z));
+    timer_end(c, ts);
+    if (c->opts.mass_project) {
+        CHK(mean_to_device(c, z));
+        HIPCHK(launch_shift(c->stream, z, c->d_scal + SC_MEAN, -1.0, c->g.N));
+    }
+    return PFC_OK;
+}
+
+// Right-preconditioned flexible GMRES(m) from x = 0 on J x = b (Sec. 4, Eq. (21)).
+// Classical Gram-Schmidt with one re-orthogonalisation pass; Givens rotations on the host.
+pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol, double atol, int* its,
+                  double* res_out) {
+    const long N = c->g.N;
+    const int m = c->opts.gmres_restart;
+    const int maxit = c->opts.gmres_maxit;
+    double bnorm;
+    CHK(norm2(c, b, &bnorm));
+    const double target = std::max(rtol * bnorm, atol);
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
+    *its = 0;
+    *res_out = bnorm;
+    if (bnorm <= target) return PFC_OK;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    double* V = c->d_V;
+    double* Z = c->d_Z;
+    double beta = bnorm;
+    bool first = true;
+    int total = 0;
+    while (true) {
+        // r = b - J x  (x = 0 on the first cycle)
+        if (first) {
+            HIPCHK(launch_scale(c->stream, b, 1.0 / beta, V, N));
+        } else {
+            CHK(jv_impl(c, x, dt, nullptr, c->d_r));
+            HIPCHK(launch_axpby(c->stream, 1.0, b, -1.0, c->d_r, c->d_r, N));
+            CHK(norm2(c, c->d_r, &beta));
+            if (beta <= target) {
+                *res_out = beta;
+                break;
+            }
+            HIPCHK(launch_scale(c->stream, c->d_r, 1.0 / beta, V, N));
+        }
+        first = false;
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jdone = 0;
+        bool conv = false;
+        for (int j = 0; j < m; ++j) {
+            double* zj = Z + (long)j * N;
+            double* w = V + (long)(j + 1) * N;
+            CHK(apply_impl(c, V + (long)j * N, zj));
+            CHK(jv_impl(c, zj, dt, nullptr, w));
+            // CGS2: h = V^T w ; w -= V h ; h2 = V^T w ; w -= V h2 (norm fused)
+            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, c->d_part));
+            HIPCHK(launch_reduce_rows(c->stream, c->d_part, j + 1, c->d_scal + SC_H, 1.0));
+            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, c->d_scal + SC_H, -1.0, w, N, nullptr));
+            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, c->d_part));
+            HIPCHK(launch_reduce_rows(c->stream, c->d_part, j + 1, c->d_scal + SC_H2, 1.0));
+            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, c->d_scal + SC_H2, -1.0, w, N, c->d_part));
+            HIPCHK(launch_reduce_rows(c->stream, c->d_part, 1, c->d_scal + SC_NORM, 1.0));
+            HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, c->stream));
+            CHK(sync(c));
+            const double hn = std::sqrt(c->h_pin[SC_NORM]);
+            if (!std::isfinite(hn)) return fail(c, PFC_ENAN, "non-finite Arnoldi norm");
+            for (int i = 0; i <= j; ++i) H[i * m + j] = c->h_pin[SC_H + i] + c->h_pin[SC_H2 + i];
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0.0) HIPCHK(launch_scale(c->stream, w, 1.0 / hn, w, N));
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
+            sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            jdone = j + 1;
+            *res_out = std::fabs(g[j + 1]);
+            if (*res_out <= target || hn == 0.0) {
+                conv = true;
+                break;
+            }
+            if (total >= maxit) break;
+        }
+        // y = R^{-1} g ; x += Z y
+        for (int i = jdone - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < jdone; ++k) s -= H[i * m + k] * y[k];
+            y[i] = s / H[i * m + i];
+        }
+        HIPCHK(hipMemcpyAsync(c->d_scal + SC_Y, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(launch_maxpy(c->stream, Z, N, jdone, c->d_scal + SC_Y, 1.0, x, N, nullptr));
+        CHK(sync(c));   // y lives in host memory until the copy has run
+        if (conv || total >= maxit) break;
+    }
+    *its = total;
+    if (*res_out > target) return fail(c, PFC_EKRYLOV, "GMRES did not reach its tolerance");
+    return PFC_OK;
+}
+
+// Rounding floor of ||F||: eps times a bound of the operator norm of F applied to Phi.
+// With kappa = sum_a 4/h_a^2 the spectral radius of -Delta_d, each term of Eq. (12) is
+// bounded by (1/dt + (1-gamma)/2 kappa + kappa^2 + kappa^3/2 + 3 kappa) ||Phi||.
+double residual_floor(const pfc_ctx* c, double dt, double xnorm) {
+    const double k = 4.0 * (c->g.ihx2 + c->g.ihy2 + c->g.ihz2);
+    const double op = 1.0 / dt + 0.5 * std::fabs(1.0 - c->model.gamma) * k + k * k + 0.5 * k * k * k + 3.0 * k;
+    return 2.220446049250313e-16 * op * xnorm;
+}
+
+pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats* st) {
+    const long N = c->g.N;
+    double fn, xnorm;
+    CHK(residual_impl(c, c->d_X, phi, dt, nullptr, c->d_F, &fn));
+    CHK(norm2(c, c->d_X, &xnorm));
+    const double target = std::max({c->opts.newton_rtol * fn, c->opts.newton_atol, residual_floor(c, dt, xnorm)});
+    st->res0 = fn;
+    st->newton_its = 0;
+    st->gmres_its = 0;
+    st->ls_cuts = 0;
+    bool factored = false;
+    for (int it = 0; it < c->opts.newton_maxit && fn > target; ++it) {
+        if (!factored) {
+            CHK(setup_impl(c, c->d_X, phi, dt));    // factor once per solve, reuse afterwards
+            factored = true;
+        } else {
+            HIPCHK(launch_coef(c, c->d_X, phi, c->d_c));
+        }
+        // J S = -F
+        HIPCHK(launch_scale(c->stream, c->d_F, -1.0, c->d_T, N));
+        int its = 0;
+        double lres = 0;
+        pfc_status s = fgmres(c, c->d_T, c->d_S, dt, c->opts.lin_rtol, c->opts.lin_atol, &its, &lres);
+        st->gmres_its += its;
+        if (s != PFC_OK && s != PFC_EKRYLOV) return s;
+        // backtracking line search on ||F||
+        double lam = 1.0, ftn = 0.0;
+        bool ok = false;
+        while (true) {
+            HIPCHK(launch_axpby(c->stream, 1.0, c->d_X, lam, c->d_S, c->d_T, N));
+            CHK(residual_impl(c, c->d_T, phi, dt, nullptr, c->d_r, &ftn));
+            if (ftn <= (1.0 - 1e-4 * lam) * fn) {
+                ok = true;
+                break;
+            }
+            if (lam <= 1.0 / 1024.0) break;
+            lam *= 0.5;
+            st->ls_cuts++;
+        }
+        st->newton_its++;
+        if (!ok) return fail(c, PFC_ENOTCONV, "line search failed");
+        std::swap(c->d_X, c->d_T);
+        std::swap(c->d_F, c->d_r);
+        fn = ftn;
+    }
+    st->res_final = fn;
+    if (fn > target) return fail(c, PFC_ENOTCONV, "Newton did not reach its tolerance");
+    return PFC_OK;
+}
+
+pfc_status energy_impl(pfc_ctx* c, const double* phi, double* e, double* m) {
+    HIPCHK(launch_energy(c, phi, c->d_part));
+    const int np = energy_partial_count(c);
+    HIPCHK(launch_reduce_rows_n(c->stream, c->d_part, 2, np, c->d_scal + SC_E, c->g.cell_volume));
+    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + SC_E, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    *e = c->h_pin[0];
+    *m = c->h_pin[1];
+    if (!std::isfinite(*e)) return fail(c, PFC_ENAN, "non-finite energy");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
+    if (hipMalloc((void**)p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
+        *p = nullptr;
+        return fail(c, PFC_ENOMEM, "device allocation failed");
+    }
+    return PFC_OK;
+}
+
+void free_all(pfc_ctx* c) {
+    void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, c->d_fac, c->d_flag, c->d_c,
+                    c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
+                    c->d_tmp3, c->d_part, c->d_scal};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    if (c->h_pin) hipHostFree(c->h_pin);
+    for (auto e : c->timer.pool) hipEventDestroy(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+void pfc_default_opts(pfc_opts* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->newton_rtol = 1e-8;
+    o->newton_atol = 1e-10;
+    o->lin_rtol = 1e-3;
+    o->lin_atol = 1e-11;
+    o->newton_maxit = 50;
+    o->gmres_restart = 30;
+    o->gmres_maxit = 300;
+    o->sub[0] = o->sub[1] = o->sub[2] = 2;
+    o->overlap = 2;
+    o->ras_kind = PFC_RAS_LEFT;
+    o->sub_solver = PFC_SUB_ILU0;
+    o->precond_fp32 = 0;
+    o->mass_project = 1;
+    o->guess = PFC_GUESS_PREVIOUS;
+    o->dt_min = o->dt_max = 0.1;
+    o->eta = 0.0;
+    o->max_retries = 4;
+    o->timing = 0;
+}
+
+pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* op, void* stream,
+                      pfc_ctx** out) {
+    if (!gr || !md || !op || !out) return PFC_EINVAL;
+    *out = nullptr;
+    pfc_ctx* c = new pfc_ctx();
+    c->grid = *gr;
+    c->model = *md;
+    c->opts = *op;
+    c->stream = (hipStream_t)stream;
+    auto bad = [&](const std::string& m) {
+        c->err = m;
+        return PFC_EINVAL;
+    };
+    pfc_status s = PFC_OK;
+    const int dim = gr->dim;
+    if (dim != 2 && dim != 3) s = bad("dim must be 2 or 3");
+    if (s == PFC_OK && md->mobility != 0) s = bad("only mobility M = 1 is built");
+    for (int a = 0; s == PFC_OK && a < dim; ++a) {
+        if (gr->n[a] < 8) s = bad("grid extent below 8");
+        else if (!(gr->L[a] > 0)) s = bad("domain length must be positive");
+        else if (op->sub[a] < 2 || gr->n[a] % op->sub[a] != 0) s = bad("sub[a] must be >= 2 and divide n[a]");
+        else {
+            const int e = gr->n[a] / op->sub[a] + 2 * op->overlap;
+            if (e > gr->n[a] - 3 || e > 255) s = bad("extended subdomain too wide");
+        }
+    }
+    if (s == PFC_OK && op->overlap < 0) s = bad("negative overlap");
+    if (s == PFC_OK && (op->gmres_restart < 1 || op->gmres_restart > 60)) s = bad("gmres_restart must be 1..60");
+    if (s == PFC_OK && (op->gmres_maxit < 1 || op->newton_maxit < 1)) s = bad("iteration limits must be >= 1");
+    if (s == PFC_OK && op->ras_kind != PFC_RAS_LEFT) s = bad("only left-RAS is built");
+    if (s == PFC_OK && op->sub_solver != PFC_SUB_ILU0 && op->sub_solver != PFC_SUB_LU) s = bad("bad sub_solver");
+    if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && dim != 2) {
+        c->err = "exact subdomain LU is built for 2-D only";
+        s = PFC_EUNSUP;
+    }
+    if (s == PFC_OK && !(op->dt_min > 0 && op->dt_max >= op->dt_min)) s = bad("need 0 < dt_min <= dt_max");
+    if (s == PFC_OK && op->guess == PFC_GUESS_LEARNED) {
+        c->err = "learned guess needs pfc_cnn_* (not in this build)";
+        s = PFC_EUNSUP;
+    }
+    if (s != PFC_OK) {
+        pfc_status r = s;
+        std::string msg = c->err;
+        delete c;
+        std::fprintf(stderr, "pfc_create: %s\n", msg.c_str());
+        return r;
+    }
+    // geometry
+    Geom& g = c->g;
+    g.dim = dim;
+    g.nx = gr->n[0];
+    g.ny = gr->n[1];
+    g.nz = dim == 3 ? gr->n[2] : 1;
+    g.N = (long)g.nx * g.ny * g.nz;
+    const double hx = gr->L[0] / g.nx, hy = gr->L[1] / g.ny, hz = dim == 3 ? gr->L[2] / g.nz : 1.0;
+    g.ihx2 = 1.0 / (hx * hx);
+    g.ihy2 = 1.0 / (hy * hy);
+    g.ihz2 = dim == 3 ? 1.0 / (hz * hz) : 0.0;
+    g.cell_volume = hx * hy * (dim == 3 ? hz : 1.0);
+    Decomp& d = c->dec;
+    d.ov = op->overlap;
+    d.nsub = 1;
+    d.next = 1;
+    for (int a = 0; a < 3; ++a) {
+        const bool act = a < dim;
+        d.sub[a] = act ? op->sub[a] : 1;
+        d.own[a] = act ? gr->n[a] / op->sub[a] : 1;
+        d.ext[a] = act ? d.own[a] + 2 * d.ov : 1;
+        d.nsub *= d.sub[a];
+        d.next *= d.ext[a];
+    }
+    if (op->sub_solver == PFC_SUB_LU && (d.ext[0] > 128 || 256 / d.ext[0] < 2)) {
+        s = bad("exact LU needs a box x-extent of at most 128");
+    }
+    if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && lu_factor_lds_bytes(d.ext[0]) > 160 * 1024)
+        s = bad("exact LU block too large for LDS");
+    const size_t ilu_lds = (op->precond_fp32 ? 4 : 8) * (size_t)d.next;
+    if (s == PFC_OK && op->sub_solver == PFC_SUB_ILU0 && ilu_lds > 160 * 1024) s = bad("subdomain too large for LDS");
+    if (s != PFC_OK) {
+        std::string msg = c->err;
+        delete c;
+        std::fprintf(stderr, "pfc_create: %s\n", msg.c_str());
+        return s;
+    }
+    build_stencil_table(g, md->gamma, 1.0, &c->st);
+    const long N = g.N;
+    const int m = op->gmres_restart;
+    const size_t esz = op->precond_fp32 ? sizeof(float) : sizeof(double);
+    s = PFC_OK;
+    auto A = [&](pfc_status r) {
+        if (s == PFC_OK) s = r;
+    };
+    A(dalloc(c, &c->d_c, N));
+    A(dalloc(c, &c->d_F, N));
+    A(dalloc(c, &c->d_X, N));
+    A(dalloc(c, &c->d_T, N));
+    A(dalloc(c, &c->d_S, N));
+    A(dalloc(c, &c->d_w, N));
+    A(dalloc(c, &c->d_r, N));
+    A(dalloc(c, &c->d_prev, N));
+    A(dalloc(c, &c->d_V, (size_t)(m + 1) * N));
+    A(dalloc(c, &c->d_Z, (size_t)m * N));
+    if (dim == 3) A(dalloc(c, &c->d_tmp3, 2 * (size_t)N));
+    A(dalloc(c, &c->d_part, (size_t)std::max(64 * kRedBlocks, 2 * residual_partial_count(c)) + 64));
+    A(dalloc(c, &c->d_scal, kScal));
+    A(dalloc(c, &c->d_flag, 1));
+    if (op->sub_solver == PFC_SUB_ILU0) {
+        std::vector<int> lptr, lpts;
+        std::vector<int8_t> pair;
+        build_ilu_schedule(c, c->st, &lptr, &lpts, &pair);
+        c->nlev = (int)lptr.size() - 1;
+        A(dalloc(c, &c->d_level_ptr, lptr.size()));
+        A(dalloc(c, &c->d_level_pts, lpts.size()));
+        A(dalloc(c, &c->d_pair, pair.size()));
+        c->fac_elems = (size_t)d.nsub * d.next * c->st.S;
+        A(dalloc(c, &c->d_work, c->fac_elems));
+        if (s == PFC_OK) {
+            hipMemcpy(c->d_level_ptr, lptr.data(), sizeof(int) * lptr.size(), hipMemcpyHostToDevice);
+            hipMemcpy(c->d_level_pts, lpts.data(), sizeof(int) * lpts.size(), hipMemcpyHostToDevice);
+            hipMemcpy(c->d_pair, pair.data(), pair.size(), hipMemcpyHostToDevice);
+        }
+    } else {
+        c->lu_W = d.ext[0];
+        c->lu_H = d.ext[1];
+        const size_t WW = (size_t)c->lu_W * c->lu_W;
+        c->fac_elems = (size_t)d.nsub * c->lu_H * 8 * WW;
+        A(dalloc(c, &c->d_work, (size_t)d.nsub * 22 * WW));
+    }
+    if (s == PFC_OK) {
+        if (hipMalloc(&c->d_fac, esz * c->fac_elems) != hipSuccess) s = fail(c, PFC_ENOMEM, "factor allocation failed");
+    }
+    if (s == PFC_OK && hipHostMalloc((void**)&c->h_pin, sizeof(double) * kScal) != hipSuccess)
+        s = fail(c, PFC_ENOMEM, "pinned allocation failed");
+    if (s == PFC_OK && (set_ilu_lds_limits() != hipSuccess || set_lu_lds_limits() != hipSuccess))
+        s = fail(c, PFC_EHIP, "cannot raise the LDS limit");
+    if (s == PFC_OK && hipMemset(c->d_scal, 0, sizeof(double) * kScal) != hipSuccess) s = fail(c, PFC_EHIP, "memset");
+    if (s != PFC_OK) {
+        std::fprintf(stderr, "pfc_create: %s\n", c->err.c_str());
+        free_all(c);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return PFC_OK;
+}
+
+void pfc_destroy(pfc_ctx* c) {
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+const char* pfc_last_error(const pfc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+pfc_status pfc_residual(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* src, double* F,
+                        double* norm) {
+    if (!c || !Phi || !phi || !F || !(dt > 0)) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    return residual_impl(c, Phi, phi, dt, src, F, norm);
+}
+
+pfc_status pfc_jv(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* v, double* Jv) {
+    if (!c || !Phi || !phi || !v || !Jv || !(dt > 0)) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    HIPCHK(launch_coef(c, Phi, phi, c->d_c));
+    return jv_impl(c, v, dt, nullptr, Jv);
+}
+
+pfc_status pfc_ras_setup(pfc_ctx* c, const double* Phi, const double* phi, double dt) {
+    if (!c || !Phi || !phi || !(dt > 0)) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    return setup_impl(c, Phi, phi, dt);
+}
+
+pfc_status pfc_ras_apply(pfc_ctx* c, const double* r, double* z) {
+    if (!c || !r || !z) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    return apply_impl(c, r, z);
+}
+
+pfc_status pfc_energy(pfc_ctx* c, const double* phi, double* e, double* m) {
+    if (!c || !phi || !e || !m) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    return energy_impl(c, phi, e, m);
+}
+
+pfc_status pfc_gmres(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* b, double* x,
+                     double rtol, double atol, int* its, double* res) {
+    if (!c || !Phi || !phi || !b || !x || !its || !res || !(dt > 0))
+        return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    HIPCHK(launch_coef(c, Phi, phi, c->d_c));
+    HIPCHK(hipMemcpyAsync(c->d_w, b, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
+    return fgmres(c, c->d_w, x, dt, rtol, atol, its, res);
+}
+
+pfc_status pfc_newton(pfc_ctx* c, const double* phi, double dt, double* Phi, pfc_step_stats* st) {
+    if (!c || !phi || !Phi || !st || !(dt > 0)) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    std::memset(st, 0, sizeof(*st));
+    HIPCHK(hipMemcpyAsync(c->d_X, Phi, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
+    pfc_status s = newton_impl(c, phi, dt, st);
+    HIPCHK(hipMemcpyAsync(Phi, c->d_X, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    st->dt = dt;
+    return s;
+}
+
+pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
+    if (!c || !phi || !st) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    std::memset(st, 0, sizeof(*st));
+    const long N = c->g.N;
+    const pfc_opts& o = c->opts;
+    if (!c->have_energy) {
+        double m0;
+        CHK(energy_impl(c, phi, &c->F_n, &m0));
+        c->have_energy = true;
+    }
+    double dt = o.dt_min;
+    if (c->step > 0 && o.dt_max > o.dt_min) {
+        const double fp = std::fabs(c->F_n - c->F_nm1) / c->dt_nm1;
+        dt = std::max(o.dt_min, o.dt_max / std::sqrt(1.0 + o.eta * fp * fp));
+    }
+    pfc_status s = PFC_OK;
+    for (int attempt = 0;; ++attempt) {
+        // initial guess
+        int used = PFC_GUESS_PREVIOUS;
+        if (o.guess == PFC_GUESS_EXTRAP && c->have_prev) {
+            HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
+            if (o.mass_project) {   // restore the mass of phi^n exactly: X += mean(phi - X)
+                HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
+                CHK(mean_to_device(c, c->d_w));
+                HIPCHK(launch_shift(c->stream, c->d_X, c->d_scal + SC_MEAN, 1.0, N));
+            }
+            used = PFC_GUESS_EXTRAP;
+        } else {
+            HIPCHK(hipMemcpyAsync(c->d_X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+        }
+        pfc_step_stats tmp;
+        std::memset(&tmp, 0, sizeof(tmp));
+        s = newton_impl(c, phi, dt, &tmp);
+        st->newton_its += tmp.newton_its;
+        st->gmres_its += tmp.gmres_its;
+        st->ls_cuts += tmp.ls_cuts;
+        st->res0 = tmp.res0;
+        st->res_final = tmp.res_final;
+        st->guess_used = used;
+        if (s == PFC_OK) break;
+        if ((s != PFC_ENOTCONV && s != PFC_EKRYLOV) || attempt >= o.max_retries || dt <= o.dt_min / 16) return s;
+        st->rejected++;
+        dt = std::max(dt * 0.5, o.dt_min / 16);
+    }
+    // accept: phi^(n-1) <- phi^n, phi^n <- X
+    HIPCHK(hipMemcpyAsync(c->d_prev, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(phi, c->d_X, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+    c->have_prev = true;
+    double e, m;
+    CHK(energy_impl(c, phi, &e, &m));
+    c->F_nm1 = c->F_n;
+    c->F_n = e;
+    c->dt_nm1 = dt;
+    c->t += dt;
+    c->step++;
+    st->dt = dt;
+    st->t = c->t;
+    st->energy = e;
+    st->mass = m;
+    return PFC_OK;
+}
+
+pfc_status pfc_reset(pfc_ctx* c) {
+    if (!c) return PFC_EINVAL;
+    c->step = 0;
+    c->F_n = c->F_nm1 = c->dt_nm1 = c->t = 0.0;
+    c->have_prev = c->have_energy = false;
+    for (int i = 0; i < 4; ++i) {
+        c->timer.count[i] = 0;
+        c->timer.total_ms[i] = 0.0;
+    }
+    return PFC_OK;
+}
+
+pfc_status pfc_kernel_time(pfc_ctx* c, int which, long* count, double* total_ms) {
+    if (!c || which < 0 || which > 3 || !count || !total_ms) return PFC_EINVAL;
+    *count = c->timer.count[which];
+    *total_ms = c->timer.total_ms[which];
+    return PFC_OK;
+}
+
+}  // extern "C"

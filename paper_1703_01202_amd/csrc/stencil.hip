@@ -1,0 +1,367 @@
+// Stencil kernels of the DVD scheme: residual (Sec. 3, Eq. (12)), Jacobian
+// coefficient and exact Jacobian action (Sec. 4, Eq. (19)), discrete energy and
+// mass (Sec. 3, Eqs. (7)-(8)).
+//
+// 2-D: one fused kernel per operator.  A 64x16 output tile is staged in LDS with a
+// three-cell periodic halo; the composite radius-3 operator is applied as three
+// successive five-point Laplacians inside LDS (halo 3 -> 2 -> 1 -> 0), so each
+// field is read from HBM once and the result written once.
+// 3-D: three seven-point passes through global memory (L2-resident neighbours).
+#include "pfc_internal.h"
+
+namespace pfc {
+namespace {
+
+constexpr int TX = 64;
+constexpr int TY = 16;
+constexpr int NT = 256;
+
+struct P {
+    int nx, ny, nz;
+    double ihx2, ihy2, ihz2;
+    double gamma, inv_dt;
+};
+
+__device__ __forceinline__ int wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Deterministic block sum (fixed shuffle tree, then the waves in order); result in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return s;
+}
+
+#define LAP2(A, y, x)                                                     \
+    (((A)[y][(x) + 1] + (A)[y][(x)-1] - 2.0 * (A)[y][x]) * p.ihx2 +       \
+     ((A)[(y) + 1][x] + (A)[(y)-1][x] - 2.0 * (A)[y][x]) * p.ihy2)
+
+// F = (Phi - phi)/dt - Delta_d mu_d - src, plus per-block partial sums of F^2.
+__global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Phi,
+                                                   const double* __restrict__ phi,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ F,
+                                                   double* __restrict__ part, P p) {
+    __shared__ double su[TY + 6][TX + 6];     // u = (Phi + phi)/2, halo 3
+    __shared__ double sl[TY + 4][TX + 4];     // Delta_d u, halo 2
+    __shared__ double sm[TY + 2][TX + 2];     // cubic term q, then mu_d, halo 1
+    __shared__ double sd[TY][TX];             // Phi - phi
+    __shared__ double red[NT / 64];
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+
+    for (int e = tid; e < (TY + 6) * (TX + 6); e += NT) {
+        const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
+        const long gi = (long)wrap(y0 + ly - 3, p.ny) * p.nx + wrap(x0 + lx - 3, p.nx);
+        const double a = Phi[gi], b = phi[gi];
+        su[ly][lx] = 0.5 * (a + b);
+        const int qy = ly - 2, qx = lx - 2;
+        if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2)
+            sm[qy][qx] = 0.25 * (a * a * a + a * a * b + a * b * b + b * b * b);
+        const int dy = ly - 3, dx = lx - 3;
+        if (dy >= 0 && dy < TY && dx >= 0 && dx < TX) sd[dy][dx] = a - b;
+    }
+    __syncthreads();
+    for (int e = tid; e < (TY + 4) * (TX + 4); e += NT) {
+        const int ly = e / (TX + 4), lx = e - ly * (TX + 4);
+        sl[ly][lx] = LAP2(su, ly + 1, lx + 1);
+    }
+    __syncthreads();
+    for (int e = tid; e < (TY + 2) * (TX + 2); e += NT) {
+        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        const double l = sl[ly + 1][lx + 1];
+        sm[ly][lx] += (1.0 - p.gamma) * su[ly + 2][lx + 2] + 2.0 * l + LAP2(sl, ly + 1, lx + 1);
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = tid; e < TY * TX; e += NT) {
+        const int ly = e / TX, lx = e - ly * TX;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const double lm = LAP2(sm, ly + 1, lx + 1);
+        if (gx < p.nx && gy < p.ny) {
+            const long gi = (long)gy * p.nx + gx;
+            double f = sd[ly][lx] * p.inv_dt - lm;
+            if (src) f -= src[gi];
+            F[gi] = f;
+            acc += f * f;
+        }
+    }
+    if (part) {
+        const double s = block_sum(acc, red);
+        if (tid == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// Jv = v/dt - Delta_d[(1-gamma)/2 v + Delta_d v + 1/2 Delta_d^2 v + c v], v shifted by
+// -(*vshift) when vshift is given (zero-mean projection fused into the load).
+__global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
+                                             const double* __restrict__ cc,
+                                             const double* __restrict__ vshift,
+                                             double* __restrict__ Jv, P p) {
+    __shared__ double sv[TY + 6][TX + 6];
+    __shared__ double sl[TY + 4][TX + 4];
+    __shared__ double sn[TY + 2][TX + 2];     // c, then the inner operator, halo 1
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    const double sh = vshift ? *vshift : 0.0;
+
+    for (int e = tid; e < (TY + 6) * (TX + 6); e += NT) {
+        const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
+        const long gi = (long)wrap(y0 + ly - 3, p.ny) * p.nx + wrap(x0 + lx - 3, p.nx);
+        sv[ly][lx] = v[gi] - sh;
+        const int qy = ly - 2, qx = lx - 2;
+        if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2) sn[qy][qx] = cc[gi];
+    }
+    __syncthreads();
+    for (int e = tid; e < (TY + 4) * (TX + 4); e += NT) {
+        const int ly = e / (TX + 4), lx = e - ly * (TX + 4);
+        sl[ly][lx] = LAP2(sv, ly + 1, lx + 1);
+    }
+    __syncthreads();
+    for (int e = tid; e < (TY + 2) * (TX + 2); e += NT) {
+        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        const double vv = sv[ly + 2][lx + 2];
+        sn[ly][lx] = 0.5 * (1.0 - p.gamma) * vv + sl[ly + 1][lx + 1] +
+                     0.5 * LAP2(sl, ly + 1, lx + 1) + sn[ly][lx] * vv;
+    }
+    __syncthreads();
+    for (int e = tid; e < TY * TX; e += NT) {
+        const int ly = e / TX, lx = e - ly * TX;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const double ln = LAP2(sn, ly + 1, lx + 1);
+        if (gx < p.nx && gy < p.ny) Jv[(long)gy * p.nx + gx] = sv[ly + 3][lx + 3] * p.inv_dt - ln;
+    }
+}
+
+// Partial sums of G_d (Eq. (7)) and of phi per block: part[b] and part[nblk + b].
+__global__ __launch_bounds__(NT) void k_energy2d(const double* __restrict__ phi,
+                                                 double* __restrict__ part, P p) {
+    __shared__ double s[TY + 2][TX + 2];
+    __shared__ double red[NT / 64];
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    for (int e = tid; e < (TY + 2) * (TX + 2); e += NT) {
+        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        s[ly][lx] = phi[(long)wrap(y0 + ly - 1, p.ny) * p.nx + wrap(x0 + lx - 1, p.nx)];
+    }
+    __syncthreads();
+    double eg = 0.0, em = 0.0;
+    for (int e = tid; e < TY * TX; e += NT) {
+        const int ly = e / TX + 1, lx = e % TX + 1;
+        if (x0 + lx - 1 < p.nx && y0 + ly - 1 < p.ny) {
+            const double f = s[ly][lx];
+            const double xp = s[ly][lx + 1] - f, xm = f - s[ly][lx - 1];
+            const double yp = s[ly + 1][lx] - f, ym = f - s[ly - 1][lx];
+            const double lap = (xp - xm) * p.ihx2 + (yp - ym) * p.ihy2;
+            eg += 0.5 * (1.0 - p.gamma) * f * f + 0.25 * f * f * f * f + 0.5 * lap * lap -
+                  0.5 * ((xp * xp + xm * xm) * p.ihx2 + (yp * yp + ym * ym) * p.ihy2);
+            em += f;
+        }
+    }
+    const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+    const double sg = block_sum(eg, red);
+    if (tid == 0) part[b] = sg;
+    const double sm = block_sum(em, red);
+    if (tid == 0) part[nb + b] = sm;
+}
+
+// ---------------------------------------------------------------------------
+// Generic N-d multi-pass kernels (3-D; also valid for 2-D with nz = 1)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double lap7(const double* __restrict__ a, int x, int y, int z, const P& p) {
+    const long sxy = (long)p.nx * p.ny;
+    const long c = z * sxy + (long)y * p.nx + x;
+    const double ac = a[c];
+    const int xp = x + 1 == p.nx ? 0 : x + 1, xm = x == 0 ? p.nx - 1 : x - 1;
+    const int yp = y + 1 == p.ny ? 0 : y + 1, ym = y == 0 ? p.ny - 1 : y - 1;
+    const long row = z * sxy + (long)y * p.nx;
+    double r = (a[row + xp] + a[row + xm] - 2.0 * ac) * p.ihx2 +
+               (a[z * sxy + (long)yp * p.nx + x] + a[z * sxy + (long)ym * p.nx + x] - 2.0 * ac) * p.ihy2;
+    if (p.nz > 1) {
+        const int zp = z + 1 == p.nz ? 0 : z + 1, zm = z == 0 ? p.nz - 1 : z - 1;
+        r += (a[zp * sxy + (long)y * p.nx + x] + a[zm * sxy + (long)y * p.nx + x] - 2.0 * ac) * p.ihz2;
+    }
+    return r;
+}
+
+#define MP_INDEX                                                         \
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;                 \
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;                 \
+    const int z = blockIdx.z;                                            \
+    if (x >= p.nx || y >= p.ny) return;                                  \
+    const long i = ((long)z * p.ny + y) * p.nx + x;
+
+// out = (a + b)/2 (mode 0) or a - shift (mode 1)
+__global__ void k_mp_combine(const double* __restrict__ a, const double* __restrict__ b,
+                             const double* __restrict__ shift, int mode, double* __restrict__ out,
+                             long n) {
+    const double sh = shift ? *shift : 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = mode == 0 ? 0.5 * (a[i] + b[i]) : a[i] - sh;
+}
+
+__global__ void k_mp_lap(const double* __restrict__ u, double* __restrict__ out, P p) {
+    MP_INDEX
+    out[i] = lap7(u, x, y, z, p);
+}
+
+// mu = (1-gamma) u + 2 Lu + Delta Lu + q (residual) or inner Jacobian operator (jv)
+__global__ void k_mp_inner(const double* __restrict__ Phi, const double* __restrict__ phi,
+                           const double* __restrict__ u, const double* __restrict__ Lu,
+                           const double* __restrict__ cc, int jv, double* __restrict__ out, P p) {
+    MP_INDEX
+    const double l = Lu[i];
+    const double ll = lap7(Lu, x, y, z, p);
+    if (!jv) {
+        const double a = Phi[i], b = phi[i];
+        out[i] = (1.0 - p.gamma) * u[i] + 2.0 * l + ll + 0.25 * (a * a * a + a * a * b + a * b * b + b * b * b);
+    } else {
+        const double vv = u[i];
+        out[i] = 0.5 * (1.0 - p.gamma) * vv + l + 0.5 * ll + cc[i] * vv;
+    }
+}
+
+// residual (jv = 0): F = (Phi - phi)/dt - Delta mu - src ; jv: out = v/dt - Delta inner
+__global__ void k_mp_final(const double* __restrict__ a, const double* __restrict__ b,
+                           const double* __restrict__ m, const double* __restrict__ src, int jv,
+                           double* __restrict__ out, P p) {
+    MP_INDEX
+    const double lm = lap7(m, x, y, z, p);
+    double f = (jv ? a[i] : a[i] - b[i]) * p.inv_dt - lm;
+    if (src) f -= src[i];
+    out[i] = f;
+}
+
+__global__ __launch_bounds__(NT) void k_mp_energy(const double* __restrict__ phi,
+                                                  double* __restrict__ part, P p) {
+    __shared__ double red[NT / 64];
+    const long n = (long)p.nx * p.ny * p.nz;
+    const long sxy = (long)p.nx * p.ny;
+    double eg = 0.0, em = 0.0;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
+        const int x = (int)(i % p.nx), y = (int)((i / p.nx) % p.ny), z = (int)(i / sxy);
+        const double f = phi[i];
+        const int xp = x + 1 == p.nx ? 0 : x + 1, xm = x == 0 ? p.nx - 1 : x - 1;
+        const int yp = y + 1 == p.ny ? 0 : y + 1, ym = y == 0 ? p.ny - 1 : y - 1;
+        const double dxp = phi[z * sxy + (long)y * p.nx + xp] - f, dxm = f - phi[z * sxy + (long)y * p.nx + xm];
+        const double dyp = phi[z * sxy + (long)yp * p.nx + x] - f, dym = f - phi[z * sxy + (long)ym * p.nx + x];
+        double lap = (dxp - dxm) * p.ihx2 + (dyp - dym) * p.ihy2;
+        double grad = (dxp * dxp + dxm * dxm) * p.ihx2 + (dyp * dyp + dym * dym) * p.ihy2;
+        if (p.nz > 1) {
+            const int zp = z + 1 == p.nz ? 0 : z + 1, zm = z == 0 ? p.nz - 1 : z - 1;
+            const double dzp = phi[zp * sxy + (long)y * p.nx + x] - f, dzm = f - phi[zm * sxy + (long)y * p.nx + x];
+            lap += (dzp - dzm) * p.ihz2;
+            grad += (dzp * dzp + dzm * dzm) * p.ihz2;
+        }
+        eg += 0.5 * (1.0 - p.gamma) * f * f + 0.25 * f * f * f * f + 0.5 * lap * lap - 0.5 * grad;
+        em += f;
+    }
+    const double sg = block_sum(eg, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sg;
+    const double sm = block_sum(em, red);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = sm;
+}
+
+__global__ __launch_bounds__(NT) void k_sumsq(const double* __restrict__ x, long n,
+                                              double* __restrict__ part) {
+    __shared__ double red[NT / 64];
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) acc += x[i] * x[i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_coef(const double* __restrict__ Phi, const double* __restrict__ phi,
+                       double* __restrict__ c, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double a = Phi[i], b = phi[i];
+        c[i] = 0.25 * (3.0 * a * a + 2.0 * a * b + b * b);
+    }
+}
+
+P make_params(const pfc_ctx* c, double dt) {
+    P p;
+    p.nx = c->g.nx;
+    p.ny = c->g.ny;
+    p.nz = c->g.nz;
+    p.ihx2 = c->g.ihx2;
+    p.ihy2 = c->g.ihy2;
+    p.ihz2 = c->g.ihz2;
+    p.gamma = c->model.gamma;
+    p.inv_dt = dt > 0 ? 1.0 / dt : 0.0;
+    return p;
+}
+
+dim3 tiles2d(const pfc_ctx* c) { return dim3((c->g.nx + TX - 1) / TX, (c->g.ny + TY - 1) / TY); }
+dim3 mp_grid(const pfc_ctx* c) { return dim3((c->g.nx + 63) / 64, (c->g.ny + 3) / 4, c->g.nz); }
+
+}  // namespace
+
+int residual_partial_count(const pfc_ctx* c) {
+    if (c->g.dim == 2) {
+        dim3 g = tiles2d(c);
+        return g.x * g.y;
+    }
+    return kRedBlocks;
+}
+
+int energy_partial_count(const pfc_ctx* c) { return residual_partial_count(c); }
+
+hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
+                           const double* src, double* F, double* partials) {
+    const P p = make_params(c, dt);
+    if (c->g.dim == 2) {
+        hipLaunchKernelGGL(k_residual2d, tiles2d(c), dim3(NT), 0, c->stream, Phi, phi, src, F, partials, p);
+        return hipGetLastError();
+    }
+    double* u = c->d_tmp3;
+    double* Lu = c->d_tmp3 + c->g.N;
+    hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, Phi, phi, nullptr, 0, u, c->g.N);
+    hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, u, Lu, p);
+    // mu overwrites u only after every Lu neighbour is read: use F as the mu buffer
+    hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, Lu, nullptr, 0, F, p);
+    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, F, src, 0, u, p);
+    hipMemcpyAsync(F, u, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream);
+    if (partials) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, F, c->g.N, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, double* cbuf) {
+    hipLaunchKernelGGL(k_coef, dim3(2048), dim3(256), 0, c->stream, Phi, phi, cbuf, c->g.N);
+    return hipGetLastError();
+}
+
+hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt,
+                     const double* vshift, double* Jv) {
+    const P p = make_params(c, dt);
+    if (c->g.dim == 2) {
+        hipLaunchKernelGGL(k_jv2d, tiles2d(c), dim3(NT), 0, c->stream, v, cbuf, vshift, Jv, p);
+        return hipGetLastError();
+    }
+    double* u = c->d_tmp3;
+    double* Lu = c->d_tmp3 + c->g.N;
+    hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, v, nullptr, vshift, 1, u, c->g.N);
+    hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, u, Lu, p);
+    hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, nullptr, nullptr, u, Lu, cbuf, 1, Jv, p);
+    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, u, nullptr, Jv, nullptr, 1, Lu, p);
+    hipMemcpyAsync(Jv, Lu, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* partials) {
+    const P p = make_params(c, 0.0);
+    if (c->g.dim == 2) {
+        hipLaunchKernelGGL(k_energy2d, tiles2d(c), dim3(NT), 0, c->stream, phi, partials, p);
+    } else {
+        hipLaunchKernelGGL(k_mp_energy, dim3(kRedBlocks), dim3(NT), 0, c->stream, phi, partials, p);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pfc

@@ -1,0 +1,90 @@
+"""The C-ABI library loads and exports every entry point of include/pfc.h (CPU only).
+
+Also checks host-side argument validation, which returns before any device call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1703_01202_amd", "libpfc.so")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "pfc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfc_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpfc.so is not built: run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_hot_path():
+    names = _declared_functions()
+    for required in ("pfc_residual", "pfc_jv", "pfc_ras_setup", "pfc_ras_apply", "pfc_step",
+                     "pfc_energy", "pfc_gmres", "pfc_newton", "pfc_create", "pfc_destroy"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header():
+    from paper_1703_01202_amd import _lib
+    assert set(_declared_functions()) <= set(_lib.SIGNATURES)
+
+
+def _create(lib, n=(64, 64, 1), sub=(4, 4, 1), overlap=2, dim=2, **kw):
+    from paper_1703_01202_amd import _lib
+    for name, (res, args) in _lib.SIGNATURES.items():
+        getattr(lib, name).restype = res
+        getattr(lib, name).argtypes = args
+    g = _lib.PfcGrid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = n[a]
+        g.L[a] = 10.0
+    m = _lib.PfcModel(gamma=0.25, mobility=kw.pop("mobility", 0))
+    o = _lib.PfcOpts()
+    lib.pfc_default_opts(ctypes.byref(o))
+    for a in range(3):
+        o.sub[a] = sub[a]
+    o.overlap = overlap
+    for k, v in kw.items():
+        setattr(o, k, v)
+    ctx = ctypes.c_void_p()
+    return lib.pfc_create(ctypes.byref(g), ctypes.byref(m), ctypes.byref(o), None, ctypes.byref(ctx))
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(sub=(3, 4, 1)), -1),                  # 3 does not divide 64
+    (dict(sub=(1, 4, 1)), -1),                  # fewer than two boxes
+    (dict(overlap=30), -1),                     # extended box wider than n - 3
+    (dict(n=(4, 64, 1)), -1),                   # grid too small
+    (dict(gmres_restart=0), -1),
+    (dict(gmres_restart=100), -1),
+    (dict(mobility=1), -1),                     # only M = 1 built
+    (dict(dt_min=0.0), -1),
+    (dict(sub_solver=1, dim=3, n=(32, 32, 32), sub=(4, 4, 4)), -8),   # exact LU is 2-D only
+    (dict(ras_kind=1), -1),
+])
+def test_create_rejects_bad_arguments(lib, kw, status):
+    assert _create(lib, **kw) == status
+
+
+def test_default_opts_match_paper_tolerances(lib):
+    from paper_1703_01202_amd import _lib
+    lib.pfc_default_opts.argtypes = [ctypes.POINTER(_lib.PfcOpts)]
+    o = _lib.PfcOpts()
+    lib.pfc_default_opts(ctypes.byref(o))
+    # Sec. 5: eps_r = 1e-8, eps_a = 1e-10, xi_r = 1e-3, xi_a = 1e-11
+    assert (o.newton_rtol, o.newton_atol, o.lin_rtol, o.lin_atol) == (1e-8, 1e-10, 1e-3, 1e-11)
+    assert o.gmres_restart == 30 and o.mass_project == 1

@@ -42,7 +42,7 @@ def apply_bytes(shape, sub, overlap, sub_solver, fp32):
     nsub = sub[0] * sub[1]
     if sub_solver == "lu":
         W, H = ex, ey
-        fac = H * (7 * W * W + W)           # nonzeros of the stored block rows
+        fac = H * 7 * W * W                 # [Lh | S^-1 | -Uh] per block row, all dense
     else:
         fac = 0
         for y in range(ey):

@@ -107,6 +107,14 @@ struct pfc_ctx {
 
 namespace pfc {
 
+// Allow a kernel the whole 160 KB LDS of a gfx950 CU minus its static LDS.
+inline hipError_t set_dynamic_lds_limit(const void* f) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, f);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)a.sharedSizeBytes);
+}
+
 // ---- stencil kernels (stencil.hip) ----
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
                            const double* src, double* F, double* partials);

@@ -303,11 +303,9 @@ hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z) {
 }
 
 hipError_t set_ilu_lds_limits() {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ilu_apply<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = set_dynamic_lds_limit((const void*)k_ilu_apply<double>);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_ilu_apply<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               160 * 1024);
+    return set_dynamic_lds_limit((const void*)k_ilu_apply<float>);
 }
 
 }  // namespace pfc

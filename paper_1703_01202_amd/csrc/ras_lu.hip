@@ -1,24 +1,28 @@
-// Restricted additive Schwarz with exact subdomain solves (Sec. 4: subdomain problems
-// solved "directly" by LU), 2-D.
+// Restricted additive Schwarz with exact subdomain solves (Sec. 4: the subdomain problems
+// may be solved directly by a sparse LU factorisation), 2-D.
 //
 // In the natural order of an ex x ey box the subdomain matrix A_k (Eq. (25)/(26)) is
 // block banded: blocks are box rows of W = ex cells, and block (I, J) is nonzero for
-// |I - J| <= 3 (the stencil reaches three rows).  Gaussian elimination without
-// pivoting keeps that block band, so the exact factors are
-//     L: blocks L(I, I-3..I-1) and unit-lower L(I, I);   U: U(I, I) and U(I, I+1..I+3).
-// The factorisation is a right-looking block LU over a sliding window of 4 x 4 blocks;
-// the diagonal blocks are factored and inverted in LDS.  For the solve each block row
-// stores [L(I, I-3..I-1) | inv L(I,I) | U(I, I+1..I+3) | inv U(I,I)], column-major, so
-//     forward:  y_I = inv L(I,I) (r_I - sum_K L(I,K) y_K)
-//     backward: x_I = inv U(I,I) (y_I - sum_J U(I,J) x_J)
-// are two short dense products per block row, with coalesced factor reads.
-// Elimination without pivoting is exact here because the Jacobian's symmetric part
-// is positive definite for the step sizes used (its Fourier symbol at uniform states
-// is 1/dt + kappa((1-kappa)^2 - gamma + 2c)/2 > 0); a zero pivot is reported.
+// |I - J| <= 3 (the stencil reaches three rows).  Block Gaussian elimination without
+// pivoting keeps that band and gives the exact factorisation A = Lh D Uh with
+//     S_KK   = A_KK after the updates of steps < K      (D = diag(S_KK)),
+//     Lh(I,K) = A(I,K) S_KK^-1,  Uh(K,J) = S_KK^-1 A(K,J),  A(I,J) -= A(I,K) S_KK^-1 A(K,J),
+// for |I - K|, |J - K| <= 3.  S_KK^-1 is formed by Gauss-Jordan elimination in LDS.
+// The solve needs no triangular solve inside a block:
+//     forward:  z_I = r_I - sum_{K=I-3}^{I-1} Lh(I,K) z_K
+//     backward: x_I = S_II^-1 z_I - sum_{J=I+1}^{I+3} Uh(I,J) x_J
+// Each block row stores [Lh(I,I-3..I-1) | S_II^-1 | -Uh(I,I+1..I+3)] (7 W^2 values), each
+// W x W block column-major, so each half sweep is one dense product per block row whose
+// input is a contiguous slice of the box vector.
+// Elimination without pivoting is exact here because the symmetric part of the Jacobian
+// is positive definite for the step sizes used (its Fourier symbol at a uniform state is
+// 1/dt + kappa((1-kappa)^2 - gamma + 2c)/2 > 0); a zero pivot is reported.
 #include "pfc_internal.h"
 
 namespace pfc {
 namespace {
+
+constexpr int kSmallW = 36;        // boxes up to this width factor entirely in LDS
 
 struct LuBox {
     int W, H;                  // block size (box x extent), block rows (box y extent)
@@ -32,197 +36,482 @@ __device__ __forceinline__ int wrapg(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-// window slot of block (I, J)
+// window slot of block (I, J) in the 16-block workspace
 __device__ __forceinline__ double* slot(double* win, int I, int J, int W) {
     return win + (long)(((I & 3) * 4) + (J & 3)) * W * W;
 }
 
-__device__ void assemble_block(double* dst, int I, int J, const LuBox& b, const StencilTable& st,
-                               const double* __restrict__ cc, int ox, int oy) {
+// Stencil coefficients of the Jacobian by offset, (dy+3)*7 + dx+3, staged in LDS once per
+// kernel (kconst and d1; zero outside the stencil).
+struct LdsStencil {
+    double k[49];
+    double d1[49];
+};
+
+__device__ void stage_stencil(LdsStencil* t, const LuBox& b, const StencilTable& st) {
+    for (int o = threadIdx.x; o < 49; o += blockDim.x) {
+        const int s = b.idx7[o];
+        t->k[o] = s >= 0 ? st.kconst[s] : 0.0;
+        t->d1[o] = s >= 0 ? st.d1[s] : 0.0;
+    }
+}
+
+// Block (I, J) of A_k into dst (row-major).  crow holds c along box row J (W values).
+__device__ void assemble_block(double* dst, int I, int J, const LuBox& b, const LdsStencil* t,
+                               const double* crow) {
     const int W = b.W, dy = J - I;
-    const int gy = wrapg(oy + J, b.ny);
     for (int e = threadIdx.x; e < W * W; e += blockDim.x) {
         const int p = e / W, q = e - p * W;
         const int dx = q - p;
         double v = 0.0;
         if (abs(dx) + abs(dy) <= 3) {
-            const int s = b.idx7[(dy + 3) * 7 + dx + 3];
-            v = st.kconst[s] - st.d1[s] * cc[(long)gy * b.nx + wrapg(ox + q, b.nx)];
+            const int o = (dy + 3) * 7 + dx + 3;
+            v = t->k[o] - t->d1[o] * crow[q];
         }
         dst[e] = v;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_lu_factor(const double* __restrict__ cc, double* __restrict__ work,
-                                                   T* __restrict__ fac, int* __restrict__ flag, LuBox b,
-                                                   StencilTable st) {
+// c along box row J into the LDS ring slot J % 8 (W <= 72 values per slot).
+__device__ void load_c_row(double* ring, int J, const LuBox& b, const double* __restrict__ cc, int ox, int oy) {
+    const long row = (long)wrapg(oy + J, b.ny) * b.nx;
+    for (int q = threadIdx.x; q < b.W; q += blockDim.x) ring[(J & 7) * 72 + q] = cc[row + wrapg(ox + q, b.nx)];
+}
+
+// Inverse of the W x W block in G0 by Gauss-Jordan elimination without pivoting, taking
+// the pivots four at a time: for the pivot block K = {k0..k0+3} with P = a(K,K),
+//     a'(K,K) = P^-1,            a'(K,j) = P^-1 a(K,j),
+//     a'(i,K) = -a(i,K) P^-1,    a'(i,j) = a(i,j) - a(i,K) P^-1 a(K,j)      (i, j not in K),
+// which is four scalar Gauss-Jordan steps done at once.  Every thread inverts the 4 x 4
+// pivot block in registers (scalar Gauss-Jordan, same pivots); the matrix is double-
+// buffered through G1 with one barrier per block.  A last block narrower than four is
+// padded with the identity.  Returns the buffer holding the inverse.
+__device__ double* gauss_jordan(double* G0, double* G1, int W, int* flag) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double* a = G0;
+    double* o = G1;
+    for (int k0 = 0; k0 < W; k0 += 4) {
+        const int bs = min(4, W - k0);
+        double P[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                P[r][c] = (r < bs && c < bs) ? a[(k0 + r) * W + k0 + c] : (r == c ? 1.0 : 0.0);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {           // in-register Gauss-Jordan of P
+            const double piv = P[kk][kk];
+            if (tid == 0 && (!(piv != 0.0) || !isfinite(piv))) *flag = 1;
+            const double ip = 1.0 / piv;
+            double rowk[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rowk[c] = (c == kk) ? ip : P[kk][c] * ip;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r == kk) continue;
+                const double f = P[r][kk];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) P[r][c] = (c == kk ? 0.0 : P[r][c]) - f * rowk[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) P[kk][c] = rowk[c];
+        }
+        for (int e = tid; e < W * W; e += nt) {
+            const int i = e / W, j = e - i * W;
+            const int ri = i - k0, cj = j - k0;
+            const bool iK = ri >= 0 && ri < bs, jK = cj >= 0 && cj < bs;
+            double aiK[4], aKj[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                aiK[s] = (s < bs) ? a[i * W + k0 + s] : 0.0;
+                aKj[s] = (s < bs) ? a[(k0 + s) * W + j] : 0.0;
+            }
+            double v;
+            if (iK && jK) {
+                v = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (r == ri && c == cj) v = P[r][c];
+            } else if (iK) {
+                v = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) t += P[r][s] * aKj[s];
+                    if (r == ri) v = t;
+                }
+            } else {
+                double w[4];                        // a(i,K) P^-1
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) t += aiK[r] * P[r][c];
+                    w[c] = t;
+                }
+                if (jK) {
+                    v = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (c == cj) v = -w[c];
+                } else {
+                    v = a[e];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) v -= w[s] * aKj[s];
+                }
+            }
+            o[e] = v;
+        }
+        __syncthreads();
+        double* t = a;
+        a = o;
+        o = t;
+    }
+    return a;
+}
+
+// Dense W x W product on one 4 x 4 register tile, operands in LDS (row-major, ld = W);
+// tile t covers rows 4*(t / nq).., columns 4*(t % nq).., indices clamped at the edge.
+template <int WMAX>
+__device__ __forceinline__ void tile_product(const double* A, const double* B, int W, int tile,
+                                             double acc[4][4], int* p0, int* q0) {
+    const int nq = (W + 3) / 4;
+    *p0 = 4 * (tile / nq);
+    *q0 = 4 * (tile - (tile / nq) * nq);
+    int pr[4], qc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        pr[a] = min(*p0 + a, W - 1);
+        qc[a] = min(*q0 + a, W - 1);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+#pragma unroll 4
+    for (int m = 0; m < W; ++m) {
+        {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = A[pr[a] * W + m];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bv[c] = B[m * W + qc[c]];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+        }
+    }
+}
+
+// Boxes of width W <= kSmallW: every block of a step is staged in LDS:
+//   G0, G1 (Gauss-Jordan), A(K+1..K+3, K) -> Pa[3], A(K, K+1..K+3) -> Pb[3], Lh -> Pl[3]
+// (11 W^2 doubles).
+template <typename T, int WMAX>
+__global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restrict__ cc, double* __restrict__ work,
+                                                       T* __restrict__ fac, int* __restrict__ flag, LuBox b,
+                                                       StencilTable st) {
     extern __shared__ double lds[];
     const int W = b.W, H = b.H, WW = W * W;
-    double* Dg = lds;              // diagonal block, factored in place (L strict lower, U upper)
-    double* Li = lds + WW;         // inverse of unit-lower L(K,K)
-    double* Ui = lds + 2 * WW;     // inverse of U(K,K)
+    double* G0 = lds;
+    double* G1 = lds + WW;
+    double* Pa = lds + 2 * WW;
+    double* Pb = lds + 5 * WW;
+    double* Pl = lds + 8 * WW;
     const int k = blockIdx.x;
     const int ox = (k % b.subx) * b.ownx - b.ov, oy = (k / b.subx) * b.owny - b.ov;
-    double* win = work + (long)k * 22 * WW;   // 16 window slots + 6 panel scratch blocks
-    T* out = fac + (long)k * H * 8 * WW;
+    double* win = work + (long)k * 16 * WW;
+    T* out = fac + (long)k * H * 7 * WW;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int nq = (W + 3) / 4;
+    const int ntile = nq * nq;
+    __shared__ LdsStencil sst;
+    __shared__ double cring[8 * 72];        // c along the box rows entering the window
+    stage_stencil(&sst, b, st);
+    for (int J = 0; J < 5 && J < H; ++J) load_c_row(cring, J, b, cc, ox, oy);
+    __syncthreads();
 
     for (int I = 0; I < 4 && I < H; ++I)
-        for (int J = 0; J < 4 && J < H; ++J) assemble_block(slot(win, I, J, W), I, J, b, st, cc, ox, oy);
+        for (int J = 0; J < 4 && J < H; ++J)
+            assemble_block(slot(win, I, J, W), I, J, b, &sst, cring + (J & 7) * 72);
     __syncthreads();
 
     for (int K = 0; K < H; ++K) {
-        // (a) LU of the diagonal block in LDS
-        const double* A = slot(win, K, K, W);
-        for (int e = tid; e < WW; e += nt) Dg[e] = A[e];
-        __syncthreads();
-        for (int kk = 0; kk < W; ++kk) {
-            const double piv = Dg[kk * W + kk];
-            if (tid == 0 && (!(piv != 0.0) || !isfinite(piv))) *flag = 1;
-            for (int i = kk + 1 + tid; i < W; i += nt) Dg[i * W + kk] /= piv;
-            __syncthreads();
-            const int m = W - kk - 1;
-            for (int e = tid; e < m * m; e += nt) {
-                const int i = kk + 1 + e / m, j = kk + 1 + e % m;
-                Dg[i * W + j] -= Dg[i * W + kk] * Dg[kk * W + j];
-            }
-            __syncthreads();
-        }
-        // (b) inverses: rows of inv L top-down, rows of inv U bottom-up, interleaved
-        for (int e = tid; e < WW; e += nt) {
-            Li[e] = 0.0;
-            Ui[e] = 0.0;
-        }
-        __syncthreads();
-        for (int st2 = 0; st2 < W; ++st2) {
-            const int i = st2;              // inv L row i: Li[i][j] = -(L_ij + sum_{j<m<i} L_im Li[m][j]), j < i
-            const int iu = W - 1 - st2;     // inv U row iu: Ui[iu][j] = (delta - sum_{iu<m<=j} U_iu,m Ui[m][j]) / U_iu,iu
-            for (int j = tid; j < 2 * W; j += nt) {
-                if (j < W) {
-                    if (j < i) {
-                        double s = Dg[i * W + j];
-                        for (int m = j + 1; m < i; ++m) s += Dg[i * W + m] * Li[m * W + j];
-                        Li[i * W + j] = -s;
-                    } else if (j == i) {
-                        Li[i * W + i] = 1.0;
-                    }
-                } else {
-                    const int jj = j - W;
-                    if (jj >= iu) {
-                        double s = (jj == iu) ? 1.0 : 0.0;
-                        for (int m = iu + 1; m <= jj; ++m) s -= Dg[iu * W + m] * Ui[m * W + jj];
-                        Ui[iu * W + jj] = s / Dg[iu * W + iu];
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        // (c) panels into scratch: L(I,K) = A(I,K) inv U(K,K) -> scr[bi],
-        //     U(K,J) = inv L(K,K) A(K,J) -> scr[3 + bj]  (triangular inverses from LDS)
         const int nI = min(3, H - 1 - K);
-        for (int blk = 0; blk < 2 * nI; ++blk) {
-            const bool isL = blk < nI;
-            const int other = K + 1 + (isL ? blk : blk - nI);
-            const double* M = isL ? slot(win, other, K, W) : slot(win, K, other, W);
-            double* dst = win + (long)(16 + (isL ? blk : 3 + blk - nI)) * WW;
-            for (int e = tid; e < WW; e += nt) {
-                const int p = e / W, q = e - p * W;
-                double s = 0.0;
-                if (isL)
-                    for (int m = 0; m <= q; ++m) s += M[p * W + m] * Ui[m * W + q];
-                else
-                    for (int m = 0; m <= p; ++m) s += Li[p * W + m] * M[m * W + q];
-                dst[e] = s;
-            }
-        }
-        // (e1) store inv L(K,K) and inv U(K,K) of block row K, column-major
-        T* rowK = out + (long)K * 8 * WW;
-        for (int e = tid; e < WW; e += nt) {
-            const int p = e / W, q = e - p * W;     // element (p, q) -> column-major q * W + p
-            rowK[3 * WW + q * W + p] = (T)Li[e];
-            rowK[7 * WW + q * W + p] = (T)Ui[e];
+        T* rowK = out + (long)K * 7 * WW;
+        for (int e = tid; e < WW; e += nt) G0[e] = slot(win, K, K, W)[e];
+        for (int e = tid; e < nI * WW; e += nt) {
+            const int bi = e / WW, r = e - bi * WW;
+            Pa[bi * WW + r] = slot(win, K + 1 + bi, K, W)[r];
+            Pb[bi * WW + r] = slot(win, K, K + 1 + bi, W)[r];
         }
         __syncthreads();
-        // (c2) stage the U(K,J) panels in LDS (the diagonal block and inverses are done)
-        double* Us = lds;
-        for (int e = tid; e < nI * WW; e += nt) Us[e] = win[(long)19 * WW + e];
-        __syncthreads();
-        // (d) Schur complement: A(I,J) -= L(I,K) U(K,J); rows of L broadcast from L2, U from LDS
-        for (int bi = 0; bi < nI; ++bi)
-            for (int bj = 0; bj < nI; ++bj) {
-                const double* Lb = win + (long)(16 + bi) * WW;
-                const double* Ub = Us + (long)bj * WW;
-                double* Cb = slot(win, K + 1 + bi, K + 1 + bj, W);
-                for (int e = tid; e < WW; e += nt) {
-                    const int p = e / W, q = e - p * W;
-                    double s = 0.0;
-                    for (int m = 0; m < W; ++m) s += Lb[p * W + m] * Ub[m * W + q];
-                    Cb[e] -= s;
-                }
-            }
-        // (e2) store U(K, K+1..K+3) of block row K and L(I, K) of the rows below
-        for (int bj = 0; bj < 3; ++bj) {
-            const int J = K + 1 + bj;
-            for (int e = tid; e < WW; e += nt) {
-                const int p = e / W, q = e - p * W;
-                rowK[4 * WW + (bj * W + q) * W + p] = (T)(J < H ? Us[(long)bj * WW + e] : 0.0);
-            }
-        }
-        for (int bi = 0; bi < 3; ++bi) {
-            const int I = K + 1 + bi;
-            if (I >= H) break;
-            T* rowI = out + (long)I * 8 * WW;
-            const int cb = K - I + 3;                 // column block of L(I, K) within L(I, I-3..I-1)
-            for (int e = tid; e < WW; e += nt) {
-                const int p = e / W, q = e - p * W;
-                rowI[(cb * W + q) * W + p] = (T)win[(long)(16 + bi) * WW + e];
+        const double* Sinv = gauss_jordan(G0, G1, W, flag);
+        // Lh(I,K) = A(I,K) S^-1 -> Pl (LDS); Uh(K,J) = S^-1 A(K,J) -> stored negated
+        for (int t = tid; t < 2 * nI * ntile; t += nt) {
+            const int blk = t / ntile, tile = t - blk * ntile;
+            double acc[4][4];
+            int p0, q0;
+            if (blk < nI) {
+                tile_product<WMAX>(Pa + blk * WW, Sinv, W, tile, acc, &p0, &q0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (p0 + a < W && q0 + c < W) Pl[blk * WW + (p0 + a) * W + q0 + c] = acc[a][c];
+            } else {
+                const int bj = blk - nI;
+                tile_product<WMAX>(Sinv, Pb + bj * WW, W, tile, acc, &p0, &q0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (p0 + a < W && q0 + c < W)
+                            rowK[4 * WW + bj * WW + (q0 + c) * W + p0 + a] = (T)(-acc[a][c]);
             }
         }
-        if (K < 3) {   // L(K, K') for K' < 0 does not exist: zero those column blocks
-            for (int cb = 0; cb < 3 - K; ++cb)
-                for (int e = tid; e < WW; e += nt) rowK[cb * WW + e] = (T)0.0;
+        // S^-1 of block row K; zero Uh blocks past the box and Lh blocks before it
+        for (int e = tid; e < WW; e += nt) {          // e = q * W + p: coalesced column-major stores
+            const int q = e / W, p = e - q * W;
+            rowK[3 * WW + e] = (T)Sinv[p * W + q];
+            for (int bj = nI; bj < 3; ++bj) rowK[4 * WW + bj * WW + e] = (T)0.0;
+            if (K < 3)
+                for (int cb = 0; cb < 3 - K; ++cb) rowK[cb * WW + e] = (T)0.0;
         }
         __syncthreads();
-        // (f) slide the window: block row and column K + 4 enter
+        // Schur complement A(I,J) -= Lh(I,K) A(K,J); the C tile is loaded before the product
+        // so that its global-memory latency overlaps the LDS work
+        const int nsch = nI * nI * ntile;
+        for (int t = tid; t < nsch; t += nt) {
+            const int blk = t / ntile, tile = t - blk * ntile;
+            const int bi = blk / nI, bj = blk - bi * nI;
+            const int tp = 4 * (tile / nq), tq = 4 * (tile - (tile / nq) * nq);
+            double* C = slot(win, K + 1 + bi, K + 1 + bj, W);
+            double cv[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cv[a][c] = C[min(tp + a, W - 1) * W + min(tq + c, W - 1)];
+            double acc[4][4];
+            int p0, q0;
+            tile_product<WMAX>(Pl + bi * WW, Pb + bj * WW, W, tile, acc, &p0, &q0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (p0 + a < W && q0 + c < W) C[(p0 + a) * W + q0 + c] = cv[a][c] - acc[a][c];
+        }
+        // Lh(I, K) of the rows below: column block K - I + 3 of their panel
+        for (int e = tid; e < nI * WW; e += nt) {
+            const int bi = e / WW, r = e - bi * WW;
+            const int q = r / W, p = r - q * W;
+            out[(long)(K + 1 + bi) * 7 * WW + (2 - bi) * WW + r] = (T)Pl[bi * WW + p * W + q];
+        }
+        __syncthreads();
+        // slide the window: block row and column K + 4 enter
         const int N4 = K + 4;
         if (N4 < H) {
-            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, st, cc, ox, oy);
-            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, st, cc, ox, oy);
+            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72);
+            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72);
         }
+        if (N4 + 1 < H) load_c_row(cring, N4 + 1, b, cc, ox, oy);   // ring slot of row K-3, no longer read
         __syncthreads();
     }
 }
 
+// C (+)= sign * A B for W x W blocks with A streamed by rows from global memory and B in
+// LDS.  Thread t owns row p = t / TPR and the columns q = (t % TPR) + TPR * i; it keeps a
+// chunk of 8 entries of its row of A in registers, so A is read once per output row.
+template <int QMAX>
+__device__ void gemm_rows(double* C, const double* __restrict__ A, const double* B, int W, double sign,
+                          bool accumulate) {
+    const int tid = threadIdx.x, TPR = blockDim.x / W;
+    const int p = tid / TPR, q0 = tid - p * TPR;
+    if (p >= W) return;
+    double acc[QMAX];
+#pragma unroll
+    for (int i = 0; i < QMAX; ++i) acc[i] = 0.0;
+    for (int m0 = 0; m0 < W; m0 += 8) {
+        double a[8];
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) a[mm] = (m0 + mm < W) ? A[p * W + m0 + mm] : 0.0;
+#pragma unroll
+        for (int i = 0; i < QMAX; ++i) {
+            const int q = min(q0 + TPR * i, W - 1);     // clamped: tail lanes compute a discarded duplicate
+#pragma unroll
+            for (int mm = 0; mm < 8; ++mm) {
+                const int m = min(m0 + mm, W - 1);       // a[mm] = 0 past the end
+                acc[i] += a[mm] * B[m * W + q];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < QMAX; ++i) {
+        const int q = q0 + TPR * i;
+        if (q < W) C[p * W + q] = (accumulate ? C[p * W + q] : 0.0) + sign * acc[i];
+    }
+}
+
+// C = A B with A in LDS and B streamed by columns from global memory.
+template <int PMAX>
+__device__ void gemm_cols(double* C, const double* A, const double* __restrict__ B, int W) {
+    const int tid = threadIdx.x, TPC = blockDim.x / W;
+    const int q = tid / TPC, p0 = tid - q * TPC;
+    if (q >= W) return;
+    double acc[PMAX];
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i) acc[i] = 0.0;
+    for (int m0 = 0; m0 < W; m0 += 8) {
+        double bcol[8];
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) bcol[mm] = (m0 + mm < W) ? B[(m0 + mm) * W + q] : 0.0;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) {
+            const int p = min(p0 + TPC * i, W - 1);
+#pragma unroll
+            for (int mm = 0; mm < 8; ++mm) {
+                const int m = min(m0 + mm, W - 1);      // bcol[mm] = 0 past the end
+                acc[i] += A[p * W + m] * bcol[mm];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i) {
+        const int p = p0 + TPC * i;
+        if (p < W) C[p * W + q] = acc[i];
+    }
+}
+
+// Wider boxes (kSmallW < W <= 72): Gauss-Jordan in LDS, panels in the global workspace
+// (blocks 16..21), the A(K, J) blocks staged into LDS for the Schur update (3 W^2 doubles).
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_apply(const double* __restrict__ r, double* __restrict__ z,
-                                                  const T* __restrict__ fac, LuBox b) {
+__global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict__ cc, double* __restrict__ work,
+                                                        T* __restrict__ fac, int* __restrict__ flag, LuBox b,
+                                                        StencilTable st) {
+    extern __shared__ double lds[];
+    const int W = b.W, H = b.H, WW = W * W;
+    const int k = blockIdx.x;
+    const int ox = (k % b.subx) * b.ownx - b.ov, oy = (k / b.subx) * b.owny - b.ov;
+    double* win = work + (long)k * 22 * WW;
+    T* out = fac + (long)k * H * 7 * WW;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ LdsStencil sst;
+    __shared__ double cring[8 * 72];        // c along the box rows entering the window
+    stage_stencil(&sst, b, st);
+    for (int J = 0; J < 5 && J < H; ++J) load_c_row(cring, J, b, cc, ox, oy);
+    __syncthreads();
+
+    for (int I = 0; I < 4 && I < H; ++I)
+        for (int J = 0; J < 4 && J < H; ++J)
+            assemble_block(slot(win, I, J, W), I, J, b, &sst, cring + (J & 7) * 72);
+    __syncthreads();
+
+    for (int K = 0; K < H; ++K) {
+        const int nI = min(3, H - 1 - K);
+        T* rowK = out + (long)K * 7 * WW;
+        for (int e = tid; e < WW; e += nt) lds[e] = slot(win, K, K, W)[e];
+        __syncthreads();
+        const double* Sinv = gauss_jordan(lds, lds + WW, W, flag);
+        // Lh(I,K) = A(I,K) S^-1 -> blocks 16+bi; Uh(K,J) = S^-1 A(K,J) -> blocks 19+bj
+        for (int bi = 0; bi < nI; ++bi)
+            gemm_rows<24>(win + (long)(16 + bi) * WW, slot(win, K + 1 + bi, K, W), Sinv, W, 1.0, false);
+        for (int bj = 0; bj < nI; ++bj)
+            gemm_cols<24>(win + (long)(19 + bj) * WW, Sinv, slot(win, K, K + 1 + bj, W), W);
+        for (int e = tid; e < WW; e += nt) {
+            const int q = e / W, p = e - q * W;
+            rowK[3 * WW + e] = (T)Sinv[p * W + q];
+        }
+        __syncthreads();
+        double* As = lds;                // S^-1 is done: stage A(K, K+1..K+3) for the Schur update
+        for (int e = tid; e < nI * WW; e += nt) {
+            const int bj = e / WW, r = e - bj * WW;
+            As[e] = slot(win, K, K + 1 + bj, W)[r];
+        }
+        __syncthreads();
+        for (int bi = 0; bi < nI; ++bi)
+            for (int bj = 0; bj < nI; ++bj)
+                gemm_rows<24>(slot(win, K + 1 + bi, K + 1 + bj, W), win + (long)(16 + bi) * WW, As + (long)bj * WW,
+                              W, -1.0, true);
+        for (int e = tid; e < WW; e += nt) {
+            const int q = e / W, p = e - q * W, rm = p * W + q;
+            for (int bj = 0; bj < 3; ++bj)
+                rowK[4 * WW + bj * WW + e] = (T)(bj < nI ? -win[(long)(19 + bj) * WW + rm] : 0.0);
+            if (K < 3)
+                for (int cb = 0; cb < 3 - K; ++cb) rowK[cb * WW + e] = (T)0.0;
+            for (int bi = 0; bi < nI; ++bi)
+                out[(long)(K + 1 + bi) * 7 * WW + (2 - bi) * WW + e] = (T)win[(long)(16 + bi) * WW + rm];
+        }
+        __syncthreads();
+        const int N4 = K + 4;
+        if (N4 < H) {
+            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72);
+            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72);
+        }
+        if (N4 + 1 < H) load_c_row(cring, N4 + 1, b, cc, ox, oy);   // ring slot of row K-3, no longer read
+        __syncthreads();
+    }
+}
+
+// Block solve.  Thread (p, g), g < G = blockDim / W, handles row p of a block row and the
+// columns q = g + G*i of its dense product; it holds the factors of DEPTH block rows ahead
+// in registers so that their loads overlap the barriers of the current row.
+//   forward  (half 0): z_I = y_I - [Lh(I,I-3..I-1)] y[(I-3)W : IW]        (3W columns)
+//   backward (half 1): x_I = [S_II^-1 | -Uh(I,I+1..I+3)] y[IW : (I+4)W]    (4W columns)
+template <typename T, int NPL, int DEPTH>
+__global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z, const T* __restrict__ fac,
+                           LuBox b) {
     extern __shared__ unsigned char smem_raw[];
     const int W = b.W, H = b.H, WW = W * W;
     T* y = reinterpret_cast<T*>(smem_raw);          // W*H box vector
     T* red = y + W * H;                              // G * W partial sums
     const int tid = threadIdx.x;
-    const int G = blockDim.x / W;                    // column groups
+    const int G = blockDim.x / W;
     const int p = tid % W, g = tid / W;
     const bool act = g < G;
     const int k = blockIdx.x;
     const int ox = (k % b.subx) * b.ownx - b.ov, oy = (k / b.subx) * b.owny - b.ov;
-    const T* F = fac + (long)k * H * 8 * WW;
+    const T* F = fac + (long)k * H * 7 * WW;
 
     for (int e = tid; e < W * H; e += blockDim.x) {
         const int x = e % W, yy = e / W;
         y[e] = (T)r[(long)wrapg(oy + yy, b.ny) * b.nx + wrapg(ox + x, b.nx)];
     }
+
+    T pl[DEPTH + 1][NPL];
+    auto load = [&](int I, int half, T* l) {
+        const T* base = F + (long)I * 7 * WW + half * 3 * WW;
+        const int ncol = half ? 4 * W : 3 * W;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int q = g + G * i;
+            l[i] = (act && q < ncol) ? base[q * W + p] : (T)0;
+        }
+    };
+    auto rotate = [&]() {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d)
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) pl[d][i] = pl[d + 1][i];
+    };
+
+    // forward sweep
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d)
+        if (d < H) load(d, 0, pl[d]);
     __syncthreads();
-    // forward substitution, block row by block row
     for (int I = 0; I < H; ++I) {
-        const T* Lp = F + (long)I * 8 * WW;
-        const T* Li = Lp + 3 * WW;
-        T acc = 0;
+        if (I + DEPTH < H) load(I + DEPTH, 0, pl[DEPTH]);
         if (act) {
-            const int q0 = I >= 3 ? 0 : (3 - I) * W;
-            const T* yb = y + (I - 3) * W;
-            for (int q = q0 + g; q < 3 * W; q += G) acc += Lp[q * W + p] * yb[q];
+            T acc = 0;
+            const int base = (I - 3) * W;
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                const int q = g + G * i;
+                if (q < 3 * W && base + q >= 0) acc += pl[0][i] * y[base + q];
+            }
             red[g * W + p] = acc;
         }
         __syncthreads();
@@ -232,40 +521,23 @@ __global__ __launch_bounds__(256) void k_lu_apply(const double* __restrict__ r, 
             y[I * W + tid] = s;
         }
         __syncthreads();
-        if (act) {
-            acc = 0;
-            for (int q = g; q < W; q += G) acc += Li[q * W + p] * y[I * W + q];
-            red[g * W + p] = acc;
-        }
-        __syncthreads();
-        if (tid < W) {
-            T s = 0;
-            for (int gg = 0; gg < G; ++gg) s += red[gg * W + tid];
-            y[I * W + tid] = s;
-        }
-        __syncthreads();
+        rotate();
     }
-    // backward substitution
+    // backward sweep (S^-1 and -Uh in one product)
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d)
+        if (H - 1 - d >= 0) load(H - 1 - d, 1, pl[d]);
     for (int I = H - 1; I >= 0; --I) {
-        const T* Up = F + (long)I * 8 * WW + 4 * WW;
-        const T* Ui = Up + 3 * WW;
+        if (I - DEPTH >= 0) load(I - DEPTH, 1, pl[DEPTH]);
         if (act) {
             T acc = 0;
-            const int qend = min(3, H - 1 - I) * W;
-            const T* xb = y + (I + 1) * W;
-            for (int q = g; q < qend; q += G) acc += Up[q * W + p] * xb[q];
-            red[g * W + p] = acc;
-        }
-        __syncthreads();
-        if (tid < W) {
-            T s = y[I * W + tid];
-            for (int gg = 0; gg < G; ++gg) s -= red[gg * W + tid];
-            y[I * W + tid] = s;
-        }
-        __syncthreads();
-        if (act) {
-            T acc = 0;
-            for (int q = g; q < W; q += G) acc += Ui[q * W + p] * y[I * W + q];
+            const int base = I * W;
+            const int qend = (1 + min(3, H - 1 - I)) * W;
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                const int q = g + G * i;
+                if (q < qend) acc += pl[0][i] * y[base + q];
+            }
             red[g * W + p] = acc;
         }
         __syncthreads();
@@ -275,6 +547,7 @@ __global__ __launch_bounds__(256) void k_lu_apply(const double* __restrict__ r, 
             y[I * W + tid] = s;
         }
         __syncthreads();
+        rotate();
     }
     // restricted extension: owned cells only
     for (int e = tid; e < b.ownx * b.owny; e += blockDim.x) {
@@ -298,43 +571,78 @@ LuBox make_lubox(const pfc_ctx* c, const StencilTable& st) {
     return b;
 }
 
+// Launch shape of the solve for box width W; NPL covers ceil(4W / G), G = threads / W:
+//   W <= 32: 256 threads, G >= 8  -> NPL 16, prefetch 2 rows (FP32) / 1 row (FP64)
+//   W <= 72: 1024 threads, G >= 14 -> NPL 21, prefetch 1 row (FP32) / none (FP64)
+template <typename T>
+hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b) {
+    constexpr bool f32 = sizeof(T) == 4;
+    const int threads = b.W <= 32 ? 256 : 1024;
+    const int G = threads / b.W;
+    const size_t sh = sizeof(T) * ((size_t)b.W * b.H + (size_t)G * b.W);
+    const T* f = (const T*)c->d_fac;
+    const dim3 grid(c->dec.nsub), blk(threads);
+    if (b.W <= 32)
+        hipLaunchKernelGGL((k_lu_apply<T, 16, f32 ? 2 : 1>), grid, blk, sh, c->stream, r, z, f, b);
+    else
+        hipLaunchKernelGGL((k_lu_apply<T, 21, f32 ? 1 : 0>), grid, blk, sh, c->stream, r, z, f, b);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-size_t lu_factor_lds_bytes(int W) { return sizeof(double) * 3 * (size_t)W * W; }
+size_t lu_factor_lds_bytes(int W) { return sizeof(double) * (W <= kSmallW ? 11 : 3) * (size_t)W * W; }
+
+size_t lu_work_blocks(int W) { return W <= kSmallW ? 16 : 22; }
+
+size_t lu_factor_elems_per_block_row(int W) { return 7 * (size_t)W * W; }
 
 hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& st) {
     const LuBox b = make_lubox(c, st);
     const size_t sh = lu_factor_lds_bytes(b.W);
-    if (c->opts.precond_fp32)
-        hipLaunchKernelGGL(k_lu_factor<float>, dim3(c->dec.nsub), dim3(256), sh, c->stream, c->d_c, c->d_work,
-                           (float*)c->d_fac, c->d_flag, b, st);
-    else
-        hipLaunchKernelGGL(k_lu_factor<double>, dim3(c->dec.nsub), dim3(256), sh, c->stream, c->d_c, c->d_work,
-                           (double*)c->d_fac, c->d_flag, b, st);
+    const dim3 grid(c->dec.nsub), blk(256);
+    const bool f32 = c->opts.precond_fp32;
+    float* ff = (float*)c->d_fac;
+    double* fd = (double*)c->d_fac;
+    if (b.W <= 24) {
+        if (f32)
+            hipLaunchKernelGGL((k_lu_factor_lds<float, 24>), grid, blk, sh, c->stream, c->d_c, c->d_work, ff,
+                               c->d_flag, b, st);
+        else
+            hipLaunchKernelGGL((k_lu_factor_lds<double, 24>), grid, blk, sh, c->stream, c->d_c, c->d_work, fd,
+                               c->d_flag, b, st);
+    } else if (b.W <= kSmallW) {
+        if (f32)
+            hipLaunchKernelGGL((k_lu_factor_lds<float, kSmallW>), grid, blk, sh, c->stream, c->d_c, c->d_work, ff,
+                               c->d_flag, b, st);
+        else
+            hipLaunchKernelGGL((k_lu_factor_lds<double, kSmallW>), grid, blk, sh, c->stream, c->d_c, c->d_work, fd,
+                               c->d_flag, b, st);
+    } else {
+        if (f32)
+            hipLaunchKernelGGL(k_lu_factor_wide<float>, grid, blk, sh, c->stream, c->d_c, c->d_work, ff, c->d_flag,
+                               b, st);
+        else
+            hipLaunchKernelGGL(k_lu_factor_wide<double>, grid, blk, sh, c->stream, c->d_c, c->d_work, fd, c->d_flag,
+                               b, st);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z) {
     const LuBox b = make_lubox(c, c->st);
-    const int threads = 256;
-    const int G = threads / b.W;
-    if (c->opts.precond_fp32) {
-        const size_t sh = sizeof(float) * ((size_t)b.W * b.H + (size_t)G * b.W);
-        hipLaunchKernelGGL(k_lu_apply<float>, dim3(c->dec.nsub), dim3(threads), sh, c->stream, r, z,
-                           (const float*)c->d_fac, b);
-    } else {
-        const size_t sh = sizeof(double) * ((size_t)b.W * b.H + (size_t)G * b.W);
-        hipLaunchKernelGGL(k_lu_apply<double>, dim3(c->dec.nsub), dim3(threads), sh, c->stream, r, z,
-                           (const double*)c->d_fac, b);
-    }
-    return hipGetLastError();
+    if (c->opts.precond_fp32) return launch_apply_t<float>(c, r, z, b);
+    return launch_apply_t<double>(c, r, z, b);
 }
 
 hipError_t set_lu_lds_limits() {
-    const void* fns[] = {(const void*)k_lu_factor<double>, (const void*)k_lu_factor<float>,
-                         (const void*)k_lu_apply<double>, (const void*)k_lu_apply<float>};
+    const void* fns[] = {(const void*)k_lu_factor_lds<double, 24>, (const void*)k_lu_factor_lds<float, 24>,
+                         (const void*)k_lu_factor_lds<double, kSmallW>, (const void*)k_lu_factor_lds<float, kSmallW>,
+                         (const void*)k_lu_factor_wide<double>, (const void*)k_lu_factor_wide<float>,
+                         (const void*)k_lu_apply<double, 16, 1>, (const void*)k_lu_apply<float, 16, 2>,
+                         (const void*)k_lu_apply<double, 21, 0>, (const void*)k_lu_apply<float, 21, 1>};
     for (const void* f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = set_dynamic_lds_limit(f);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

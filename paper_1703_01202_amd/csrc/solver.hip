@@ -22,6 +22,8 @@ void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<in
 hipError_t set_ilu_lds_limits();
 hipError_t set_lu_lds_limits();
 size_t lu_factor_lds_bytes(int W);
+size_t lu_work_blocks(int W);
+size_t lu_factor_elems_per_block_row(int W);
 }  // namespace pfc
 
 using namespace pfc;
@@ -460,10 +462,8 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
         d.nsub *= d.sub[a];
         d.next *= d.ext[a];
     }
-    if (op->sub_solver == PFC_SUB_LU && (d.ext[0] > 128 || 256 / d.ext[0] < 2)) {
-        s = bad("exact LU needs a box x-extent of at most 128");
-    }
-    if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && lu_factor_lds_bytes(d.ext[0]) > 160 * 1024)
+    if (op->sub_solver == PFC_SUB_LU && d.ext[0] > 72) s = bad("exact LU needs a box x-extent of at most 72");
+    if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && lu_factor_lds_bytes(d.ext[0]) > 159 * 1024)
         s = bad("exact LU block too large for LDS");
     const size_t ilu_lds = (op->precond_fp32 ? 4 : 8) * (size_t)d.next;
     if (s == PFC_OK && op->sub_solver == PFC_SUB_ILU0 && ilu_lds > 160 * 1024) s = bad("subdomain too large for LDS");
@@ -514,8 +514,8 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
         c->lu_W = d.ext[0];
         c->lu_H = d.ext[1];
         const size_t WW = (size_t)c->lu_W * c->lu_W;
-        c->fac_elems = (size_t)d.nsub * c->lu_H * 8 * WW;
-        A(dalloc(c, &c->d_work, (size_t)d.nsub * 22 * WW));
+        c->fac_elems = (size_t)d.nsub * c->lu_H * lu_factor_elems_per_block_row(c->lu_W);
+        A(dalloc(c, &c->d_work, (size_t)d.nsub * lu_work_blocks(c->lu_W) * WW));
     }
     if (s == PFC_OK) {
         if (hipMalloc(&c->d_fac, esz * c->fac_elems) != hipSuccess) s = fail(c, PFC_ENOMEM, "factor allocation failed");

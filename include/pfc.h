@@ -87,6 +87,12 @@ typedef struct {
     double dt_min, dt_max, eta;       /* Eq. (16); dt_min == dt_max gives a fixed step */
     int max_retries;                  /* dt halvings after a failed Newton solve, default 4 */
     int timing;                       /* 1: time every preconditioner/stencil launch with events */
+    int precond_lag;                  /* 0: factor at the first Newton step of every time step (the
+                                         paper's reuse); L > 0: pfc_step keeps the factors for up to L
+                                         time steps while dt stays within 20% of the dt they were built
+                                         with and GMRES iterations per Newton step stay at most twice
+                                         (+1) those of the step that factored; a failed solve on lagged
+                                         factors is retried with fresh ones */
 } pfc_opts;
 
 typedef struct {

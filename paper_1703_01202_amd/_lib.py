@@ -38,7 +38,7 @@ class PfcOpts(ctypes.Structure):
         ("sub_solver", ctypes.c_int), ("precond_fp32", ctypes.c_int), ("mass_project", ctypes.c_int),
         ("guess", ctypes.c_int),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double), ("eta", ctypes.c_double),
-        ("max_retries", ctypes.c_int), ("timing", ctypes.c_int),
+        ("max_retries", ctypes.c_int), ("timing", ctypes.c_int), ("precond_lag", ctypes.c_int),
     ]
 
 

@@ -102,6 +102,13 @@ struct pfc_ctx {
     double F_n = 0, F_nm1 = 0, dt_nm1 = 0, t = 0;
     bool have_prev = false, have_energy = false;
 
+    // factorisation reuse across time steps (opts.precond_lag)
+    bool fac_valid = false;
+    double fac_dt = 0.0;               // dt the factors were built with
+    long fac_step = -1;                // time step that built them
+    double fac_gpn = 0.0;              // GMRES iterations per Newton step of that time step
+    double last_gpn = 0.0;             // ... of the last time step
+
     pfc::KernelTimer timer;
 };
 

@@ -159,8 +159,23 @@ pfc_status setup_impl(pfc_ctx* c, const double* Phi, const double* phi, double d
     HIPCHK(hipMemcpyAsync(c->h_pin, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     CHK(sync(c));
     std::memcpy(&flag, c->h_pin, sizeof(int));
-    if (flag) return fail(c, PFC_EPIVOT, "zero or non-finite pivot in a subdomain factorisation");
+    if (flag) {
+        c->fac_valid = false;
+        return fail(c, PFC_EPIVOT, "zero or non-finite pivot in a subdomain factorisation");
+    }
+    c->fac_valid = true;
+    c->fac_dt = dt;
+    c->fac_step = c->step;
     return PFC_OK;
+}
+
+// May the factors of an earlier time step precondition this one (opts.precond_lag)?
+bool may_reuse_factors(const pfc_ctx* c, double dt) {
+    const int lag = c->opts.precond_lag;
+    if (lag <= 0 || !c->fac_valid || c->fac_step < 0) return false;
+    if (c->step - c->fac_step >= lag) return false;
+    if (std::fabs(dt - c->fac_dt) > 0.2 * c->fac_dt) return false;
+    return c->last_gpn <= 2.0 * c->fac_gpn + 1.0;
 }
 
 pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
@@ -284,7 +299,7 @@ double residual_floor(const pfc_ctx* c, double dt, double xnorm) {
     return 2.220446049250313e-16 * op * xnorm;
 }
 
-pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats* st) {
+pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats* st, bool reuse = false) {
     const long N = c->g.N;
     double fn, xnorm;
     CHK(residual_impl(c, c->d_X, phi, dt, nullptr, c->d_F, &fn));
@@ -294,7 +309,7 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
     st->newton_its = 0;
     st->gmres_its = 0;
     st->ls_cuts = 0;
-    bool factored = false;
+    bool factored = reuse;                          // lagged factors of an earlier step
     for (int it = 0; it < c->opts.newton_maxit && fn > target; ++it) {
         if (!factored) {
             CHK(setup_impl(c, c->d_X, phi, dt));    // factor once per solve, reuse afterwards
@@ -420,6 +435,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (s == PFC_OK && op->overlap < 0) s = bad("negative overlap");
     if (s == PFC_OK && (op->gmres_restart < 1 || op->gmres_restart > 60)) s = bad("gmres_restart must be 1..60");
     if (s == PFC_OK && (op->gmres_maxit < 1 || op->newton_maxit < 1)) s = bad("iteration limits must be >= 1");
+    if (s == PFC_OK && op->precond_lag < 0) s = bad("precond_lag must be >= 0");
     if (s == PFC_OK && op->ras_kind != PFC_RAS_LEFT) s = bad("only left-RAS is built");
     if (s == PFC_OK && op->sub_solver != PFC_SUB_ILU0 && op->sub_solver != PFC_SUB_LU) s = bad("bad sub_solver");
     if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && dim != 2) {
@@ -623,7 +639,32 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
         }
         pfc_step_stats tmp;
         std::memset(&tmp, 0, sizeof(tmp));
-        s = newton_impl(c, phi, dt, &tmp);
+        const bool reuse = may_reuse_factors(c, dt);
+        const long fac_before = c->fac_step;
+        s = newton_impl(c, phi, dt, &tmp, reuse);
+        if (s != PFC_OK && reuse && (s == PFC_ENOTCONV || s == PFC_EKRYLOV)) {
+            // lagged factors did not do: same dt, fresh factors
+            st->newton_its += tmp.newton_its;
+            st->gmres_its += tmp.gmres_its;
+            if (used == PFC_GUESS_EXTRAP) {
+                HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
+                if (o.mass_project) {
+                    HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
+                    CHK(mean_to_device(c, c->d_w));
+                    HIPCHK(launch_shift(c->stream, c->d_X, c->d_scal + SC_MEAN, 1.0, N));
+                }
+            } else {
+                HIPCHK(hipMemcpyAsync(c->d_X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+            }
+            std::memset(&tmp, 0, sizeof(tmp));
+            c->fac_valid = false;
+            s = newton_impl(c, phi, dt, &tmp, false);
+        }
+        if (s == PFC_OK && tmp.newton_its > 0) {
+            const double gpn = (double)tmp.gmres_its / tmp.newton_its;
+            if (c->fac_step != fac_before || c->fac_step == c->step) c->fac_gpn = gpn;
+            c->last_gpn = gpn;
+        }
         st->newton_its += tmp.newton_its;
         st->gmres_its += tmp.gmres_its;
         st->ls_cuts += tmp.ls_cuts;
@@ -658,6 +699,9 @@ pfc_status pfc_reset(pfc_ctx* c) {
     c->step = 0;
     c->F_n = c->F_nm1 = c->dt_nm1 = c->t = 0.0;
     c->have_prev = c->have_energy = false;
+    c->fac_valid = false;
+    c->fac_step = -1;
+    c->fac_gpn = c->last_gpn = 0.0;
     for (int i = 0; i < 4; ++i) {
         c->timer.count[i] = 0;
         c->timer.total_ms[i] = 0.0;

@@ -263,6 +263,26 @@ def test_trajectory_small_noise_10_steps():
     s.close()
 
 
+@pytest.mark.parametrize("lag,fp32,guess", [(5, False, "previous"), (20, True, "extrap")])
+def test_trajectory_lagged_factors_fp32_extrapolation(lag, fp32, guess):
+    """Factors kept across steps, FP32 factors and extrapolated guesses change the work,
+    not the accepted solution: same oracle trajectory to the Newton tolerance."""
+    pfc = _pfc()
+    w = I.small_noise_64()
+    h = S.spacing(w.shape, w.lengths)
+    phi0 = w.initial()
+    ref = S.run(phi0, 6, w.gamma, h, w.dt_min, w.dt_max)
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, dt_min=w.dt_min, dt_max=w.dt_max,
+                   newton_rtol=0.0, newton_atol=1e-11, precond_lag=lag, precond_fp32=fp32, guess=guess)
+    phi = T(phi0)
+    m0 = S.mass(phi0, h)
+    for n in range(6):
+        st = s.step(phi)
+        assert rel(N(phi), ref.phis[n + 1]) < 1e-10, n
+        assert abs(st["mass"] - m0) <= 1e-12 * abs(m0)
+    s.close()
+
+
 def test_adaptive_steps_follow_energy_history():
     pfc = _pfc()
     w = I.crystal_growth(128, (2, 2), nsteps=6)

@@ -23,6 +23,26 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (calibrated against a known-size copy; see profiles/), valid only for the kernel source
+# they were taken on: the sha256 prefix of the source file must match.
+MEASURED_TRAFFIC = {
+    ("fast", "ras_apply"): {"file": "paper_1703_01202_amd/csrc/ras_lu.hip", "sha": "85bc499dad3601b5",
+                            "bytes": 1.2230e9},
+}
+
+
+def measured_traffic(variant, kernel):
+    import hashlib
+    m = MEASURED_TRAFFIC.get((variant, kernel))
+    if not m:
+        return None
+    try:
+        sha = hashlib.sha256(open(os.path.join(ROOT, m["file"]), "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return m["bytes"] if sha == m["sha"] else None
+
 VARIANTS = {
     # the paper's method as configured: FP64 everywhere, 16 x 16 subdomains, overlap 4,
     # exact subdomain LU factored once per step, previous solution as initial guess
@@ -121,7 +141,8 @@ def run_variant(name, steps, warmup, timing=True):
     avg_s = ms / 1e3 / max(cnt, 1)
     gbs = bytes_per[dom] / avg_s / 1e9 if cnt else 0.0
     res["roofline"] = {"kernel": names[dom], "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
-                       "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                       "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                       "traffic": measured_traffic(name, names[dom]),
                        "bytes_per_launch": bytes_per[dom], "avg_launch_us": avg_s * 1e6, "launches": cnt,
                        "factorisation_ms_total": kt[3][1]}
     return res
@@ -135,12 +156,21 @@ def main():
     ap.add_argument("--variant", default="fast", choices=sorted(VARIANTS))
     ap.add_argument("--compare", default="plain", help="second variant timed beside (or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 512 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     main_res = run_variant(args.variant, args.steps, args.warmup)
     cmp_res = None
     if args.compare != "none" and args.compare != args.variant:
@@ -157,7 +187,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if not VARIANTS[args.variant]["precond_fp32"] else "f64 (f32 preconditioner)",
+        "dtype": "f64",
+        "precond_dtype": "f32" if VARIANTS[args.variant]["precond_fp32"] else "f64",
         "data": "synthetic",
         "config": {"workload": "pfc2d_1024_crystal: 1024^2 periodic, [0,400]^2, gamma 0.25, mean -0.285, "
                                "3 hex crystallites r=10 cells, adaptive dt 1e-2..10 eta 5000",

@@ -93,6 +93,10 @@ typedef struct {
                                          with and GMRES iterations per Newton step stay at most twice
                                          (+1) those of the step that factored; a failed solve on lagged
                                          factors is retried with fresh ones */
+    int newton_rel_ref;               /* reference of eps_r in Eq. (20): 1 (default) ||F(phi^n)||, the
+                                         residual of the paper's initial guess Phi_0 = phi^n, whatever
+                                         guess starts the iteration, so every guess meets the same
+                                         target; 0: ||F|| at the guess actually used */
 } pfc_opts;
 
 typedef struct {

@@ -32,7 +32,7 @@ class Solver:
     def __init__(self, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precond_fp32=False,
                  dt_min=0.1, dt_max=None, eta=0.0, newton_rtol=1e-8, newton_atol=1e-10,
                  lin_rtol=1e-3, lin_atol=1e-11, gmres_restart=30, gmres_maxit=300, newton_maxit=50,
-                 guess="previous", mass_project=True, max_retries=4, timing=False, precond_lag=0, stream=None):
+                 guess="previous", mass_project=True, max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True, stream=None):
         import torch
         self._torch = torch
         self.lib = _lib.load()
@@ -69,6 +69,7 @@ class Solver:
         o.max_retries = int(max_retries)
         o.timing = int(bool(timing))
         o.precond_lag = int(precond_lag)
+        o.newton_rel_ref = int(bool(newton_rel_ref))
         self.opts = o
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream

@@ -93,9 +93,10 @@ struct pfc_ctx {
     double* d_tmp3 = nullptr;          // 3-D multi-pass temporaries (2 * N)
 
     // reductions
-    double* d_part = nullptr;          // kRedBlocks * 64 partials
-    double* d_scal = nullptr;          // 256 device scalars
-    double* h_pin = nullptr;           // pinned host mirror (256 doubles)
+    double* d_part = nullptr;          // partials summed on the device (Gram-Schmidt, apply sums)
+    double* d_scal = nullptr;          // device scalars, then partials summed on the host
+    double* h_pin = nullptr;           // pinned host mirror of d_scal
+    int n_scal = 0;                    // doubles in d_scal / h_pin
 
     // time history
     long step = 0;
@@ -123,35 +124,38 @@ inline hipError_t set_dynamic_lds_limit(const void* f) {
 }
 
 // ---- stencil kernels (stencil.hip) ----
+// Reductions leave per-block partials (device_reduce.h); partial_count gives their number.
+int residual_partial_count(const pfc_ctx* c);   // blocks of the residual / energy kernels
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
-                           const double* src, double* F, double* partials);
+                           const double* src, double* F, double* norm_part);
 hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, double* cbuf);
-hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt,
-                     const double* vshift, double* Jv);
-hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* partials);
+// Jv of (v - s), s = shift_scale * sum(shift_part[0..shift_n)) (no shift if shift_part is null);
+// s is stored in *shift_out when given.
+hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt, const double* shift_part,
+                     int shift_n, double shift_scale, double* shift_out, double* Jv);
+hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2);
 
-// ---- BLAS-1 and reductions (blas.hip) ----
-hipError_t launch_dot_partials(hipStream_t s, const double* x, const double* y, long n,
-                               double* partials);
-hipError_t launch_sum_partials(hipStream_t s, const double* x, long n, double* partials);
-hipError_t launch_reduce_rows(hipStream_t s, const double* partials, int rows, double* out,
-                              double scale);
-hipError_t launch_multidot(hipStream_t s, const double* V, long ld, int k, const double* w,
-                           long n, double* partials);
-hipError_t launch_maxpy(hipStream_t s, const double* V, long ld, int k, const double* coef,
-                        double sign, double* w, long n, double* norm_partials);
+// ---- BLAS-1 (blas.hip) ----
+hipError_t launch_dot(hipStream_t s, const double* x, const double* y, long n, double* partials);
+hipError_t launch_reduce_rows_n(hipStream_t s, const double* partials, int rows, int count, double* out,
+                                double scale);
+hipError_t launch_multidot(hipStream_t s, const double* V, long ld, int k, const double* w, long n,
+                           double* partials);
+hipError_t launch_maxpy(hipStream_t s, const double* V, long ld, int k, const double* coef_part, int coef_n,
+                        double sign, double* w, long n, double* norm_part, double* coef_out);
 hipError_t launch_axpby(hipStream_t s, double a, const double* x, double b, const double* y,
                         double* out, long n);
 hipError_t launch_scale(hipStream_t s, const double* x, double a, double* out, long n);
-hipError_t launch_shift(hipStream_t s, double* x, const double* dev_scalar, double sign, long n);
+hipError_t launch_shift(hipStream_t s, double* x, const double* part, int np, double scale, long n);
 hipError_t launch_extrap(hipStream_t s, const double* phi, const double* prev, double ratio,
                          double* out, long n);
 
 // ---- Schwarz preconditioner (ras_ilu.hip, ras_lu.hip) ----
+// sum_part (nullable): one partial per subdomain of the sum of the output z.
 void build_stencil_table(const Geom& g, double gamma, double dt, StencilTable* t);
 hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& t);
-hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z);
+hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
 hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& t);
-hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z);
+hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
 
 }  // namespace pfc

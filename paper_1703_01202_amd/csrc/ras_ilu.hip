@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <map>
 
+#include "device_reduce.h"
 #include "pfc_internal.h"
 
 namespace pfc {
@@ -174,7 +175,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, double* __restrict__ z,
                                                   const T* __restrict__ fac, const int* __restrict__ lptr,
                                                   const int* __restrict__ lpts, Box b, StencilTable st,
-                                                  int nlev) {
+                                                  int nlev, double* __restrict__ sum_part) {
     extern __shared__ unsigned char smem_raw[];
     T* yv = reinterpret_cast<T*>(smem_raw);
     const int S = st.S, D = st.diag;
@@ -224,9 +225,17 @@ __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, 
     // restricted extension: write only the owned cells
     const int owx = b.ownx, owy = b.owny, owz = b.nz > 1 ? b.ownz : 1;
     const int zoff = b.nz > 1 ? b.ov : 0;
+    double acc = 0.0;
     for (int e = threadIdx.x; e < owx * owy * owz; e += blockDim.x) {
         const int x = e % owx + b.ov, y = (e / owx) % owy + b.ov, zz = e / (owx * owy) + zoff;
-        z[gidx(b, ox, oy, oz, x, y, zz)] = (double)yv[(zz * b.ey + y) * b.ex + x];
+        const double v = (double)yv[(zz * b.ey + y) * b.ex + x];
+        z[gidx(b, ox, oy, oz, x, y, zz)] = v;
+        acc += v;
+    }
+    if (sum_part) {
+        __shared__ double red[16];
+        const double sum = block_sum_det(acc, red);
+        if (threadIdx.x == 0) sum_part[blockIdx.x] = sum;
     }
 }
 
@@ -287,17 +296,17 @@ hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& st) {
     return hipGetLastError();
 }
 
-hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z) {
+hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {
     const Box b = make_box(c);
     const StencilTable& st = c->st;
     if (c->opts.precond_fp32) {
         const size_t sh = sizeof(float) * b.next;
         hipLaunchKernelGGL(k_ilu_apply<float>, dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
-                           (const float*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev);
+                           (const float*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
     } else {
         const size_t sh = sizeof(double) * b.next;
         hipLaunchKernelGGL(k_ilu_apply<double>, dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
-                           (const double*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev);
+                           (const double*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
     }
     return hipGetLastError();
 }

@@ -17,6 +17,7 @@
 // Elimination without pivoting is exact here because the symmetric part of the Jacobian
 // is positive definite for the step sizes used (its Fourier symbol at a uniform state is
 // 1/dt + kappa((1-kappa)^2 - gamma + 2c)/2 > 0); a zero pivot is reported.
+#include "device_reduce.h"
 #include "pfc_internal.h"
 
 namespace pfc {
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
 //   backward (half 1): x_I = [S_II^-1 | -Uh(I,I+1..I+3)] y[IW : (I+4)W]    (4W columns)
 template <typename T, int NPL, int DEPTH>
 __global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z, const T* __restrict__ fac,
-                           LuBox b) {
+                           LuBox b, double* __restrict__ sum_part) {
     extern __shared__ unsigned char smem_raw[];
     const int W = b.W, H = b.H, WW = W * W;
     T* y = reinterpret_cast<T*>(smem_raw);          // W*H box vector
@@ -549,10 +550,18 @@ __global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z,
         __syncthreads();
         rotate();
     }
-    // restricted extension: owned cells only
+    // restricted extension: owned cells only (and their sum, for the zero-mean projection)
+    double acc = 0.0;
     for (int e = tid; e < b.ownx * b.owny; e += blockDim.x) {
         const int x = e % b.ownx + b.ov, yy = e / b.ownx + b.ov;
-        z[(long)wrapg(oy + yy, b.ny) * b.nx + wrapg(ox + x, b.nx)] = (double)y[yy * W + x];
+        const double v = (double)y[yy * W + x];
+        z[(long)wrapg(oy + yy, b.ny) * b.nx + wrapg(ox + x, b.nx)] = v;
+        acc += v;
+    }
+    if (sum_part) {
+        __shared__ double red[16];
+        const double sum = block_sum_det(acc, red);
+        if (tid == 0) sum_part[blockIdx.x] = sum;
     }
 }
 
@@ -575,7 +584,7 @@ LuBox make_lubox(const pfc_ctx* c, const StencilTable& st) {
 //   W <= 32: 256 threads, G >= 8  -> NPL 16, prefetch 2 rows (FP32) / 1 row (FP64)
 //   W <= 72: 1024 threads, G >= 14 -> NPL 21, prefetch 1 row (FP32) / none (FP64)
 template <typename T>
-hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b) {
+hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b, double* sum_part) {
     constexpr bool f32 = sizeof(T) == 4;
     const int threads = b.W <= 32 ? 256 : 1024;
     const int G = threads / b.W;
@@ -583,9 +592,9 @@ hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b
     const T* f = (const T*)c->d_fac;
     const dim3 grid(c->dec.nsub), blk(threads);
     if (b.W <= 32)
-        hipLaunchKernelGGL((k_lu_apply<T, 16, f32 ? 2 : 1>), grid, blk, sh, c->stream, r, z, f, b);
+        hipLaunchKernelGGL((k_lu_apply<T, 16, f32 ? 2 : 1>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
     else
-        hipLaunchKernelGGL((k_lu_apply<T, 21, f32 ? 1 : 0>), grid, blk, sh, c->stream, r, z, f, b);
+        hipLaunchKernelGGL((k_lu_apply<T, 21, f32 ? 1 : 0>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
     return hipGetLastError();
 }
 
@@ -629,10 +638,10 @@ hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& st) {
     return hipGetLastError();
 }
 
-hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z) {
+hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {
     const LuBox b = make_lubox(c, c->st);
-    if (c->opts.precond_fp32) return launch_apply_t<float>(c, r, z, b);
-    return launch_apply_t<double>(c, r, z, b);
+    if (c->opts.precond_fp32) return launch_apply_t<float>(c, r, z, b, sum_part);
+    return launch_apply_t<double>(c, r, z, b, sum_part);
 }
 
 hipError_t set_lu_lds_limits() {

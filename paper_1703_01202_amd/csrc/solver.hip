@@ -14,9 +14,6 @@
 
 namespace pfc {
 int residual_partial_count(const pfc_ctx* c);
-int energy_partial_count(const pfc_ctx* c);
-hipError_t launch_reduce_rows_n(hipStream_t s, const double* partials, int rows, int count, double* out,
-                                double scale);
 void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<int>* lptr,
                         std::vector<int>* lpts, std::vector<int8_t>* pair);
 hipError_t set_ilu_lds_limits();
@@ -30,14 +27,29 @@ using namespace pfc;
 
 namespace {
 
-constexpr int kScal = 256;      // device scalar slots
-// slots in d_scal
-constexpr int SC_NORM = 0;      // norm^2 / generic reduction result
-constexpr int SC_MEAN = 1;      // mean for projections
+// d_scal: scalar slots, then (from SC_P) partials that the host sums after one copy
+constexpr int kScal = 320;
 constexpr int SC_H = 8;         // first Gram-Schmidt coefficients (64)
 constexpr int SC_H2 = 80;       // second pass coefficients (64)
 constexpr int SC_Y = 160;       // update coefficients (64)
-constexpr int SC_E = 240;       // energy, mass
+constexpr int SC_SHIFT = 240;   // shift of the update
+constexpr int SC_M = 256;       // means of the preconditioned vectors z_j (64)
+constexpr int SC_P = kScal;     // host-summed partials (norms, residual, energy)
+
+// d_part: partials summed by the next kernel on the device
+//   [0, 64 R)        first Gram-Schmidt pass, row j = partials of v_j . w  (R = kRedBlocks)
+//   [64 R, 128 R)    second pass
+//   [128 R, ...)     row j (nsub partials) = per-subdomain sums of z_j, j < 64
+inline double* part_md1(pfc_ctx* c) { return c->d_part; }
+inline double* part_md2(pfc_ctx* c) { return c->d_part + 64L * kRedBlocks; }
+inline double* part_apply(pfc_ctx* c, int j) { return c->d_part + 128L * kRedBlocks + (long)j * c->dec.nsub; }
+
+// Sum of np partials copied back to h_pin[SC_P ...], in index order.
+double host_sum(const pfc_ctx* c, int off, int np) {
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += c->h_pin[SC_P + off + i];
+    return s;
+}
 
 #define HIPCHK(expr)                                                                     \
     do {                                                                                 \
@@ -103,19 +115,20 @@ pfc_status sync(pfc_ctx* c) {
 
 // Euclidean norm of a device vector (synchronises).
 pfc_status norm2(pfc_ctx* c, const double* x, double* out) {
-    HIPCHK(launch_dot_partials(c->stream, x, x, c->g.N, c->d_part));
-    HIPCHK(launch_reduce_rows(c->stream, c->d_part, 1, c->d_scal + SC_NORM, 1.0));
-    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + SC_NORM, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(launch_dot(c->stream, x, x, c->g.N, c->d_scal + SC_P));
+    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, c->d_scal + SC_P, sizeof(double) * kRedBlocks, hipMemcpyDeviceToHost,
+                          c->stream));
     CHK(sync(c));
-    *out = std::sqrt(c->h_pin[0]);
+    *out = std::sqrt(host_sum(c, 0, kRedBlocks));
     if (!std::isfinite(*out)) return fail(c, PFC_ENAN, "non-finite norm");
     return PFC_OK;
 }
 
-// mean of x into d_scal[SC_MEAN] (device only)
-pfc_status mean_to_device(pfc_ctx* c, const double* x) {
-    HIPCHK(launch_sum_partials(c->stream, x, c->g.N, c->d_part));
-    HIPCHK(launch_reduce_rows(c->stream, c->d_part, 1, c->d_scal + SC_MEAN, 1.0 / (double)c->g.N));
+// x += scale * sum(y) with the sum formed on the device (no synchronisation)
+pfc_status shift_by_sum(pfc_ctx* c, double* x, const double* y, double scale) {
+    double* part = part_md1(c);
+    HIPCHK(launch_dot(c->stream, y, nullptr, c->g.N, part));
+    HIPCHK(launch_shift(c->stream, x, part, kRedBlocks, scale, c->g.N));
     return PFC_OK;
 }
 
@@ -123,21 +136,24 @@ pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, doubl
                          double* F, double* nrm) {
     int ts;
     timer_begin(c, 1, &ts);
-    HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_part : nullptr));
+    HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_scal + SC_P : nullptr));
     timer_end(c, ts);
     if (!nrm) return PFC_OK;
-    HIPCHK(launch_reduce_rows_n(c->stream, c->d_part, 1, residual_partial_count(c), c->d_scal + SC_NORM, 1.0));
-    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + SC_NORM, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    const int np = residual_partial_count(c);
+    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, c->d_scal + SC_P, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream));
     CHK(sync(c));
-    *nrm = std::sqrt(c->h_pin[0]);
+    *nrm = std::sqrt(host_sum(c, 0, np));
     if (!std::isfinite(*nrm)) return fail(c, PFC_ENAN, "non-finite residual norm");
     return PFC_OK;
 }
 
-pfc_status jv_impl(pfc_ctx* c, const double* v, double dt, const double* vshift, double* out) {
+// out = J (v - s) with s = mean of v formed from the apply's per-subdomain sums in
+// shift_part (nullable), stored in *shift_out.
+pfc_status jv_impl(pfc_ctx* c, const double* v, double dt, const double* shift_part, double* shift_out,
+                   double* out) {
     int ts;
     timer_begin(c, 2, &ts);
-    HIPCHK(launch_jv(c, v, c->d_c, dt, vshift, out));
+    HIPCHK(launch_jv(c, v, c->d_c, dt, shift_part, c->dec.nsub, 1.0 / (double)c->g.N, shift_out, out));
     timer_end(c, ts);
     return PFC_OK;
 }
@@ -178,18 +194,22 @@ bool may_reuse_factors(const pfc_ctx* c, double dt) {
     return c->last_gpn <= 2.0 * c->fac_gpn + 1.0;
 }
 
-pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
+// z = H^-1 r; with sum_part the apply kernel also leaves one partial sum of z per subdomain.
+pfc_status apply_raw(pfc_ctx* c, const double* r, double* z, double* sum_part) {
     int ts;
     timer_begin(c, 0, &ts);
     if (c->opts.sub_solver == PFC_SUB_LU)
-        HIPCHK(launch_lu_apply(c, r, z));
+        HIPCHK(launch_lu_apply(c, r, z, sum_part));
     else
-        HIPCHK(launch_ilu_apply(c, r, z));
+        HIPCHK(launch_ilu_apply(c, r, z, sum_part));
     timer_end(c, ts);
-    if (c->opts.mass_project) {
-        CHK(mean_to_device(c, z));
-        HIPCHK(launch_shift(c->stream, z, c->d_scal + SC_MEAN, -1.0, c->g.N));
-    }
+    return PFC_OK;
+}
+
+pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
+    const bool proj = c->opts.mass_project;
+    CHK(apply_raw(c, r, z, proj ? part_apply(c, 0) : nullptr));
+    if (proj) HIPCHK(launch_shift(c->stream, z, part_apply(c, 0), c->dec.nsub, -1.0 / (double)c->g.N, c->g.N));
     return PFC_OK;
 }
 
@@ -200,6 +220,7 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
     const long N = c->g.N;
     const int m = c->opts.gmres_restart;
     const int maxit = c->opts.gmres_maxit;
+    const bool proj = c->opts.mass_project;
     double bnorm;
     CHK(norm2(c, b, &bnorm));
     const double target = std::max(rtol * bnorm, atol);
@@ -207,7 +228,7 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
     *its = 0;
     *res_out = bnorm;
     if (bnorm <= target) return PFC_OK;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(SC_SHIFT - SC_Y + 1, 0.0);
     double* V = c->d_V;
     double* Z = c->d_Z;
     double beta = bnorm;
@@ -218,7 +239,7 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
         if (first) {
             HIPCHK(launch_scale(c->stream, b, 1.0 / beta, V, N));
         } else {
-            CHK(jv_impl(c, x, dt, nullptr, c->d_r));
+            CHK(jv_impl(c, x, dt, nullptr, nullptr, c->d_r));
             HIPCHK(launch_axpby(c->stream, 1.0, b, -1.0, c->d_r, c->d_r, N));
             CHK(norm2(c, c->d_r, &beta));
             if (beta <= target) {
@@ -235,19 +256,22 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
         for (int j = 0; j < m; ++j) {
             double* zj = Z + (long)j * N;
             double* w = V + (long)(j + 1) * N;
-            CHK(apply_impl(c, V + (long)j * N, zj));
-            CHK(jv_impl(c, zj, dt, nullptr, w));
+            // z_j = H^-1 v_j, kept unprojected; its mean m_j is removed on the fly (Jv load
+            // shift, and once from the update), which is the zero-mean projection of R12
+            double* pj = proj ? part_apply(c, j) : nullptr;
+            CHK(apply_raw(c, V + (long)j * N, zj, pj));
+            CHK(jv_impl(c, zj, dt, pj, c->d_scal + SC_M + j, w));
             // CGS2: h = V^T w ; w -= V h ; h2 = V^T w ; w -= V h2 (norm fused)
-            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, c->d_part));
-            HIPCHK(launch_reduce_rows(c->stream, c->d_part, j + 1, c->d_scal + SC_H, 1.0));
-            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, c->d_scal + SC_H, -1.0, w, N, nullptr));
-            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, c->d_part));
-            HIPCHK(launch_reduce_rows(c->stream, c->d_part, j + 1, c->d_scal + SC_H2, 1.0));
-            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, c->d_scal + SC_H2, -1.0, w, N, c->d_part));
-            HIPCHK(launch_reduce_rows(c->stream, c->d_part, 1, c->d_scal + SC_NORM, 1.0));
-            HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md1(c)));
+            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, nullptr,
+                                c->d_scal + SC_H));
+            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md2(c)));
+            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_scal + SC_P,
+                                c->d_scal + SC_H2));
+            HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal, sizeof(double) * (SC_P + kRedBlocks), hipMemcpyDeviceToHost,
+                                  c->stream));
             CHK(sync(c));
-            const double hn = std::sqrt(c->h_pin[SC_NORM]);
+            const double hn = std::sqrt(host_sum(c, 0, kRedBlocks));
             if (!std::isfinite(hn)) return fail(c, PFC_ENAN, "non-finite Arnoldi norm");
             for (int i = 0; i <= j; ++i) H[i * m + j] = c->h_pin[SC_H + i] + c->h_pin[SC_H2 + i];
             H[(j + 1) * m + j] = hn;
@@ -279,9 +303,15 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
             for (int k = i + 1; k < jdone; ++k) s -= H[i * m + k] * y[k];
             y[i] = s / H[i * m + i];
         }
-        HIPCHK(hipMemcpyAsync(c->d_scal + SC_Y, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice,
-                              c->stream));
-        HIPCHK(launch_maxpy(c->stream, Z, N, jdone, c->d_scal + SC_Y, 1.0, x, N, nullptr));
+        // x += sum_j y_j (z_j - m_j); the m_j came back with the last Hessenberg column
+        double shift = 0.0;
+        if (proj)
+            for (int i = 0; i < jdone; ++i) shift += y[i] * c->h_pin[SC_M + i];
+        y[SC_SHIFT - SC_Y] = shift;
+        HIPCHK(hipMemcpyAsync(c->d_scal + SC_Y, y.data(), sizeof(double) * (SC_SHIFT - SC_Y + 1),
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(launch_maxpy(c->stream, Z, N, jdone, c->d_scal + SC_Y, 1, 1.0, x, N, nullptr, nullptr));
+        if (proj) HIPCHK(launch_shift(c->stream, x, c->d_scal + SC_SHIFT, 1, -1.0, N));
         CHK(sync(c));   // y lives in host memory until the copy has run
         if (conv || total >= maxit) break;
     }
@@ -299,12 +329,23 @@ double residual_floor(const pfc_ctx* c, double dt, double xnorm) {
     return 2.220446049250313e-16 * op * xnorm;
 }
 
-pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats* st, bool reuse = false) {
+// ||F(phi^n)||: the residual of the paper's initial guess Phi_0 = phi^n, the reference of the
+// relative Newton test when opts.newton_rel_ref is set (uses d_r as scratch).
+pfc_status reference_norm(pfc_ctx* c, const double* phi, double dt, double* out) {
+    return residual_impl(c, phi, phi, dt, nullptr, c->d_r, out);
+}
+
+// Newton from the iterate in d_X.  The stop test of Eq. (20) is
+// ||F|| <= max(eps_r * fref, eps_a, rounding floor) with fref = ||F(Phi_0)|| unless a
+// reference fref >= 0 is given.
+pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats* st, bool reuse = false,
+                       double fref = -1.0) {
     const long N = c->g.N;
     double fn, xnorm;
     CHK(residual_impl(c, c->d_X, phi, dt, nullptr, c->d_F, &fn));
     CHK(norm2(c, c->d_X, &xnorm));
-    const double target = std::max({c->opts.newton_rtol * fn, c->opts.newton_atol, residual_floor(c, dt, xnorm)});
+    if (fref < 0.0) fref = fn;
+    const double target = std::max({c->opts.newton_rtol * fref, c->opts.newton_atol, residual_floor(c, dt, xnorm)});
     st->res0 = fn;
     st->newton_its = 0;
     st->gmres_its = 0;
@@ -350,13 +391,13 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
 }
 
 pfc_status energy_impl(pfc_ctx* c, const double* phi, double* e, double* m) {
-    HIPCHK(launch_energy(c, phi, c->d_part));
-    const int np = energy_partial_count(c);
-    HIPCHK(launch_reduce_rows_n(c->stream, c->d_part, 2, np, c->d_scal + SC_E, c->g.cell_volume));
-    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + SC_E, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    const int np = residual_partial_count(c);
+    HIPCHK(launch_energy(c, phi, c->d_scal + SC_P));
+    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, c->d_scal + SC_P, 2 * sizeof(double) * np, hipMemcpyDeviceToHost,
+                          c->stream));
     CHK(sync(c));
-    *e = c->h_pin[0];
-    *m = c->h_pin[1];
+    *e = host_sum(c, 0, np) * c->g.cell_volume;
+    *m = host_sum(c, np, np) * c->g.cell_volume;
     if (!std::isfinite(*e)) return fail(c, PFC_ENAN, "non-finite energy");
     return PFC_OK;
 }
@@ -404,6 +445,8 @@ void pfc_default_opts(pfc_opts* o) {
     o->eta = 0.0;
     o->max_retries = 4;
     o->timing = 0;
+    o->precond_lag = 0;
+    o->newton_rel_ref = 1;
 }
 
 pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* op, void* stream,
@@ -508,8 +551,9 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     A(dalloc(c, &c->d_V, (size_t)(m + 1) * N));
     A(dalloc(c, &c->d_Z, (size_t)m * N));
     if (dim == 3) A(dalloc(c, &c->d_tmp3, 2 * (size_t)N));
-    A(dalloc(c, &c->d_part, (size_t)std::max(64 * kRedBlocks, 2 * residual_partial_count(c)) + 64));
-    A(dalloc(c, &c->d_scal, kScal));
+    A(dalloc(c, &c->d_part, 128 * (size_t)kRedBlocks + 64 * (size_t)c->dec.nsub));
+    c->n_scal = SC_P + std::max(kRedBlocks, 2 * residual_partial_count(c));
+    A(dalloc(c, &c->d_scal, (size_t)c->n_scal));
     A(dalloc(c, &c->d_flag, 1));
     if (op->sub_solver == PFC_SUB_ILU0) {
         std::vector<int> lptr, lpts;
@@ -536,11 +580,12 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (s == PFC_OK) {
         if (hipMalloc(&c->d_fac, esz * c->fac_elems) != hipSuccess) s = fail(c, PFC_ENOMEM, "factor allocation failed");
     }
-    if (s == PFC_OK && hipHostMalloc((void**)&c->h_pin, sizeof(double) * kScal) != hipSuccess)
+    if (s == PFC_OK && hipHostMalloc((void**)&c->h_pin, sizeof(double) * c->n_scal) != hipSuccess)
         s = fail(c, PFC_ENOMEM, "pinned allocation failed");
     if (s == PFC_OK && (set_ilu_lds_limits() != hipSuccess || set_lu_lds_limits() != hipSuccess))
         s = fail(c, PFC_EHIP, "cannot raise the LDS limit");
-    if (s == PFC_OK && hipMemset(c->d_scal, 0, sizeof(double) * kScal) != hipSuccess) s = fail(c, PFC_EHIP, "memset");
+    if (s == PFC_OK && hipMemset(c->d_scal, 0, sizeof(double) * c->n_scal) != hipSuccess)
+        s = fail(c, PFC_EHIP, "memset");
     if (s != PFC_OK) {
         std::fprintf(stderr, "pfc_create: %s\n", c->err.c_str());
         free_all(c);
@@ -569,7 +614,7 @@ pfc_status pfc_residual(pfc_ctx* c, const double* Phi, const double* phi, double
 pfc_status pfc_jv(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* v, double* Jv) {
     if (!c || !Phi || !phi || !v || !Jv || !(dt > 0)) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
     HIPCHK(launch_coef(c, Phi, phi, c->d_c));
-    return jv_impl(c, v, dt, nullptr, Jv);
+    return jv_impl(c, v, dt, nullptr, nullptr, Jv);
 }
 
 pfc_status pfc_ras_setup(pfc_ctx* c, const double* Phi, const double* phi, double dt) {
@@ -599,8 +644,10 @@ pfc_status pfc_gmres(pfc_ctx* c, const double* Phi, const double* phi, double dt
 pfc_status pfc_newton(pfc_ctx* c, const double* phi, double dt, double* Phi, pfc_step_stats* st) {
     if (!c || !phi || !Phi || !st || !(dt > 0)) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
     std::memset(st, 0, sizeof(*st));
+    double fref = -1.0;
+    if (c->opts.newton_rel_ref) CHK(reference_norm(c, phi, dt, &fref));
     HIPCHK(hipMemcpyAsync(c->d_X, Phi, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
-    pfc_status s = newton_impl(c, phi, dt, st);
+    pfc_status s = newton_impl(c, phi, dt, st, false, fref);
     HIPCHK(hipMemcpyAsync(Phi, c->d_X, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     st->dt = dt;
@@ -630,8 +677,7 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
             HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
             if (o.mass_project) {   // restore the mass of phi^n exactly: X += mean(phi - X)
                 HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
-                CHK(mean_to_device(c, c->d_w));
-                HIPCHK(launch_shift(c->stream, c->d_X, c->d_scal + SC_MEAN, 1.0, N));
+                CHK(shift_by_sum(c, c->d_X, c->d_w, 1.0 / (double)N));
             }
             used = PFC_GUESS_EXTRAP;
         } else {
@@ -639,9 +685,11 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
         }
         pfc_step_stats tmp;
         std::memset(&tmp, 0, sizeof(tmp));
+        double fref = -1.0;
+        if (o.newton_rel_ref && used != PFC_GUESS_PREVIOUS) CHK(reference_norm(c, phi, dt, &fref));
         const bool reuse = may_reuse_factors(c, dt);
         const long fac_before = c->fac_step;
-        s = newton_impl(c, phi, dt, &tmp, reuse);
+        s = newton_impl(c, phi, dt, &tmp, reuse, fref);
         if (s != PFC_OK && reuse && (s == PFC_ENOTCONV || s == PFC_EKRYLOV)) {
             // lagged factors did not do: same dt, fresh factors
             st->newton_its += tmp.newton_its;
@@ -650,15 +698,14 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
                 HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
                 if (o.mass_project) {
                     HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
-                    CHK(mean_to_device(c, c->d_w));
-                    HIPCHK(launch_shift(c->stream, c->d_X, c->d_scal + SC_MEAN, 1.0, N));
+                    CHK(shift_by_sum(c, c->d_X, c->d_w, 1.0 / (double)N));
                 }
             } else {
                 HIPCHK(hipMemcpyAsync(c->d_X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
             }
             std::memset(&tmp, 0, sizeof(tmp));
             c->fac_valid = false;
-            s = newton_impl(c, phi, dt, &tmp, false);
+            s = newton_impl(c, phi, dt, &tmp, false, fref);
         }
         if (s == PFC_OK && tmp.newton_its > 0) {
             const double gpn = (double)tmp.gmres_its / tmp.newton_its;

@@ -7,13 +7,17 @@
 // successive five-point Laplacians inside LDS (halo 3 -> 2 -> 1 -> 0), so each
 // field is read from HBM once and the result written once.
 // 3-D: three seven-point passes through global memory (L2-resident neighbours).
+#include "device_reduce.h"
 #include "pfc_internal.h"
 
 namespace pfc {
 namespace {
 
+#ifndef PFC_STENCIL_TILE_Y
+#define PFC_STENCIL_TILE_Y 16
+#endif
 constexpr int TX = 64;
-constexpr int TY = 16;
+constexpr int TY = PFC_STENCIL_TILE_Y;   // 64 x 16 outputs measured fastest (occupancy beats halo reuse)
 constexpr int NT = 256;
 
 struct P {
@@ -27,17 +31,9 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-// Deterministic block sum (fixed shuffle tree, then the waves in order); result in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-    return s;
+// Periodic index for i in [-n, 2n): one compare and add instead of a division.
+__device__ __forceinline__ int wrap1(int i, int n) {
+    return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
 #define LAP2(A, y, x)                                                     \
@@ -53,20 +49,20 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
     __shared__ double su[TY + 6][TX + 6];     // u = (Phi + phi)/2, halo 3
     __shared__ double sl[TY + 4][TX + 4];     // Delta_d u, halo 2
     __shared__ double sm[TY + 2][TX + 2];     // cubic term q, then mu_d, halo 1
-    __shared__ double sd[TY][TX];             // Phi - phi
     __shared__ double red[NT / 64];
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    const bool big = p.nx >= TX + 6 && p.ny >= TY + 6;   // one wrap step suffices
 
     for (int e = tid; e < (TY + 6) * (TX + 6); e += NT) {
         const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
-        const long gi = (long)wrap(y0 + ly - 3, p.ny) * p.nx + wrap(x0 + lx - 3, p.nx);
+        const int gy = big ? wrap1(y0 + ly - 3, p.ny) : wrap(y0 + ly - 3, p.ny);
+        const int gx = big ? wrap1(x0 + lx - 3, p.nx) : wrap(x0 + lx - 3, p.nx);
+        const long gi = (long)gy * p.nx + gx;
         const double a = Phi[gi], b = phi[gi];
         su[ly][lx] = 0.5 * (a + b);
         const int qy = ly - 2, qx = lx - 2;
         if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2)
             sm[qy][qx] = 0.25 * (a * a * a + a * a * b + a * b * b + b * b * b);
-        const int dy = ly - 3, dx = lx - 3;
-        if (dy >= 0 && dy < TY && dx >= 0 && dx < TX) sd[dy][dx] = a - b;
     }
     __syncthreads();
     for (int e = tid; e < (TY + 4) * (TX + 4); e += NT) {
@@ -87,33 +83,44 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
         const double lm = LAP2(sm, ly + 1, lx + 1);
         if (gx < p.nx && gy < p.ny) {
             const long gi = (long)gy * p.nx + gx;
-            double f = sd[ly][lx] * p.inv_dt - lm;
+            double f = (Phi[gi] - phi[gi]) * p.inv_dt - lm;     // re-read: these lines are in L2
             if (src) f -= src[gi];
             F[gi] = f;
             acc += f * f;
         }
     }
     if (part) {
-        const double s = block_sum(acc, red);
+        const double s = block_sum_det(acc, red);
         if (tid == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
     }
 }
 
-// Jv = v/dt - Delta_d[(1-gamma)/2 v + Delta_d v + 1/2 Delta_d^2 v + c v], v shifted by
-// -(*vshift) when vshift is given (zero-mean projection fused into the load).
+// Jv = v/dt - Delta_d[(1-gamma)/2 v + Delta_d v + 1/2 Delta_d^2 v + c v] with v shifted by
+// -s, s = shift_scale * sum(shift_part[0..shift_n)) when shift_part is given (zero-mean
+// projection fused into the load; every block forms s in the same order and block 0
+// stores it in *shift_out).
 __global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
                                              const double* __restrict__ cc,
-                                             const double* __restrict__ vshift,
+                                             const double* __restrict__ shift_part, int shift_n,
+                                             double shift_scale, double* __restrict__ shift_out,
                                              double* __restrict__ Jv, P p) {
     __shared__ double sv[TY + 6][TX + 6];
     __shared__ double sl[TY + 4][TX + 4];
     __shared__ double sn[TY + 2][TX + 2];     // c, then the inner operator, halo 1
+    __shared__ double red[NT / 64];
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
-    const double sh = vshift ? *vshift : 0.0;
+    double sh = 0.0;
+    if (shift_part) {
+        sh = shift_scale * sum_partials_bcast(shift_part, shift_n, red);
+        if (shift_out && tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) *shift_out = sh;
+    }
+    const bool big = p.nx >= TX + 6 && p.ny >= TY + 6;
 
     for (int e = tid; e < (TY + 6) * (TX + 6); e += NT) {
         const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
-        const long gi = (long)wrap(y0 + ly - 3, p.ny) * p.nx + wrap(x0 + lx - 3, p.nx);
+        const int gy = big ? wrap1(y0 + ly - 3, p.ny) : wrap(y0 + ly - 3, p.ny);
+        const int gx = big ? wrap1(x0 + lx - 3, p.nx) : wrap(x0 + lx - 3, p.nx);
+        const long gi = (long)gy * p.nx + gx;
         sv[ly][lx] = v[gi] - sh;
         const int qy = ly - 2, qx = lx - 2;
         if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2) sn[qy][qx] = cc[gi];
@@ -164,9 +171,9 @@ __global__ __launch_bounds__(NT) void k_energy2d(const double* __restrict__ phi,
         }
     }
     const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
-    const double sg = block_sum(eg, red);
+    const double sg = block_sum_det(eg, red);
     if (tid == 0) part[b] = sg;
-    const double sm = block_sum(em, red);
+    const double sm = block_sum_det(em, red);
     if (tid == 0) part[nb + b] = sm;
 }
 
@@ -197,11 +204,18 @@ __device__ __forceinline__ double lap7(const double* __restrict__ a, int x, int 
     if (x >= p.nx || y >= p.ny) return;                                  \
     const long i = ((long)z * p.ny + y) * p.nx + x;
 
-// out = (a + b)/2 (mode 0) or a - shift (mode 1)
-__global__ void k_mp_combine(const double* __restrict__ a, const double* __restrict__ b,
-                             const double* __restrict__ shift, int mode, double* __restrict__ out,
-                             long n) {
-    const double sh = shift ? *shift : 0.0;
+// out = (a + b)/2 (mode 0) or a - s (mode 1), s = shift_scale * sum(shift_part[0..shift_n))
+// (s = 0 without shift_part; block 0 stores s in *shift_out)
+__global__ __launch_bounds__(256) void k_mp_combine(const double* __restrict__ a, const double* __restrict__ b,
+                                                    const double* __restrict__ shift_part, int shift_n,
+                                                    double shift_scale, double* __restrict__ shift_out, int mode,
+                                                    double* __restrict__ out, long n) {
+    __shared__ double red[4];
+    double sh = 0.0;
+    if (shift_part) {
+        sh = shift_scale * sum_partials_bcast(shift_part, shift_n, red);
+        if (shift_out && threadIdx.x == 0 && blockIdx.x == 0) *shift_out = sh;
+    }
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
         out[i] = mode == 0 ? 0.5 * (a[i] + b[i]) : a[i] - sh;
 }
@@ -262,9 +276,9 @@ __global__ __launch_bounds__(NT) void k_mp_energy(const double* __restrict__ phi
         eg += 0.5 * (1.0 - p.gamma) * f * f + 0.25 * f * f * f * f + 0.5 * lap * lap - 0.5 * grad;
         em += f;
     }
-    const double sg = block_sum(eg, red);
+    const double sg = block_sum_det(eg, red);
     if (threadIdx.x == 0) part[blockIdx.x] = sg;
-    const double sm = block_sum(em, red);
+    const double sm = block_sum_det(em, red);
     if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = sm;
 }
 
@@ -273,7 +287,7 @@ __global__ __launch_bounds__(NT) void k_sumsq(const double* __restrict__ x, long
     __shared__ double red[NT / 64];
     double acc = 0.0;
     for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) acc += x[i] * x[i];
-    const double s = block_sum(acc, red);
+    const double s = block_sum_det(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -311,24 +325,23 @@ int residual_partial_count(const pfc_ctx* c) {
     return kRedBlocks;
 }
 
-int energy_partial_count(const pfc_ctx* c) { return residual_partial_count(c); }
-
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
-                           const double* src, double* F, double* partials) {
+                           const double* src, double* F, double* norm_part) {
     const P p = make_params(c, dt);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_residual2d, tiles2d(c), dim3(NT), 0, c->stream, Phi, phi, src, F, partials, p);
+        hipLaunchKernelGGL(k_residual2d, tiles2d(c), dim3(NT), 0, c->stream, Phi, phi, src, F, norm_part, p);
         return hipGetLastError();
     }
     double* u = c->d_tmp3;
     double* Lu = c->d_tmp3 + c->g.N;
-    hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, Phi, phi, nullptr, 0, u, c->g.N);
+    hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, Phi, phi, nullptr, 0, 0.0, nullptr, 0, u,
+                       c->g.N);
     hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, u, Lu, p);
     // mu overwrites u only after every Lu neighbour is read: use F as the mu buffer
     hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, Lu, nullptr, 0, F, p);
     hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, F, src, 0, u, p);
     hipMemcpyAsync(F, u, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream);
-    if (partials) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, F, c->g.N, partials);
+    if (norm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, F, c->g.N, norm_part);
     return hipGetLastError();
 }
 
@@ -337,16 +350,18 @@ hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, d
     return hipGetLastError();
 }
 
-hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt,
-                     const double* vshift, double* Jv) {
+hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt, const double* shift_part,
+                     int shift_n, double shift_scale, double* shift_out, double* Jv) {
     const P p = make_params(c, dt);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_jv2d, tiles2d(c), dim3(NT), 0, c->stream, v, cbuf, vshift, Jv, p);
+        hipLaunchKernelGGL(k_jv2d, tiles2d(c), dim3(NT), 0, c->stream, v, cbuf, shift_part, shift_n, shift_scale,
+                           shift_out, Jv, p);
         return hipGetLastError();
     }
     double* u = c->d_tmp3;
     double* Lu = c->d_tmp3 + c->g.N;
-    hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, v, nullptr, vshift, 1, u, c->g.N);
+    hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, v, nullptr, shift_part, shift_n,
+                       shift_scale, shift_out, 1, u, c->g.N);
     hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, u, Lu, p);
     hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, nullptr, nullptr, u, Lu, cbuf, 1, Jv, p);
     hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, u, nullptr, Jv, nullptr, 1, Lu, p);
@@ -354,12 +369,12 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
     return hipGetLastError();
 }
 
-hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* partials) {
+hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2) {
     const P p = make_params(c, 0.0);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_energy2d, tiles2d(c), dim3(NT), 0, c->stream, phi, partials, p);
+        hipLaunchKernelGGL(k_energy2d, tiles2d(c), dim3(NT), 0, c->stream, phi, part2, p);
     } else {
-        hipLaunchKernelGGL(k_mp_energy, dim3(kRedBlocks), dim3(NT), 0, c->stream, phi, partials, p);
+        hipLaunchKernelGGL(k_mp_energy, dim3(kRedBlocks), dim3(NT), 0, c->stream, phi, part2, p);
     }
     return hipGetLastError();
 }

@@ -88,3 +88,25 @@ def test_default_opts_match_paper_tolerances(lib):
     # Sec. 5: eps_r = 1e-8, eps_a = 1e-10, xi_r = 1e-3, xi_a = 1e-11
     assert (o.newton_rtol, o.newton_atol, o.lin_rtol, o.lin_atol) == (1e-8, 1e-10, 1e-3, 1e-11)
     assert o.gmres_restart == 30 and o.mass_project == 1
+    assert o.precond_lag == 0 and o.newton_rel_ref == 1
+
+
+def test_opts_struct_size_matches_header():
+    # the ctypes mirror must have the C layout: compile a probe of sizeof/offsetof with gcc
+    import os
+    import subprocess
+    import tempfile
+    from paper_1703_01202_amd import _lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "pfc.h"\n'
+           'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(pfc_opts), offsetof(pfc_opts, newton_rel_ref),'
+           ' sizeof(pfc_step_stats), sizeof(pfc_grid)); return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        cpath, exe = os.path.join(d, "p.c"), os.path.join(d, "p")
+        open(cpath, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(root, "include"), cpath, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(_lib.PfcOpts)
+    assert int(out[1]) == _lib.PfcOpts.newton_rel_ref.offset
+    assert int(out[2]) == ctypes.sizeof(_lib.PfcStepStats)
+    assert int(out[3]) == ctypes.sizeof(_lib.PfcGrid)

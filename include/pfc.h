@@ -99,9 +99,12 @@ typedef struct {
                                          target; 0: ||F|| at the guess actually used */
 } pfc_opts;
 
+/* Per-step statistics.  res0 = ||F|| at the initial guess, res_final at the accepted
+ * iterate, res_ref = ||F(phi^n)|| (the reference of the relative test; equals res0 for the
+ * previous-step guess). */
 typedef struct {
     int newton_its, gmres_its, ls_cuts, rejected, guess_used;
-    double dt, t, energy, mass, res0, res_final;
+    double dt, t, energy, mass, res0, res_final, res_ref;
 } pfc_step_stats;
 
 typedef struct pfc_ctx pfc_ctx;

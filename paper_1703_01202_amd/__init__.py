@@ -13,7 +13,7 @@ import ctypes
 from . import _lib
 from ._lib import PfcError, PfcStepStats
 
-__all__ = ["Solver", "PfcError", "PfcStepStats", "load"]
+__all__ = ["Solver", "GuessNet", "PfcError", "PfcStepStats", "load"]
 
 load = _lib.load
 
@@ -158,7 +158,95 @@ class Solver:
     def reset(self):
         self._check(self.lib.pfc_reset(self.ctx))
 
+    def attach_net(self, net, scales, dt_train):
+        """Use ``net`` (a GuessNet) for ``guess="learned"``; scales = (s_a, s_b, s_o)."""
+        sc = (ctypes.c_double * 3)(*[float(v) for v in scales])
+        self._check(self.lib.pfc_attach_net(self.ctx, net.handle if net is not None else None, sc, float(dt_train)))
+        self._net = net          # the context keeps the pointer: keep the object alive
+
     def kernel_time(self, which):
         cnt, ms = ctypes.c_long(0), ctypes.c_double(0.0)
         self._check(self.lib.pfc_kernel_time(self.ctx, int(which), ctypes.byref(cnt), ctypes.byref(ms)))
         return cnt.value, ms.value
+
+
+class GuessNet:
+    """The learned-guess network of ``include/pfc_net.h`` (a ``pfc_net`` handle).
+
+    Inputs are float32 CUDA tensors of shape (2, ny, nx), outputs (ny, nx); parameters
+    are a float32 numpy vector of ``GuessNet.NPARAM`` numbers (layout in the header).
+    """
+    NPARAM = _lib.NET_NPARAM
+
+    def __init__(self, params=None, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = _lib.load()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        st = self.lib.pfc_net_create(ctypes.c_void_p(stream), ctypes.byref(h))
+        if st != _lib.PFC_OK:
+            raise PfcError(st, "pfc_net_create failed")
+        self.handle = h
+        if params is not None:
+            self.set_params(params)
+
+    def _check(self, status):
+        if status != _lib.PFC_OK:
+            raise PfcError(status, self.lib.pfc_net_last_error(self.handle).decode())
+
+    def _plane(self, t, shape, name):
+        torch = self._torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape {tuple(shape)}")
+        return _ptr(t)
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        if p.size != self.NPARAM:
+            raise ValueError(f"expected {self.NPARAM} parameters, got {p.size}")
+        self._check(self.lib.pfc_net_set_params(self.handle, p.ctypes.data_as(_lib.c_float_p)))
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(self.NPARAM, dtype=np.float32)
+        self._check(self.lib.pfc_net_get_params(self.handle, p.ctypes.data_as(_lib.c_float_p)))
+        return p
+
+    def forward(self, x, out=None):
+        ny, nx = x.shape[1:]
+        y = out if out is not None else self._torch.empty((ny, nx), dtype=self._torch.float32, device="cuda")
+        self._check(self.lib.pfc_net_forward(self.handle, self._plane(x, (2, ny, nx), "x"), ny, nx,
+                                             self._plane(y, (ny, nx), "y")))
+        return y
+
+    def gradient(self, x, t, scale=1.0, accumulate=False, want_loss=True):
+        ny, nx = x.shape[1:]
+        loss = ctypes.c_double(0.0)
+        self._check(self.lib.pfc_net_gradient(self.handle, self._plane(x, (2, ny, nx), "x"),
+                                              self._plane(t, (ny, nx), "t"), ny, nx, float(scale),
+                                              int(bool(accumulate)), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def get_gradient(self):
+        import numpy as np
+        g = np.empty(self.NPARAM, dtype=np.float32)
+        self._check(self.lib.pfc_net_get_gradient(self.handle, g.ctypes.data_as(_lib.c_float_p)))
+        return g
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.pfc_net_adam(self.handle, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pfc_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

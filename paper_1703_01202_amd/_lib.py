@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpfc.so")
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
+c_float_p = ctypes.POINTER(ctypes.c_float)
 
 PFC_OK = 0
 STATUS = {0: "PFC_OK", -1: "PFC_EINVAL", -2: "PFC_ENOMEM", -3: "PFC_EHIP", -4: "PFC_ENAN",
@@ -49,6 +50,7 @@ class PfcStepStats(ctypes.Structure):
         ("rejected", ctypes.c_int), ("guess_used", ctypes.c_int),
         ("dt", ctypes.c_double), ("t", ctypes.c_double), ("energy", ctypes.c_double),
         ("mass", ctypes.c_double), ("res0", ctypes.c_double), ("res_final", ctypes.c_double),
+        ("res_ref", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -77,7 +79,22 @@ SIGNATURES = {
     "pfc_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PfcStepStats)]),
     "pfc_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "pfc_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_long), c_double_p]),
+    # learned initial guess (include/pfc_net.h)
+    "pfc_net_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pfc_net_destroy": (None, [ctypes.c_void_p]),
+    "pfc_net_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pfc_net_set_params": (ctypes.c_int, [ctypes.c_void_p, c_float_p]),
+    "pfc_net_get_params": (ctypes.c_int, [ctypes.c_void_p, c_float_p]),
+    "pfc_net_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "pfc_net_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_int, c_double_p]),
+    "pfc_net_get_gradient": (ctypes.c_int, [ctypes.c_void_p, c_float_p]),
+    "pfc_net_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double]),
+    "pfc_attach_net": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, ctypes.c_double]),
 }
+
+NET_NPARAM = 19393
 
 _lib = None
 

@@ -1,0 +1,682 @@
+// Learned Newton initial guess: a four-layer 3x3 periodic convolutional network with
+// hand-written forward, backward and Adam kernels for gfx950 (C ABI in include/pfc_net.h).
+//
+// Layouts
+//   input x      planar FP32 [2][HW]
+//   activations  FP32 in groups of four channels, [8][HW][4] (one 16-byte load gives the
+//                four channels of a cell; 32 consecutive cells of a group are 512 bytes)
+//   output y     FP32 [HW]
+// The two 32 -> 32 layers are a dense contraction (K = 9 taps x 32 channels = 288) and run
+// on the matrix cores: v_mfma_f32_32x32x8 bf16 with the 32 output channels as M, 32
+// consecutive cells as N and (tap, input channel) as K.  Each FP32 activation is split
+// into hi = bf16(a) and lo = bf16(a - hi) and both parts are multiplied by the bf16 weight,
+// so the products carry ~16 significant bits of the activation and accumulate in FP32.
+// The thin first (2 -> 32) and last (32 -> 1) layers and the weight gradients use FP32 FMA.
+// Reductions (loss, weight gradients) leave per-block partials summed in a fixed order.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/pfc_net.h"
+#include "device_reduce.h"
+#include "pfc_internal.h"
+
+namespace pfc {
+namespace {
+
+constexpr int CIN = PFC_NET_CIN, WID = PFC_NET_WIDTH, NG = WID / 4;
+constexpr int OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 608, OFF_B2 = 9824, OFF_W3 = 9856, OFF_B3 = 19072,
+              OFF_W4 = 19104, OFF_B4 = 19392;
+constexpr int NPARAM = PFC_NET_NPARAM;
+static_assert(OFF_B4 + 1 == NPARAM, "parameter layout");
+constexpr int KSTEPS = 36;                 // 9 taps x 4 pairs of channel groups (8 channels per step)
+constexpr int PACK = KSTEPS * 64;          // packed A operands (4 bf16 each) per layer and direction
+constexpr int WG_BLOCKS = 256;             // fixed grid of the weight-gradient kernels
+constexpr int WG_MAXOUT = WID * WID * 9 + WID;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest, ties to even
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+__device__ __forceinline__ int wrapm(int i, int n) { return ((i % n) + n) % n; }
+
+__device__ __forceinline__ bool is_weight_index(int i) {
+    return i < OFF_B1 || (i >= OFF_W2 && i < OFF_B2) || (i >= OFF_W3 && i < OFF_B3) || (i >= OFF_W4 && i < OFF_B4);
+}
+
+// q = parameters with the convolution weights rounded to bf16; pack = matrix-core A operands
+// of the inner layers: set 0/1 layer 2 forward/backward, set 2/3 layer 3.  Entry
+// [set][s][lane][j], step s = tap * 4 + pair, row m = lane % 32, k = 8 pair + 4 (lane / 32) + j:
+//   forward  A[m = out ch][k = in ch] = W[m][k][tap]
+//   backward A[m = in ch][k = out ch] = W[k][m][8 - tap]  (adjoint: swap channels, mirror taps)
+__global__ void k_prepare(const float* __restrict__ theta, float* __restrict__ q, unsigned short* __restrict__ pack) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NPARAM) q[i] = is_weight_index(i) ? bf2f(f2bf(theta[i])) : theta[i];
+    if (i < 4 * PACK * 4) {
+        const int set = i / (PACK * 4), r = i % (PACK * 4);
+        const int s = r / 256, lane = (r / 4) % 64, j = r % 4;
+        const int tap = s / 4, pair = s % 4;
+        const int m = lane % 32, k = 8 * pair + 4 * (lane / 32) + j;
+        const int woff = set < 2 ? OFF_W2 : OFF_W3;
+        const int idx = (set & 1) ? woff + (k * WID + m) * 9 + (8 - tap) : woff + (m * WID + k) * 9 + tap;
+        pack[i] = f2bf(theta[idx]);
+    }
+}
+
+// layer 1: a1 = tanh(conv(x; W1) + b1), x planar [2][HW], a1 grouped
+__global__ __launch_bounds__(256) void k_in_fwd(const float* __restrict__ x, const float* __restrict__ q,
+                                                float* __restrict__ a1, int ny, int nx) {
+    __shared__ float w[OFF_W2];
+    for (int i = threadIdx.x; i < OFF_W2; i += blockDim.x) w[i] = q[OFF_W1 + i];
+    __syncthreads();
+    const long HW = (long)ny * nx;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
+        const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
+        float in[CIN][9];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const long row = (long)wrap1(y + dy - 1, ny) * nx;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const long qi = row + wrap1(xx + dx - 1, nx);
+#pragma unroll
+                for (int c = 0; c < CIN; ++c) in[c][dy * 3 + dx] = x[c * HW + qi];
+            }
+        }
+#pragma unroll 1
+        for (int g = 0; g < NG; ++g) {
+            float o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int co = 4 * g + j;
+                float z = w[OFF_B1 + co];
+#pragma unroll
+                for (int c = 0; c < CIN; ++c)
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) z += w[(co * CIN + c) * 9 + t] * in[c][t];
+                o[j] = tanhf(z);
+            }
+            *reinterpret_cast<float4*>(a1 + ((long)g * HW + p) * 4) = make_float4(o[0], o[1], o[2], o[3]);
+        }
+    }
+}
+
+// inner layers on the matrix cores.  MODE 0: out = tanh(conv(in) + bias) (forward);
+// MODE 1: out = conv(in) * (1 - aux^2) (backward through the previous tanh, aux = its output).
+// One wave computes 32 consecutive cells x 32 output channels per tile.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv32(const float* __restrict__ in, const bf16x4* __restrict__ pack,
+                                                const float* __restrict__ bias, const float* __restrict__ aux,
+                                                float* __restrict__ out, int ny, int nx) {
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    const long wave = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const long nwaves = (long)gridDim.x * (blockDim.x >> 6);
+    const long HW = (long)ny * nx;
+    const long ntiles = (HW + 31) / 32;
+    bf16x4 A[KSTEPS];
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) A[s] = pack[s * 64 + lane];
+    for (long tile = wave; tile < ntiles; tile += nwaves) {
+        const long p = tile * 32 + col;
+        const bool valid = p < HW;
+        const int y = valid ? (int)(p / nx) : 0;
+        const int x = valid ? (int)(p - (long)y * nx) : 0;
+        f32x16 acc = {};
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const long row = (long)wrap1(y + dy - 1, ny) * nx;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const long qi = row + wrap1(x + dx - 1, nx);
+#pragma unroll
+                for (int pair = 0; pair < 4; ++pair) {
+                    const int cg = 2 * pair + half;
+                    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (valid) v = *reinterpret_cast<const float4*>(in + ((long)cg * HW + qi) * 4);
+                    const unsigned short h0 = f2bf(v.x), h1 = f2bf(v.y), h2 = f2bf(v.z), h3 = f2bf(v.w);
+                    bf16x4 hi, lo;
+                    hi[0] = (short)h0;
+                    hi[1] = (short)h1;
+                    hi[2] = (short)h2;
+                    hi[3] = (short)h3;
+                    lo[0] = (short)f2bf(v.x - bf2f(h0));
+                    lo[1] = (short)f2bf(v.y - bf2f(h1));
+                    lo[2] = (short)f2bf(v.z - bf2f(h2));
+                    lo[3] = (short)f2bf(v.w - bf2f(h3));
+                    const int s = (dy * 3 + dx) * 4 + pair;
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], hi, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], lo, acc, 0, 0, 0);
+                }
+            }
+        }
+        if (!valid) continue;
+        // lane holds cell p and output channels 8 (r / 4) + 4 half + r % 4, r = 0..15
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            const int cg = 2 * q4 + half;
+            const long o = ((long)cg * HW + p) * 4;
+            float r[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r[j] = acc[4 * q4 + j];
+            if (MODE == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) r[j] = tanhf(r[j] + bias[4 * cg + j]);
+            } else {
+                const float4 a = *reinterpret_cast<const float4*>(aux + o);
+                r[0] *= 1.f - a.x * a.x;
+                r[1] *= 1.f - a.y * a.y;
+                r[2] *= 1.f - a.z * a.z;
+                r[3] *= 1.f - a.w * a.w;
+            }
+            *reinterpret_cast<float4*>(out + o) = make_float4(r[0], r[1], r[2], r[3]);
+        }
+    }
+}
+
+// layer 4: y = conv(a3; W4) + b4
+__global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a3, const float* __restrict__ q,
+                                                 float* __restrict__ yout, int ny, int nx) {
+    __shared__ float w[WID * 9 + 1];
+    for (int i = threadIdx.x; i < WID * 9 + 1; i += blockDim.x) w[i] = q[OFF_W4 + i];
+    __syncthreads();
+    const long HW = (long)ny * nx;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
+        const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
+        float acc = w[WID * 9];
+#pragma unroll 1
+        for (int dy = 0; dy < 3; ++dy) {
+            const long row = (long)wrap1(y + dy - 1, ny) * nx;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const long qi = row + wrap1(xx + dx - 1, nx);
+                const int t = dy * 3 + dx;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const float4 v = *reinterpret_cast<const float4*>(a3 + ((long)g * HW + qi) * 4);
+                    acc += w[(4 * g) * 9 + t] * v.x + w[(4 * g + 1) * 9 + t] * v.y + w[(4 * g + 2) * 9 + t] * v.z +
+                           w[(4 * g + 3) * 9 + t] * v.w;
+                }
+            }
+        }
+        yout[p] = acc;
+    }
+}
+
+// dy = scale * 2 (y - t) / HW and per-block partials of sum (y - t)^2
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t,
+                                              float* __restrict__ dy, long HW, float gmul, double* __restrict__ part) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
+        const float d = y[p] - t[p];
+        dy[p] = gmul * d;
+        acc += (double)d * (double)d;
+    }
+    const double s = block_sum_det(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// backward through layer 4 and the tanh of layer 3:
+// g3[c](p) = (1 - a3[c](p)^2) sum_tap W4[c][tap] dy(p - off(tap))
+__global__ __launch_bounds__(256) void k_out_bwd(const float* __restrict__ dy, const float* __restrict__ q,
+                                                 const float* __restrict__ a3, float* __restrict__ g3, int ny,
+                                                 int nx) {
+    __shared__ float w[WID * 9];
+    for (int i = threadIdx.x; i < WID * 9; i += blockDim.x) w[i] = q[OFF_W4 + i];
+    __syncthreads();
+    const long HW = (long)ny * nx;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
+        const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
+        float d[9];   // d[t'] = dy(p + off(t')), paired with the mirrored tap 8 - t'
+#pragma unroll
+        for (int dyo = 0; dyo < 3; ++dyo)
+#pragma unroll
+            for (int dxo = 0; dxo < 3; ++dxo)
+                d[dyo * 3 + dxo] = dy[(long)wrap1(y + dyo - 1, ny) * nx + wrap1(xx + dxo - 1, nx)];
+#pragma unroll 1
+        for (int g = 0; g < NG; ++g) {
+            const long o = ((long)g * HW + p) * 4;
+            const float4 a = *reinterpret_cast<const float4*>(a3 + o);
+            float r[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * g + j;
+                float s = 0.f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) s += w[c * 9 + (8 - t)] * d[t];
+                r[j] = s;
+            }
+            r[0] *= 1.f - a.x * a.x;
+            r[1] *= 1.f - a.y * a.y;
+            r[2] *= 1.f - a.z * a.z;
+            r[3] *= 1.f - a.w * a.w;
+            *reinterpret_cast<float4*>(g3 + o) = make_float4(r[0], r[1], r[2], r[3]);
+        }
+    }
+}
+
+// Weight and bias gradient of one layer, per-block partials:
+//   dW[o][c][tap] = sum_p g[o](p) a[c](p + off(tap)),  db[o] = sum_p g[o](p)
+// G output channels (32: grouped layout, 1: plain), A input channels (32: grouped, 2: planar).
+// A block walks tiles of 64 cells of one row; thread t owns channel o and CB input
+// channels for all 9 taps over a contiguous share of the tile's cells (NPH shares).
+template <int G, int A>
+__global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ g, const float* __restrict__ a, int ny,
+                                               int nx, float* __restrict__ part) {
+    constexpr int CB = A == 32 ? 4 : 2;
+    constexpr int NPAIR = G * (A / CB);
+    constexpr int NPH = 256 / NPAIR;
+    constexpr int XS = 64 / NPH;
+    constexpr int NO = G * A * 9;
+    static_assert(NPAIR * NPH == 256 && XS * NPH == 64, "thread mapping");
+    __shared__ float gs[G][65];
+    __shared__ float as_[A][3][67];
+    __shared__ float red[NPH > 1 ? NPH * NPAIR * (CB * 9 + 1) : 1];
+    const int t = threadIdx.x;
+    const int pair = t % NPAIR, ph = t / NPAIR;
+    const int o = pair / (A / CB), cb = (pair % (A / CB)) * CB;
+    const long HW = (long)ny * nx;
+    const int ntx = (nx + 63) / 64;
+    const long ntiles = (long)ny * ntx;
+    float acc[CB][9];
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[i][k] = 0.f;
+    float bacc = 0.f;
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int y = (int)(tile / ntx), x0 = (int)(tile - (long)y * ntx) * 64;
+        __syncthreads();
+        for (int e = t; e < G * 64; e += 256) {
+            int oo, xl;
+            if (G == 32) {   // channel-in-group fastest: contiguous 16-byte groups
+                const int j = e & 3, rest = e >> 2;
+                xl = rest % 64;
+                oo = (rest / 64) * 4 + j;
+            } else {
+                oo = 0;
+                xl = e;
+            }
+            const int x = x0 + xl;
+            float v = 0.f;
+            if (x < nx) {
+                const long pi = (long)y * nx + x;
+                v = G == 32 ? g[((long)(oo >> 2) * HW + pi) * 4 + (oo & 3)] : g[pi];
+            }
+            gs[oo][xl] = v;
+        }
+        for (int e = t; e < A * 3 * 66; e += 256) {
+            int c, r, xl;
+            if (A == 32) {
+                const int j = e & 3, rest = e >> 2;
+                xl = rest % 66;
+                const int rr = rest / 66;
+                r = rr % 3;
+                c = (rr / 3) * 4 + j;
+            } else {
+                xl = e % 66;
+                r = (e / 66) % 3;
+                c = e / 198;
+            }
+            const long pi = (long)wrapm(y + r - 1, ny) * nx + wrapm(x0 + xl - 1, nx);
+            as_[c][r][xl] = A == 32 ? a[((long)(c >> 2) * HW + pi) * 4 + (c & 3)] : a[(long)c * HW + pi];
+        }
+        __syncthreads();
+        for (int xl = ph * XS; xl < (ph + 1) * XS; ++xl) {
+            const float gv = gs[o][xl];
+            bacc += gv;
+#pragma unroll
+            for (int i = 0; i < CB; ++i)
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc[i][r * 3 + d] += gv * as_[cb + i][r][xl + d];
+        }
+    }
+    float* dst = part + (long)blockIdx.x * (NO + G);
+    if (NPH == 1) {
+#pragma unroll
+        for (int i = 0; i < CB; ++i)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) dst[(o * A + cb + i) * 9 + k] = acc[i][k];
+        if (cb == 0) dst[NO + o] = bacc;
+        return;
+    }
+    __syncthreads();
+    float* mine = red + ((long)ph * NPAIR + pair) * (CB * 9 + 1);
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) mine[i * 9 + k] = acc[i][k];
+    mine[CB * 9] = bacc;
+    __syncthreads();
+    for (int e = t; e < NPAIR * (CB * 9 + 1); e += 256) {
+        const int pr = e / (CB * 9 + 1), k = e % (CB * 9 + 1);
+        float s = 0.f;
+        for (int h = 0; h < NPH; ++h) s += red[((long)h * NPAIR + pr) * (CB * 9 + 1) + k];
+        const int oo = pr / (A / CB), cc = (pr % (A / CB)) * CB;
+        if (k < CB * 9)
+            dst[(oo * A + cc + k / 9) * 9 + k % 9] = s;
+        else if (cc == 0)
+            dst[NO + oo] = s;
+    }
+}
+
+// grad[off + k] (+)= sum_b part[b][k], k < n, blocks in order
+__global__ void k_wreduce(const float* __restrict__ part, int nblocks, int n, float* __restrict__ grad, int accumulate) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += part[(long)b * n + k];
+    grad[k] = accumulate ? grad[k] + s : s;
+}
+
+__global__ void k_adam(float* __restrict__ theta, const float* __restrict__ grad, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.f - b1) * g;
+    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// solver side: network input planes and the guess
+__global__ __launch_bounds__(256) void k_net_input(const double* __restrict__ phi, const double* __restrict__ prev,
+                                                   long n, double ratio, double inv_sa, double inv_sb,
+                                                   const double* __restrict__ sum_part, int np,
+                                                   float* __restrict__ x) {
+    __shared__ double red[4];
+    const double mean = sum_partials_bcast(sum_part, np, red) / (double)n;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double f = phi[i];
+        x[i] = (float)((f - mean) * inv_sa);
+        x[n + i] = (float)(ratio * (f - prev[i]) * inv_sb);
+    }
+}
+
+__global__ void k_net_guess(const double* __restrict__ phi, const float* __restrict__ y, double s_o,
+                            double* __restrict__ X, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        X[i] = phi[i] + s_o * (double)y[i];
+}
+
+inline unsigned grid_for(long n, int per = 256, unsigned cap = 4096) {
+    const long b = (n + per - 1) / per;
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+}  // namespace pfc
+
+using namespace pfc;
+
+struct pfc_net {
+    hipStream_t stream = nullptr;
+    float* d_theta = nullptr;   // master parameters
+    float* d_q = nullptr;       // rounded weights + biases
+    unsigned short* d_pack = nullptr;
+    float* d_grad = nullptr;
+    float* d_m = nullptr;
+    float* d_v = nullptr;
+    float* d_wpart = nullptr;   // weight-gradient partials
+    double* d_lpart = nullptr;  // loss partials
+    double* h_lpart = nullptr;
+    long cap = 0;               // cells the activation buffers hold
+    float *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *b1 = nullptr, *b2 = nullptr, *y = nullptr, *dy = nullptr;
+    long step = 0;
+    bool prepared = false;
+    std::string err;
+};
+
+namespace {
+
+#define NETCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            net->err = std::string(#expr) + ": " + hipGetErrorString(e_);                \
+            return PFC_EHIP;                                                             \
+        }                                                                                \
+    } while (0)
+
+void free_acts(pfc_net* net) {
+    float* bufs[] = {net->a1, net->a2, net->a3, net->b1, net->b2, net->y, net->dy};
+    for (float* p : bufs)
+        if (p) (void)hipFree(p);
+    net->a1 = net->a2 = net->a3 = net->b1 = net->b2 = net->y = net->dy = nullptr;
+    net->cap = 0;
+}
+
+pfc_status ensure(pfc_net* net, long HW) {
+    if (HW <= net->cap) return PFC_OK;
+    if (hipDeviceSynchronize() != hipSuccess) {   // earlier launches may still use the buffers
+        net->err = "stream synchronisation failed";
+        return PFC_EHIP;
+    }
+    free_acts(net);
+    const size_t big = sizeof(float) * (size_t)WID * HW, small = sizeof(float) * (size_t)HW;
+    float** bigs[] = {&net->a1, &net->a2, &net->a3, &net->b1, &net->b2};
+    for (float** p : bigs)
+        if (hipMalloc((void**)p, big) != hipSuccess) {
+            free_acts(net);
+            net->err = "out of device memory for activations";
+            return PFC_ENOMEM;
+        }
+    if (hipMalloc((void**)&net->y, small) != hipSuccess || hipMalloc((void**)&net->dy, small) != hipSuccess) {
+        free_acts(net);
+        net->err = "out of device memory for activations";
+        return PFC_ENOMEM;
+    }
+    net->cap = HW;
+    return PFC_OK;
+}
+
+pfc_status prepare(pfc_net* net, hipStream_t s) {
+    if (net->prepared) return PFC_OK;
+    hipLaunchKernelGGL(k_prepare, dim3((4 * PACK * 4 + 255) / 256), dim3(256), 0, s, net->d_theta, net->d_q,
+                       net->d_pack);
+    NETCHK(hipGetLastError());
+    net->prepared = true;
+    return PFC_OK;
+}
+
+const bf16x4* pack_of(const pfc_net* net, int set) {
+    return reinterpret_cast<const bf16x4*>(net->d_pack) + (long)set * PACK;
+}
+
+unsigned conv_grid(long HW) {
+    const long tiles = (HW + 31) / 32;
+    const long blocks = (tiles + 3) / 4;
+    return (unsigned)(blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks));
+}
+
+// forward pass on stream s, activations kept in a1..a3, output in y_out
+pfc_status forward_impl(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* y_out) {
+    const long HW = (long)ny * nx;
+    pfc_status st = ensure(net, HW);
+    if (st != PFC_OK) return st;
+    st = prepare(net, s);
+    if (st != PFC_OK) return st;
+    hipLaunchKernelGGL(k_in_fwd, dim3(grid_for(HW)), dim3(256), 0, s, x, net->d_q, net->a1, ny, nx);
+    hipLaunchKernelGGL(k_conv32<0>, dim3(conv_grid(HW)), dim3(256), 0, s, net->a1, pack_of(net, 0),
+                       net->d_q + OFF_B2, nullptr, net->a2, ny, nx);
+    hipLaunchKernelGGL(k_conv32<0>, dim3(conv_grid(HW)), dim3(256), 0, s, net->a2, pack_of(net, 2),
+                       net->d_q + OFF_B3, nullptr, net->a3, ny, nx);
+    hipLaunchKernelGGL(k_out_fwd, dim3(grid_for(HW)), dim3(256), 0, s, net->a3, net->d_q, y_out, ny, nx);
+    NETCHK(hipGetLastError());
+    return PFC_OK;
+}
+
+template <int G, int A>
+pfc_status wgrad(pfc_net* net, const float* g, const float* a, int ny, int nx, int off, int accumulate) {
+    constexpr int n = G * A * 9 + G;
+    hipLaunchKernelGGL((k_wgrad<G, A>), dim3(WG_BLOCKS), dim3(256), 0, net->stream, g, a, ny, nx, net->d_wpart);
+    hipLaunchKernelGGL(k_wreduce, dim3((n + 255) / 256), dim3(256), 0, net->stream, net->d_wpart, WG_BLOCKS, n,
+                       net->d_grad + off, accumulate);
+    NETCHK(hipGetLastError());
+    return PFC_OK;
+}
+
+}  // namespace
+
+namespace pfc {
+// for the solver: learned initial guess X = phi + s_o * net(x(phi, prev)), before the mass shift
+pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
+                     double ratio, const double* scales, const double* sum_part, int np, float* xbuf, float* ybuf,
+                     double* X) {
+    const long n = (long)ny * nx;
+    hipLaunchKernelGGL(k_net_input, dim3(grid_for(n)), dim3(256), 0, s, phi, prev, n, ratio, 1.0 / scales[0],
+                       1.0 / scales[1], sum_part, np, xbuf);
+    pfc_status st = forward_impl(net, s, xbuf, ny, nx, ybuf);
+    if (st != PFC_OK) return st;
+    hipLaunchKernelGGL(k_net_guess, dim3(grid_for(n)), dim3(256), 0, s, phi, ybuf, scales[2], X, n);
+    NETCHK(hipGetLastError());
+    return PFC_OK;
+}
+
+const char* net_error(const pfc_net* net) { return net->err.c_str(); }
+}  // namespace pfc
+
+extern "C" {
+
+pfc_status pfc_net_create(void* stream, pfc_net** out) {
+    if (!out) return PFC_EINVAL;
+    *out = nullptr;
+    pfc_net* net = new pfc_net();
+    net->stream = (hipStream_t)stream;
+    bool ok = hipMalloc((void**)&net->d_theta, sizeof(float) * NPARAM) == hipSuccess &&
+              hipMalloc((void**)&net->d_q, sizeof(float) * NPARAM) == hipSuccess &&
+              hipMalloc((void**)&net->d_pack, sizeof(unsigned short) * 4 * PACK * 4) == hipSuccess &&
+              hipMalloc((void**)&net->d_grad, sizeof(float) * NPARAM) == hipSuccess &&
+              hipMalloc((void**)&net->d_m, sizeof(float) * NPARAM) == hipSuccess &&
+              hipMalloc((void**)&net->d_v, sizeof(float) * NPARAM) == hipSuccess &&
+              hipMalloc((void**)&net->d_wpart, sizeof(float) * (size_t)WG_BLOCKS * WG_MAXOUT) == hipSuccess &&
+              hipMalloc((void**)&net->d_lpart, sizeof(double) * kRedBlocks) == hipSuccess &&
+              hipHostMalloc((void**)&net->h_lpart, sizeof(double) * kRedBlocks) == hipSuccess;
+    if (ok) {
+        ok = hipMemset(net->d_theta, 0, sizeof(float) * NPARAM) == hipSuccess &&
+             hipMemset(net->d_grad, 0, sizeof(float) * NPARAM) == hipSuccess &&
+             hipMemset(net->d_m, 0, sizeof(float) * NPARAM) == hipSuccess &&
+             hipMemset(net->d_v, 0, sizeof(float) * NPARAM) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        pfc_net_destroy(net);
+        return PFC_ENOMEM;
+    }
+    *out = net;
+    return PFC_OK;
+}
+
+void pfc_net_destroy(pfc_net* net) {
+    if (!net) return;
+    free_acts(net);
+    void* ptrs[] = {net->d_theta, net->d_q, net->d_pack, net->d_grad, net->d_m, net->d_v, net->d_wpart, net->d_lpart};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (net->h_lpart) (void)hipHostFree(net->h_lpart);
+    delete net;
+}
+
+const char* pfc_net_last_error(const pfc_net* net) { return net ? net->err.c_str() : "null network"; }
+
+pfc_status pfc_net_set_params(pfc_net* net, const float* host_params) {
+    if (!net || !host_params) return PFC_EINVAL;
+    NETCHK(hipMemcpyAsync(net->d_theta, host_params, sizeof(float) * NPARAM, hipMemcpyHostToDevice, net->stream));
+    NETCHK(hipMemsetAsync(net->d_m, 0, sizeof(float) * NPARAM, net->stream));
+    NETCHK(hipMemsetAsync(net->d_v, 0, sizeof(float) * NPARAM, net->stream));
+    NETCHK(hipStreamSynchronize(net->stream));
+    net->step = 0;
+    net->prepared = false;
+    return PFC_OK;
+}
+
+pfc_status pfc_net_get_params(pfc_net* net, float* host_params) {
+    if (!net || !host_params) return PFC_EINVAL;
+    NETCHK(hipMemcpyAsync(host_params, net->d_theta, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, net->stream));
+    NETCHK(hipStreamSynchronize(net->stream));
+    return PFC_OK;
+}
+
+pfc_status pfc_net_forward(pfc_net* net, const float* x, int ny, int nx, float* y) {
+    if (!net) return PFC_EINVAL;
+    if (!x || !y || ny < 3 || nx < 3) {
+        net->err = "bad argument";
+        return PFC_EINVAL;
+    }
+    return forward_impl(net, net->stream, x, ny, nx, y);
+}
+
+pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny, int nx, double scale,
+                            int accumulate, double* loss) {
+    if (!net) return PFC_EINVAL;
+    if (!x || !t || ny < 3 || nx < 3) {
+        net->err = "bad argument";
+        return PFC_EINVAL;
+    }
+    const long HW = (long)ny * nx;
+    hipStream_t s = net->stream;
+    pfc_status st = ensure(net, HW);
+    if (st != PFC_OK) return st;
+    st = forward_impl(net, s, x, ny, nx, net->y);
+    if (st != PFC_OK) return st;
+    hipLaunchKernelGGL(k_loss, dim3(kRedBlocks), dim3(256), 0, s, net->y, t, net->dy, HW,
+                       (float)(2.0 * scale / (double)HW), net->d_lpart);
+    NETCHK(hipGetLastError());
+    // layer 4
+    if ((st = wgrad<1, WID>(net, net->dy, net->a3, ny, nx, OFF_W4, accumulate)) != PFC_OK) return st;
+    hipLaunchKernelGGL(k_out_bwd, dim3(grid_for(HW)), dim3(256), 0, s, net->dy, net->d_q, net->a3, net->b1, ny, nx);
+    // layer 3: g3 in b1
+    if ((st = wgrad<WID, WID>(net, net->b1, net->a2, ny, nx, OFF_W3, accumulate)) != PFC_OK) return st;
+    hipLaunchKernelGGL(k_conv32<1>, dim3(conv_grid(HW)), dim3(256), 0, s, net->b1, pack_of(net, 3), nullptr, net->a2,
+                       net->b2, ny, nx);
+    // layer 2: g2 in b2
+    if ((st = wgrad<WID, WID>(net, net->b2, net->a1, ny, nx, OFF_W2, accumulate)) != PFC_OK) return st;
+    hipLaunchKernelGGL(k_conv32<1>, dim3(conv_grid(HW)), dim3(256), 0, s, net->b2, pack_of(net, 1), nullptr, net->a1,
+                       net->b1, ny, nx);
+    // layer 1: g1 in b1
+    if ((st = wgrad<WID, CIN>(net, net->b1, x, ny, nx, OFF_W1, accumulate)) != PFC_OK) return st;
+    NETCHK(hipGetLastError());
+    if (loss) {
+        NETCHK(hipMemcpyAsync(net->h_lpart, net->d_lpart, sizeof(double) * kRedBlocks, hipMemcpyDeviceToHost, s));
+        NETCHK(hipStreamSynchronize(s));
+        double sum = 0.0;
+        for (int i = 0; i < kRedBlocks; ++i) sum += net->h_lpart[i];
+        *loss = sum / (double)HW;
+    }
+    return PFC_OK;
+}
+
+pfc_status pfc_net_get_gradient(pfc_net* net, float* host_grad) {
+    if (!net || !host_grad) return PFC_EINVAL;
+    NETCHK(hipMemcpyAsync(host_grad, net->d_grad, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, net->stream));
+    NETCHK(hipStreamSynchronize(net->stream));
+    return PFC_OK;
+}
+
+pfc_status pfc_net_adam(pfc_net* net, double lr, double beta1, double beta2, double eps) {
+    if (!net) return PFC_EINVAL;
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0)) {
+        net->err = "bad Adam hyper-parameters";
+        return PFC_EINVAL;
+    }
+    net->step++;
+    const double c1 = 1.0 / (1.0 - std::pow(beta1, (double)net->step));
+    const double c2 = 1.0 / (1.0 - std::pow(beta2, (double)net->step));
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, net->stream, net->d_theta, net->d_grad,
+                       net->d_m, net->d_v, NPARAM, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
+                       (float)c2);
+    NETCHK(hipGetLastError());
+    net->prepared = false;
+    return PFC_OK;
+}
+
+}  // extern "C"

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/pfc.h"
+#include "../../include/pfc_net.h"
 
 namespace pfc {
 
@@ -53,6 +54,13 @@ struct KernelTimer {
     long count[4] = {0, 0, 0, 0};
     double total_ms[4] = {0, 0, 0, 0};
 };
+
+// ---- learned initial guess (net.hip) ----
+// X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)); before the mass shift
+pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
+                     double ratio, const double* scales, const double* sum_part, int np, float* xbuf, float* ybuf,
+                     double* X);
+const char* net_error(const pfc_net* net);
 
 }  // namespace pfc
 
@@ -110,6 +118,13 @@ struct pfc_ctx {
     double fac_gpn = 0.0;              // GMRES iterations per Newton step of that time step
     double last_gpn = 0.0;             // ... of the last time step
 
+    // learned initial guess (pfc_attach_net); the network is not owned
+    pfc_net* net = nullptr;
+    double net_scale[3] = {1.0, 1.0, 1.0};   // s_a, s_b, s_o
+    double net_dt = 0.0;                     // time step of the training data
+    float* d_netx = nullptr;                 // network input planes [2][N]
+    float* d_nety = nullptr;                 // network output [N]
+
     pfc::KernelTimer timer;
 };
 
@@ -157,5 +172,12 @@ hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
 hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
+
+// ---- learned initial guess (net.hip) ----
+// X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)); before the mass shift
+pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
+                     double ratio, const double* scales, const double* sum_part, int np, float* xbuf, float* ybuf,
+                     double* X);
+const char* net_error(const pfc_net* net);
 
 }  // namespace pfc

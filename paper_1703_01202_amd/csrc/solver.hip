@@ -414,16 +414,53 @@ pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
 void free_all(pfc_ctx* c) {
     void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, c->d_fac, c->d_flag, c->d_c,
                     c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
-                    c->d_tmp3, c->d_part, c->d_scal};
+                    c->d_tmp3, c->d_part, c->d_scal, c->d_netx, c->d_nety};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_pin) hipHostFree(c->h_pin);
     for (auto e : c->timer.pool) hipEventDestroy(e);
 }
 
+// Which initial guess this step uses: the learned one when a network is attached, the
+// history exists and dt is within 20% of the network's training step; otherwise linear
+// extrapolation when asked for (or as the learned guess's fallback) and the history exists;
+// otherwise the previous solution (the paper's choice, Sec. 4).
+int guess_kind(const pfc_ctx* c, double dt) {
+    const int g = c->opts.guess;
+    if (!c->have_prev) return PFC_GUESS_PREVIOUS;
+    if (g == PFC_GUESS_LEARNED && c->net && std::fabs(dt - c->net_dt) <= 0.2 * c->net_dt) return PFC_GUESS_LEARNED;
+    if (g == PFC_GUESS_EXTRAP || g == PFC_GUESS_LEARNED) return PFC_GUESS_EXTRAP;
+    return PFC_GUESS_PREVIOUS;
+}
+
+// d_X = initial guess of kind `used` for the step phi^n -> phi^(n+1) of size dt; the
+// extrapolated and learned guesses are shifted to the mass of phi^n when mass_project is set.
+pfc_status make_guess(pfc_ctx* c, const double* phi, double dt, int used) {
+    const long N = c->g.N;
+    if (used == PFC_GUESS_PREVIOUS) {
+        HIPCHK(hipMemcpyAsync(c->d_X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+        return PFC_OK;
+    }
+    if (used == PFC_GUESS_EXTRAP) {
+        HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
+    } else {
+        double* part = part_md1(c);
+        HIPCHK(launch_dot(c->stream, phi, nullptr, N, part));
+        pfc_status s = net_guess(c->net, c->stream, phi, c->d_prev, c->g.ny, c->g.nx, dt / c->dt_nm1, c->net_scale,
+                                 part, kRedBlocks, c->d_netx, c->d_nety, c->d_X);
+        if (s != PFC_OK) return fail(c, s, std::string("learned guess: ") + net_error(c->net));
+    }
+    if (c->opts.mass_project) {   // restore the mass of phi^n exactly: X += mean(phi - X)
+        HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
+        CHK(shift_by_sum(c, c->d_X, c->d_w, 1.0 / (double)N));
+    }
+    return PFC_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
 
 void pfc_default_opts(pfc_opts* o) {
     std::memset(o, 0, sizeof(*o));
@@ -486,8 +523,9 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
         s = PFC_EUNSUP;
     }
     if (s == PFC_OK && !(op->dt_min > 0 && op->dt_max >= op->dt_min)) s = bad("need 0 < dt_min <= dt_max");
-    if (s == PFC_OK && op->guess == PFC_GUESS_LEARNED) {
-        c->err = "learned guess needs pfc_cnn_* (not in this build)";
+    if (s == PFC_OK && (op->guess < PFC_GUESS_PREVIOUS || op->guess > PFC_GUESS_LEARNED)) s = bad("bad guess kind");
+    if (s == PFC_OK && op->guess == PFC_GUESS_LEARNED && dim != 2) {
+        c->err = "the learned guess is built for 2-D grids";
         s = PFC_EUNSUP;
     }
     if (s != PFC_OK) {
@@ -648,6 +686,7 @@ pfc_status pfc_newton(pfc_ctx* c, const double* phi, double dt, double* Phi, pfc
     if (c->opts.newton_rel_ref) CHK(reference_norm(c, phi, dt, &fref));
     HIPCHK(hipMemcpyAsync(c->d_X, Phi, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
     pfc_status s = newton_impl(c, phi, dt, st, false, fref);
+    st->res_ref = fref >= 0.0 ? fref : st->res0;
     HIPCHK(hipMemcpyAsync(Phi, c->d_X, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     st->dt = dt;
@@ -672,17 +711,8 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
     pfc_status s = PFC_OK;
     for (int attempt = 0;; ++attempt) {
         // initial guess
-        int used = PFC_GUESS_PREVIOUS;
-        if (o.guess == PFC_GUESS_EXTRAP && c->have_prev) {
-            HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
-            if (o.mass_project) {   // restore the mass of phi^n exactly: X += mean(phi - X)
-                HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
-                CHK(shift_by_sum(c, c->d_X, c->d_w, 1.0 / (double)N));
-            }
-            used = PFC_GUESS_EXTRAP;
-        } else {
-            HIPCHK(hipMemcpyAsync(c->d_X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
-        }
+        const int used = guess_kind(c, dt);
+        CHK(make_guess(c, phi, dt, used));
         pfc_step_stats tmp;
         std::memset(&tmp, 0, sizeof(tmp));
         double fref = -1.0;
@@ -694,15 +724,7 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
             // lagged factors did not do: same dt, fresh factors
             st->newton_its += tmp.newton_its;
             st->gmres_its += tmp.gmres_its;
-            if (used == PFC_GUESS_EXTRAP) {
-                HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
-                if (o.mass_project) {
-                    HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
-                    CHK(shift_by_sum(c, c->d_X, c->d_w, 1.0 / (double)N));
-                }
-            } else {
-                HIPCHK(hipMemcpyAsync(c->d_X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
-            }
+            CHK(make_guess(c, phi, dt, used));
             std::memset(&tmp, 0, sizeof(tmp));
             c->fac_valid = false;
             s = newton_impl(c, phi, dt, &tmp, false, fref);
@@ -717,6 +739,7 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
         st->ls_cuts += tmp.ls_cuts;
         st->res0 = tmp.res0;
         st->res_final = tmp.res_final;
+        st->res_ref = fref >= 0.0 ? fref : tmp.res0;
         st->guess_used = used;
         if (s == PFC_OK) break;
         if ((s != PFC_ENOTCONV && s != PFC_EKRYLOV) || attempt >= o.max_retries || dt <= o.dt_min / 16) return s;
@@ -760,6 +783,26 @@ pfc_status pfc_kernel_time(pfc_ctx* c, int which, long* count, double* total_ms)
     if (!c || which < 0 || which > 3 || !count || !total_ms) return PFC_EINVAL;
     *count = c->timer.count[which];
     *total_ms = c->timer.total_ms[which];
+    return PFC_OK;
+}
+
+pfc_status pfc_attach_net(pfc_ctx* c, pfc_net* net, const double* scales, double dt_train) {
+    if (!c) return PFC_EINVAL;
+    if (!net) {
+        c->net = nullptr;
+        return PFC_OK;
+    }
+    if (c->g.dim != 2) return fail(c, PFC_EUNSUP, "the learned guess is built for 2-D grids");
+    if (!scales || !(scales[0] > 0) || !(scales[1] > 0) || !(scales[2] > 0) || !(dt_train > 0))
+        return fail(c, PFC_EINVAL, "scales and dt_train must be positive");
+    if (!c->d_netx) {
+        if (hipMalloc((void**)&c->d_netx, sizeof(float) * 2 * (size_t)c->g.N) != hipSuccess ||
+            hipMalloc((void**)&c->d_nety, sizeof(float) * (size_t)c->g.N) != hipSuccess)
+            return fail(c, PFC_ENOMEM, "out of device memory for the network planes");
+    }
+    c->net = net;
+    for (int i = 0; i < 3; ++i) c->net_scale[i] = scales[i];
+    c->net_dt = dt_train;
     return PFC_OK;
 }
 

@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point of include/pfc.h (CPU only).
+"""The C-ABI library loads and exports every entry point of include/*.h (CPU only).
 
 Also checks host-side argument validation, which returns before any device call.
 """
@@ -13,9 +13,13 @@ LIB = os.path.join(ROOT, "paper_1703_01202_amd", "libpfc.so")
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "pfc.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pfc_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+            names.update(re.findall(r"\b(pfc_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +32,8 @@ def lib():
 def test_header_declares_the_hot_path():
     names = _declared_functions()
     for required in ("pfc_residual", "pfc_jv", "pfc_ras_setup", "pfc_ras_apply", "pfc_step",
-                     "pfc_energy", "pfc_gmres", "pfc_newton", "pfc_create", "pfc_destroy"):
+                     "pfc_energy", "pfc_gmres", "pfc_newton", "pfc_create", "pfc_destroy",
+                     "pfc_net_create", "pfc_net_forward", "pfc_net_gradient", "pfc_net_adam", "pfc_attach_net"):
         assert required in names
 
 
@@ -75,6 +80,8 @@ def _create(lib, n=(64, 64, 1), sub=(4, 4, 1), overlap=2, dim=2, **kw):
     (dict(dt_min=0.0), -1),
     (dict(sub_solver=1, dim=3, n=(32, 32, 32), sub=(4, 4, 4)), -8),   # exact LU is 2-D only
     (dict(ras_kind=1), -1),
+    (dict(guess=3), -1),                        # no such guess
+    (dict(guess=2, dim=3, n=(32, 32, 32), sub=(4, 4, 4)), -8),       # learned guess is 2-D only
 ])
 def test_create_rejects_bad_arguments(lib, kw, status):
     assert _create(lib, **kw) == status

@@ -1,0 +1,174 @@
+"""GPU parity of the learned-guess network (include/pfc_net.h) against the FP64 oracle.
+
+Tolerances.  The GPU network rounds the convolution weights to bfloat16 exactly as the
+oracle does; what differs is (i) FP32 accumulation, (ii) the inner layers' activations
+entering the matrix cores as hi + lo bfloat16 parts, |a - hi - lo| <= 2^-17 |a|, and (iii)
+tanhf.  Each layer's error is thus a few 1e-5 of the sum of |w a| it accumulates; through
+four layers the output agrees to ~1e-4 of its scale, and the gradients, which go through
+the same split products once more, to a few 1e-4 per layer.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pfc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1703_01202_amd as m
+    return m
+
+
+def _params(seed, out_scale=1.0):
+    r = np.random.Generator(np.random.PCG64(seed + 100))
+    theta = cnn.init_params(seed, out_scale=out_scale)
+    layers = cnn.unpack(theta)
+    for _, b in layers:
+        b[:] = 0.1 * r.standard_normal(b.shape)
+    return cnn.pack(layers).astype(np.float32).astype(np.float64)
+
+
+def _data(shape, seed):
+    r = np.random.Generator(np.random.PCG64(seed))
+    x = r.standard_normal((2,) + shape)
+    t = 0.3 * r.standard_normal(shape)
+    return x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+SHAPES = [(48, 80), (37, 53), (3, 3)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_matches_oracle(pfc, shape):
+    theta = _params(1)
+    x, _ = _data(shape, 2)
+    net = pfc.GuessNet(theta)
+    y = net.forward(_cuda(x)).double().cpu().numpy()
+    ref, _ = cnn.forward(theta, x)
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() <= 2e-4 * scale, np.abs(y - ref).max() / scale
+    assert np.linalg.norm(y - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("shape", SHAPES[:2])
+def test_gradient_and_loss_match_oracle(pfc, shape):
+    theta = _params(3)
+    x, t = _data(shape, 4)
+    net = pfc.GuessNet(theta)
+    loss = net.gradient(_cuda(x), _cuda(t))
+    g = net.get_gradient().astype(np.float64)
+    y, acts = cnn.forward(theta, x)
+    ref = cnn.backward(theta, acts, y, t)
+    assert abs(loss - cnn.loss(y, t)) <= 1e-4 * cnn.loss(y, t)
+    k = 0
+    for (ws, bs) in cnn.layer_shapes():
+        n = int(np.prod(ws)) + int(np.prod(bs))
+        gl, rl = g[k:k + n], ref[k:k + n]
+        assert np.linalg.norm(gl - rl) <= 5e-4 * np.linalg.norm(rl), (k, np.linalg.norm(gl - rl) / np.linalg.norm(rl))
+        k += n
+
+
+def test_gradient_accumulates_with_scale(pfc):
+    theta = _params(5)
+    x1, t1 = _data((32, 40), 6)
+    x2, t2 = _data((32, 40), 7)
+    net = pfc.GuessNet(theta)
+    net.gradient(_cuda(x1), _cuda(t1))
+    g1 = net.get_gradient().astype(np.float64)
+    net.gradient(_cuda(x2), _cuda(t2))
+    g2 = net.get_gradient().astype(np.float64)
+    net.gradient(_cuda(x1), _cuda(t1), scale=0.5)
+    net.gradient(_cuda(x2), _cuda(t2), scale=0.5, accumulate=True, want_loss=False)
+    g = net.get_gradient().astype(np.float64)
+    np.testing.assert_allclose(g, 0.5 * (g1 + g2), rtol=1e-5, atol=1e-6 * np.abs(g1).max())
+
+
+def test_adam_step_matches_oracle(pfc):
+    theta = _params(8)
+    x, t = _data((24, 24), 9)
+    net = pfc.GuessNet(theta)
+    net.gradient(_cuda(x), _cuda(t), want_loss=False)
+    g = net.get_gradient().astype(np.float64)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    ref = theta
+    for step in (1, 2):
+        net.adam(1e-3)
+        ref, m, v = cnn.adam_step(ref, g, m, v, step, 1e-3)
+    got = net.get_params().astype(np.float64)
+    np.testing.assert_allclose(got, ref, rtol=2e-6, atol=2e-7)
+
+
+def test_set_params_round_trip_and_bad_sizes(pfc):
+    theta = _params(10)
+    net = pfc.GuessNet(theta)
+    assert np.array_equal(net.get_params(), theta.astype(np.float32))
+    with pytest.raises(ValueError):
+        net.set_params(theta[:-1])
+    with pytest.raises(pfc.PfcError):
+        x = torch.zeros((2, 2, 5), dtype=torch.float32, device="cuda")
+        net.forward(x)
+
+
+def test_training_reduces_loss_on_a_learnable_map(pfc):
+    # target: a fixed stencil of the second input plane, which the network represents
+    r = np.random.Generator(np.random.PCG64(11))
+    x = r.standard_normal((2, 32, 32))
+    t = -x[1] + 0.25 * (np.roll(x[1], 1, 0) + np.roll(x[1], -1, 0))
+    net = pfc.GuessNet(_params(12, out_scale=0.3))
+    xc, tc = _cuda(x), _cuda(t)
+    l0 = net.gradient(xc, tc)
+    for _ in range(300):
+        net.adam(3e-3)
+        net.gradient(xc, tc, want_loss=False)
+    assert net.gradient(xc, tc) < 0.05 * l0
+
+
+def test_zero_output_layer_gives_the_previous_step_trajectory(pfc):
+    # with W4 = b4 = 0 the learned guess equals phi^n exactly, so the whole trajectory is
+    # bitwise the one of the previous-step guess
+    from pfc_inputs import small_noise_64
+    w = small_noise_64()
+    layers = cnn.unpack(_params(13))
+    layers[3][0][:] = 0.0
+    layers[3][1][:] = 0.0
+    net = pfc.GuessNet(cnn.pack(layers))
+    runs = []
+    for guess in ("previous", "learned"):
+        s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, dt_min=w.dt_min, dt_max=w.dt_max,
+                       newton_rtol=w.newton_rtol, newton_atol=w.newton_atol, guess=guess)
+        if guess == "learned":
+            s.attach_net(net, (0.1, 0.01, 0.01), w.dt_min)
+        phi = torch.from_numpy(w.initial()).cuda()
+        used = []
+        for _ in range(4):
+            used.append(s.step(phi)["guess_used"])
+        runs.append((phi.cpu().numpy(), used))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[1][1] == [0, 2, 2, 2]       # first step: no history yet
+
+
+def test_learned_guess_falls_back_to_extrapolation_off_its_time_step(pfc):
+    from pfc_inputs import small_noise_64
+    w = small_noise_64()
+    net = pfc.GuessNet(_params(14, out_scale=0.0))
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, dt_min=w.dt_min, dt_max=w.dt_max,
+                   newton_rtol=w.newton_rtol, newton_atol=w.newton_atol, guess="learned")
+    s.attach_net(net, (0.1, 0.01, 0.01), 10 * w.dt_min)     # trained at another dt
+    phi = torch.from_numpy(w.initial()).cuda()
+    used = [s.step(phi)["guess_used"] for _ in range(3)]
+    assert used == [0, 1, 1]
+    with pytest.raises(pfc.PfcError):
+        s.attach_net(net, (0.0, 1.0, 1.0), 0.1)

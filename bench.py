@@ -26,9 +26,10 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (calibrated against a known-size copy; see profiles/), valid only for the kernel source
 # they were taken on: the sha256 prefix of the source file must match.
-MEASURED_TRAFFIC = {
-    ("fast", "ras_apply"): {"file": "paper_1703_01202_amd/csrc/ras_lu.hip", "sha": "421a0d1982949a3a",
-                            "bytes": 1.2231e9},
+_LU_FP32_24x72 = {"file": "paper_1703_01202_amd/csrc/ras_lu.hip", "sha": "421a0d1982949a3a", "bytes": 1.2231e9}
+MEASURED_TRAFFIC = {   # the fast and learned variants run the same apply kernel on the same boxes
+    ("fast", "ras_apply"): _LU_FP32_24x72,
+    ("learned", "ras_apply"): _LU_FP32_24x72,
 }
 
 
@@ -51,7 +52,11 @@ VARIANTS = {
     # overlap 4), extrapolated initial guess, factors kept across up to 20 time steps
     # while they stay effective; residual, Arnoldi and energy stay FP64
     "fast": dict(sub=(16, 64), overlap=4, sub_solver="lu", precond_fp32=True, guess="extrap", precond_lag=20),
+    # as "fast" with the learned initial guess (include/pfc_net.h), trained before the timed
+    # region on solver trajectories of the same physics on 512^2 grids
+    "learned": dict(sub=(16, 64), overlap=4, sub_solver="lu", precond_fp32=True, guess="learned", precond_lag=20),
 }
+LEARNED_TRAINING = dict(n=512, trajectories=10, steps=201, epochs=8, lr=3e-3)
 
 
 def apply_bytes(shape, sub, overlap, sub_solver, fp32):
@@ -93,7 +98,39 @@ def cpu_baseline(nsteps=2):
                       f"Newton + FFT-preconditioned GMRES, scipy/numpy FP64, {el:.1f} s"}
 
 
-def run_variant(name, steps, warmup, timing=True):
+def train_guess_net(cfg):
+    """Train the learned-guess network (untimed set-up of the "learned" variant)."""
+    import torch
+    from paper_1703_01202_amd import learned
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)   # noqa: E731
+    t0 = time.perf_counter()
+    data = learned.generate(cfg["n"], trajectories=cfg["trajectories"], steps=cfg["steps"], log=log)
+    t1 = time.perf_counter()
+    net, hist = learned.train(data["X"], data["T"], epochs=cfg["epochs"], lr=cfg["lr"], log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    # inference cost at the benchmark grid
+    x = torch.zeros((2, 1024, 1024), dtype=torch.float32, device="cuda")
+    y = torch.empty((1024, 1024), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        net.forward(x, y)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(20):
+        net.forward(x, y)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t3) / 20 * 1e3
+    del x, y
+    meta = {"scales": data["scales"], "dt_train": data["dt"], "samples": data["stats"]["samples"],
+            "data_seconds": t1 - t0, "train_seconds": t2 - t1, "held_out_loss": hist[-1][2],
+            "loss_history": [h[2] for h in hist], "forward_ms_1024": fwd_ms, "config": cfg,
+            "arch": "4 x conv3x3 periodic, 2-32-32-32-1, tanh; bf16 weights, fp32 accumulate"}
+    del data
+    torch.cuda.empty_cache()
+    return net, meta
+
+
+def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None):
     import torch
     import paper_1703_01202_amd as pfc
     import pfc_inputs as I
@@ -104,6 +141,8 @@ def run_variant(name, steps, warmup, timing=True):
                    precond_fp32=v["precond_fp32"], guess=v["guess"], dt_min=w.dt_min, dt_max=w.dt_max,
                    eta=w.eta, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol, lin_rtol=w.lin_rtol,
                    lin_atol=w.lin_atol, timing=timing, precond_lag=v.get("precond_lag", 0))
+    if v["guess"] == "learned":
+        s.attach_net(net, net_meta["scales"], net_meta["dt_train"])
     phi = phi0.clone()
     for i in range(warmup):
         s.step(phi)
@@ -112,6 +151,7 @@ def run_variant(name, steps, warmup, timing=True):
     phi.copy_(phi0)
     torch.cuda.synchronize()
     newton = gmres = rejected = 0
+    guess_ratio, guess_used = [], {0: 0, 1: 0, 2: 0}
     t0 = time.perf_counter()
     last = {}
     for i in range(steps):
@@ -119,6 +159,9 @@ def run_variant(name, steps, warmup, timing=True):
         newton += st["newton_its"]
         gmres += st["gmres_its"]
         rejected += st["rejected"]
+        guess_used[st["guess_used"]] += 1
+        if st["res_ref"] > 0:
+            guess_ratio.append(st["res0"] / st["res_ref"])
         last = st
         if steps <= 50 or (i + 1) % 25 == 0:
             print(f"[bench] {name} step {i + 1}/{steps} t={st['t']:.2f} dt={st['dt']:.3g} "
@@ -131,7 +174,11 @@ def run_variant(name, steps, warmup, timing=True):
     res = {"steps": steps, "seconds": el, "steps_per_s": steps / el, "dof_steps_per_s": N * steps / el,
            "newton_its": newton, "gmres_its": gmres, "gmres_per_newton": gmres / max(newton, 1),
            "rejected": rejected, "t_end": last.get("t"), "energy_end": last.get("energy"),
-           "mass_end": last.get("mass"), "kernels": kt, "variant": v}
+           "mass_end": last.get("mass"), "kernels": kt, "variant": v,
+           "guess": {"used": {"previous": guess_used[0], "extrap": guess_used[1], "learned": guess_used[2]},
+                     "res0_over_ref_median": sorted(guess_ratio)[len(guess_ratio) // 2] if guess_ratio else None}}
+    if net_meta is not None:
+        res["guess_net"] = net_meta
     # roofline of the dominant kernel (largest summed event time)
     names = {0: "ras_apply", 1: "residual", 2: "jacobian_action", 3: "factorisation"}
     bytes_per = {0: apply_bytes(w.shape, v["sub"], v["overlap"], v["sub_solver"], v["precond_fp32"]),
@@ -153,7 +200,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--variant", default="fast", choices=sorted(VARIANTS))
+    ap.add_argument("--variant", default="learned", choices=sorted(VARIANTS))
     ap.add_argument("--compare", default="plain", help="second variant timed beside (or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -161,8 +208,8 @@ def main():
                     help="run one 512 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(how it would shard is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         import torch
@@ -171,13 +218,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    main_res = run_variant(args.variant, args.steps, args.warmup)
+    net = net_meta = None
+    if "learned" in (args.variant, args.compare):
+        net, net_meta = train_guess_net(LEARNED_TRAINING)
+    main_res = run_variant(args.variant, args.steps, args.warmup, net=net, net_meta=net_meta)
     cmp_res = None
     if args.compare != "none" and args.compare != args.variant:
-        cmp_res = run_variant(args.compare, args.steps, args.warmup)
+        cmp_res = run_variant(args.compare, args.steps, args.warmup, net=net, net_meta=net_meta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
     out = {
-        "metric": "PFC time steps/s, 2D 1024^2 NKS",
+        "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1,

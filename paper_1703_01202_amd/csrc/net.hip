@@ -3,15 +3,19 @@
 //
 // Layouts
 //   input x      planar FP32 [2][HW]
-//   activations  FP32 in groups of four channels, [8][HW][4] (one 16-byte load gives the
-//                four channels of a cell; 32 consecutive cells of a group are 512 bytes)
+//   activations  groups of four channels, [8][HW] x 16 bytes: the four values of a cell as
+//                hi = bf16(a) and lo = bf16(a - hi) (hi0..hi3 then lo0..lo3), so that one
+//                16-byte load gives both matrix-core operands; the value is hi + lo (exact
+//                in FP32, |a - hi - lo| <= 2^-17 |a|); 32 cells of a group are 512 bytes
 //   output y     FP32 [HW]
 // The two 32 -> 32 layers are a dense contraction (K = 9 taps x 32 channels = 288) and run
-// on the matrix cores: v_mfma_f32_32x32x8 bf16 with the 32 output channels as M, 32
-// consecutive cells as N and (tap, input channel) as K.  Each FP32 activation is split
-// into hi = bf16(a) and lo = bf16(a - hi) and both parts are multiplied by the bf16 weight,
-// so the products carry ~16 significant bits of the activation and accumulate in FP32.
-// The thin first (2 -> 32) and last (32 -> 1) layers and the weight gradients use FP32 FMA.
+// on the matrix cores: v_mfma_f32_32x32x16 bf16 with the 32 output channels as M, 32
+// consecutive cells as N and (tap, 16 input channels) as K, once for the hi and once for
+// the lo parts of the activations.  Both parts of each stored
+// activation are multiplied by the bf16 weight, so the products carry ~16 significant bits
+// of the activation and accumulate in FP32.  The split is made once, by the producing
+// kernel.  The thin first (2 -> 32) and last (32 -> 1) layers and the weight gradients use
+// FP32 FMA with the weights read as wave-uniform (scalar-register) operands.
 // Reductions (loss, weight gradients) leave per-block partials summed in a fixed order.
 #include <cmath>
 #include <cstring>
@@ -29,12 +33,12 @@ constexpr int OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 608, OFF_B2 = 9824, OFF_W3 = 98
               OFF_W4 = 19104, OFF_B4 = 19392;
 constexpr int NPARAM = PFC_NET_NPARAM;
 static_assert(OFF_B4 + 1 == NPARAM, "parameter layout");
-constexpr int KSTEPS = 36;                 // 9 taps x 4 pairs of channel groups (8 channels per step)
-constexpr int PACK = KSTEPS * 64;          // packed A operands (4 bf16 each) per layer and direction
+constexpr int KSTEPS = 18;                 // 9 taps x 2 blocks of 16 input channels
+constexpr int PACK = KSTEPS * 64;          // packed A operands (8 bf16 each) per layer and direction
 constexpr int WG_BLOCKS = 256;             // fixed grid of the weight-gradient kernels
 constexpr int WG_MAXOUT = WID * WID * 9 + WID;
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest, ties to even
@@ -46,166 +50,227 @@ __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 __device__ __forceinline__ int wrapm(int i, int n) { return ((i % n) + n) % n; }
 
+// four activations -> hi/lo bf16 pairs in one 16-byte word (see the layout above)
+__device__ __forceinline__ uint4 split4(float a0, float a1, float a2, float a3) {
+    const unsigned h0 = f2bf(a0), h1 = f2bf(a1), h2 = f2bf(a2), h3 = f2bf(a3);
+    const unsigned l0 = f2bf(a0 - bf2f(h0)), l1 = f2bf(a1 - bf2f(h1)), l2 = f2bf(a2 - bf2f(h2)),
+                   l3 = f2bf(a3 - bf2f(h3));
+    return make_uint4(h0 | (h1 << 16), h2 | (h3 << 16), l0 | (l1 << 16), l2 | (l3 << 16));
+}
+__device__ __forceinline__ float4 join4(uint4 u) {
+    return make_float4(__uint_as_float(u.x << 16) + __uint_as_float(u.z << 16),
+                       __uint_as_float(u.x & 0xFFFF0000u) + __uint_as_float(u.z & 0xFFFF0000u),
+                       __uint_as_float(u.y << 16) + __uint_as_float(u.w << 16),
+                       __uint_as_float(u.y & 0xFFFF0000u) + __uint_as_float(u.w & 0xFFFF0000u));
+}
+__device__ __forceinline__ const uint4* grp(const float* base, long g, long HW, long p) {
+    return reinterpret_cast<const uint4*>(base) + g * HW + p;
+}
+__device__ __forceinline__ uint4* grp(float* base, long g, long HW, long p) {
+    return reinterpret_cast<uint4*>(base) + g * HW + p;
+}
+
+// tanh from one exponential: sign(z) (1 - 2 / (exp(2|z|) + 1)); absolute error ~1e-7
+__device__ __forceinline__ float tanh_fast(float z) {
+    const float e = __expf(2.f * fabsf(z));
+    return copysignf(1.f - __fdividef(2.f, e + 1.f), z);
+}
+
 __device__ __forceinline__ bool is_weight_index(int i) {
     return i < OFF_B1 || (i >= OFF_W2 && i < OFF_B2) || (i >= OFF_W3 && i < OFF_B3) || (i >= OFF_W4 && i < OFF_B4);
 }
 
 // q = parameters with the convolution weights rounded to bf16; pack = matrix-core A operands
 // of the inner layers: set 0/1 layer 2 forward/backward, set 2/3 layer 3.  Entry
-// [set][s][lane][j], step s = tap * 4 + pair, row m = lane % 32, k = 8 pair + 4 (lane / 32) + j:
+// [set][s][lane][e], step s = tap * 2 + j, row m = lane % 32, k = 16 j + 8 (lane / 32) + e:
 //   forward  A[m = out ch][k = in ch] = W[m][k][tap]
 //   backward A[m = in ch][k = out ch] = W[k][m][8 - tap]  (adjoint: swap channels, mirror taps)
 __global__ void k_prepare(const float* __restrict__ theta, float* __restrict__ q, unsigned short* __restrict__ pack) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < NPARAM) q[i] = is_weight_index(i) ? bf2f(f2bf(theta[i])) : theta[i];
-    if (i < 4 * PACK * 4) {
-        const int set = i / (PACK * 4), r = i % (PACK * 4);
-        const int s = r / 256, lane = (r / 4) % 64, j = r % 4;
-        const int tap = s / 4, pair = s % 4;
-        const int m = lane % 32, k = 8 * pair + 4 * (lane / 32) + j;
+    if (i < 4 * PACK * 8) {
+        const int set = i / (PACK * 8), r = i % (PACK * 8);
+        const int st = r / 512, lane = (r / 8) % 64, e = r % 8;
+        const int tap = st / 2, j = st % 2;
+        const int m = lane % 32, k = 16 * j + 8 * (lane / 32) + e;
         const int woff = set < 2 ? OFF_W2 : OFF_W3;
         const int idx = (set & 1) ? woff + (k * WID + m) * 9 + (8 - tap) : woff + (m * WID + k) * 9 + tap;
         pack[i] = f2bf(theta[idx]);
     }
 }
 
-// layer 1: a1 = tanh(conv(x; W1) + b1), x planar [2][HW], a1 grouped
+// layer 1 at cell (y, x): the 32 channels of a1 = tanh(conv(x; W1) + b1) as 8 split groups
+__device__ __forceinline__ void layer1_cell(const float* __restrict__ x, const float* __restrict__ q, long HW, int ny,
+                                            int nx, int y, int xx, uint4* out) {
+    float in[CIN][9];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+        const long row = (long)wrap1(y + dy - 1, ny) * nx;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const long qi = row + wrap1(xx + dx - 1, nx);
+#pragma unroll
+            for (int c = 0; c < CIN; ++c) in[c][dy * 3 + dx] = x[c * HW + qi];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        float o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = 4 * g + j;
+            float z = q[OFF_B1 + co];
+#pragma unroll
+            for (int c = 0; c < CIN; ++c)
+#pragma unroll
+                for (int t = 0; t < 9; ++t) z += q[OFF_W1 + (co * CIN + c) * 9 + t] * in[c][t];
+            o[j] = tanh_fast(z);
+        }
+        out[g] = split4(o[0], o[1], o[2], o[3]);
+    }
+}
+
+// layer 1: a1 = tanh(conv(x; W1) + b1), x planar [2][HW], a1 grouped and split
 __global__ __launch_bounds__(256) void k_in_fwd(const float* __restrict__ x, const float* __restrict__ q,
                                                 float* __restrict__ a1, int ny, int nx) {
-    __shared__ float w[OFF_W2];
-    for (int i = threadIdx.x; i < OFF_W2; i += blockDim.x) w[i] = q[OFF_W1 + i];
-    __syncthreads();
     const long HW = (long)ny * nx;
-    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
-        const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
-        float in[CIN][9];
+    const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;   // one cell per thread
+    if (p >= HW) return;
+    const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
+    uint4 o[NG];
+    layer1_cell(x, q, HW, ny, nx, y, xx, o);
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const long row = (long)wrap1(y + dy - 1, ny) * nx;
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const long qi = row + wrap1(xx + dx - 1, nx);
-#pragma unroll
-                for (int c = 0; c < CIN; ++c) in[c][dy * 3 + dx] = x[c * HW + qi];
-            }
-        }
-#pragma unroll 1
-        for (int g = 0; g < NG; ++g) {
-            float o[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int co = 4 * g + j;
-                float z = w[OFF_B1 + co];
-#pragma unroll
-                for (int c = 0; c < CIN; ++c)
-#pragma unroll
-                    for (int t = 0; t < 9; ++t) z += w[(co * CIN + c) * 9 + t] * in[c][t];
-                o[j] = tanhf(z);
-            }
-            *reinterpret_cast<float4*>(a1 + ((long)g * HW + p) * 4) = make_float4(o[0], o[1], o[2], o[3]);
-        }
+    for (int g = 0; g < NG; ++g) *grp(a1, g, HW, p) = o[g];
+}
+
+// Block tiles of CT_X x CT_Y cells; the tile and its one-cell periodic halo are staged in
+// LDS as [row][channel group][column] 16-byte groups, so a wave's 32 lanes read 512
+// contiguous bytes per operand and global memory is read once per tile.
+constexpr int CT_X = 32, CT_Y = 8, CT_R = CT_Y + 2, CT_C = CT_X + 2;
+
+__device__ __forceinline__ void stage_tile(uint4 (*sm)[NG][CT_C], const float* __restrict__ in, long HW, int ny,
+                                           int nx, int y0, int x0) {
+    const bool one_wrap = ny >= CT_R && nx >= CT_C;   // halo indices then stay within [-n, 2n)
+    for (int e = threadIdx.x; e < CT_R * NG * CT_C; e += blockDim.x) {
+        const int c = e % CT_C, g = (e / CT_C) % NG, r = e / (CT_C * NG);
+        const int yy = one_wrap ? wrap1(y0 + r - 1, ny) : wrapm(y0 + r - 1, ny);
+        const int xx = one_wrap ? wrap1(x0 + c - 1, nx) : wrapm(x0 + c - 1, nx);
+        sm[r][g][c] = *grp(in, g, HW, (long)yy * nx + xx);
     }
 }
 
 // inner layers on the matrix cores.  MODE 0: out = tanh(conv(in) + bias) (forward);
 // MODE 1: out = conv(in) * (1 - aux^2) (backward through the previous tanh, aux = its output).
-// One wave computes 32 consecutive cells x 32 output channels per tile.
+// Each of the 4 waves computes two rows of 32 cells x 32 output channels of a block tile,
+// reading each of the 4 input rows it needs once for both; blocks walk the tiles so that
+// the 18 A operands stay in registers across tiles.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_conv32(const float* __restrict__ in, const bf16x4* __restrict__ pack,
-                                                const float* __restrict__ bias, const float* __restrict__ aux,
-                                                float* __restrict__ out, int ny, int nx) {
-    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
-    const long wave = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const long nwaves = (long)gridDim.x * (blockDim.x >> 6);
+__device__ __forceinline__ void conv32_body(const float* __restrict__ in, const bf16x8* __restrict__ pack,
+                                            const float* __restrict__ bias, const float* __restrict__ aux,
+                                            float* __restrict__ out, int ny, int nx) {
+    __shared__ uint4 sm[CT_R][NG][CT_C];
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31, wv = threadIdx.x >> 6;
     const long HW = (long)ny * nx;
-    const long ntiles = (HW + 31) / 32;
-    bf16x4 A[KSTEPS];
+    const int ntx = (nx + CT_X - 1) / CT_X, nty = (ny + CT_Y - 1) / CT_Y;
+    const int ntiles = ntx * nty;
+    bf16x8 A[KSTEPS];
 #pragma unroll
     for (int s = 0; s < KSTEPS; ++s) A[s] = pack[s * 64 + lane];
-    for (long tile = wave; tile < ntiles; tile += nwaves) {
-        const long p = tile * 32 + col;
-        const bool valid = p < HW;
-        const int y = valid ? (int)(p / nx) : 0;
-        const int x = valid ? (int)(p - (long)y * nx) : 0;
-        f32x16 acc = {};
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int ty = tile / ntx, tx = tile - ty * ntx;
+        const int x0 = tx * CT_X, y0 = ty * CT_Y;
+        __syncthreads();
+        stage_tile(sm, in, HW, ny, nx, y0, x0);
+        __syncthreads();
+        const int ly0 = 2 * wv;                 // this wave's rows ly0, ly0 + 1 (CT_Y = 8)
+        f32x16 acc2[2] = {{}, {}};
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const long row = (long)wrap1(y + dy - 1, ny) * nx;
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const long qi = row + wrap1(x + dx - 1, nx);
+            for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-                for (int pair = 0; pair < 4; ++pair) {
-                    const int cg = 2 * pair + half;
-                    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (valid) v = *reinterpret_cast<const float4*>(in + ((long)cg * HW + qi) * 4);
-                    const unsigned short h0 = f2bf(v.x), h1 = f2bf(v.y), h2 = f2bf(v.z), h3 = f2bf(v.w);
-                    bf16x4 hi, lo;
-                    hi[0] = (short)h0;
-                    hi[1] = (short)h1;
-                    hi[2] = (short)h2;
-                    hi[3] = (short)h3;
-                    lo[0] = (short)f2bf(v.x - bf2f(h0));
-                    lo[1] = (short)f2bf(v.y - bf2f(h1));
-                    lo[2] = (short)f2bf(v.z - bf2f(h2));
-                    lo[3] = (short)f2bf(v.w - bf2f(h3));
-                    const int s = (dy * 3 + dx) * 4 + pair;
-                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], hi, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], lo, acc, 0, 0, 0);
+                for (int j = 0; j < 2; ++j) {
+                    // channels 16 j + 8 half + 0..7 = groups 4 j + 2 half and the next one
+                    const uint4 u0 = sm[ly0 + r][4 * j + 2 * half][col + dx];
+                    const uint4 u1 = sm[ly0 + r][4 * j + 2 * half + 1][col + dx];
+                    const bf16x8 hi = __builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y));
+                    const bf16x8 lo = __builtin_bit_cast(bf16x8, make_uint4(u0.z, u0.w, u1.z, u1.w));
+                    if (r <= 2) {                // row ly0, tap dy = r
+                        const int s = (r * 3 + dx) * 2 + j;
+                        acc2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], hi, acc2[0], 0, 0, 0);
+                        acc2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], lo, acc2[0], 0, 0, 0);
+                    }
+                    if (r >= 1) {                // row ly0 + 1, tap dy = r - 1
+                        const int s = ((r - 1) * 3 + dx) * 2 + j;
+                        acc2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], hi, acc2[1], 0, 0, 0);
+                        acc2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], lo, acc2[1], 0, 0, 0);
+                    }
                 }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const f32x16& acc = acc2[rr];
+            const int ly = ly0 + rr;
+            const int y = y0 + ly, x = x0 + col;
+            if (y >= ny || x >= nx) continue;
+            const long p = (long)y * nx + x;
+            // lane holds cell p and output channels 8 (r / 4) + 4 half + r % 4, r = 0..15
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int cg = 2 * q4 + half;
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = acc[4 * q4 + e];
+                if (MODE == 0) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = tanh_fast(v[e] + bias[4 * cg + e]);
+                } else {
+                    const float4 a = join4(*grp(aux, cg, HW, p));
+                    v[0] *= 1.f - a.x * a.x;
+                    v[1] *= 1.f - a.y * a.y;
+                    v[2] *= 1.f - a.z * a.z;
+                    v[3] *= 1.f - a.w * a.w;
+                }
+                *grp(out, cg, HW, p) = split4(v[0], v[1], v[2], v[3]);
             }
-        }
-        if (!valid) continue;
-        // lane holds cell p and output channels 8 (r / 4) + 4 half + r % 4, r = 0..15
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-            const int cg = 2 * q4 + half;
-            const long o = ((long)cg * HW + p) * 4;
-            float r[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) r[j] = acc[4 * q4 + j];
-            if (MODE == 0) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) r[j] = tanhf(r[j] + bias[4 * cg + j]);
-            } else {
-                const float4 a = *reinterpret_cast<const float4*>(aux + o);
-                r[0] *= 1.f - a.x * a.x;
-                r[1] *= 1.f - a.y * a.y;
-                r[2] *= 1.f - a.z * a.z;
-                r[3] *= 1.f - a.w * a.w;
-            }
-            *reinterpret_cast<float4*>(out + o) = make_float4(r[0], r[1], r[2], r[3]);
         }
     }
 }
+static_assert(CT_Y == 8, "conv32_body gives each of its 4 waves two rows");
 
-// layer 4: y = conv(a3; W4) + b4
+#define CONV32_ARGS                                                                                        \
+    const float *__restrict__ in, const bf16x8 *__restrict__ pack, const float *__restrict__ bias,          \
+        const float *__restrict__ aux, float *__restrict__ out, int ny, int nx
+// 43.5 KB of LDS per block: three blocks per CU, so ask for registers to match
+__global__ __launch_bounds__(256, 3) void k_conv32_fwd(CONV32_ARGS) { conv32_body<0>(in, pack, bias, aux, out, ny, nx); }
+__global__ __launch_bounds__(256, 3) void k_conv32_bwd(CONV32_ARGS) { conv32_body<1>(in, pack, bias, aux, out, ny, nx); }
+
+// layer 4: y = conv(a3; W4) + b4, one cell per thread of a block tile staged in LDS
 __global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a3, const float* __restrict__ q,
                                                  float* __restrict__ yout, int ny, int nx) {
-    __shared__ float w[WID * 9 + 1];
-    for (int i = threadIdx.x; i < WID * 9 + 1; i += blockDim.x) w[i] = q[OFF_W4 + i];
-    __syncthreads();
+    __shared__ uint4 sm[CT_R][NG][CT_C];
     const long HW = (long)ny * nx;
-    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
-        const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
-        float acc = w[WID * 9];
-#pragma unroll 1
-        for (int dy = 0; dy < 3; ++dy) {
-            const long row = (long)wrap1(y + dy - 1, ny) * nx;
+    const int ntx = (nx + CT_X - 1) / CT_X;
+    const int ty = blockIdx.x / ntx, tx = blockIdx.x - ty * ntx;
+    const int x0 = tx * CT_X, y0 = ty * CT_Y;
+    stage_tile(sm, a3, HW, ny, nx, y0, x0);
+    __syncthreads();
+    const int ly = threadIdx.x / CT_X, lx = threadIdx.x % CT_X;
+    const int y = y0 + ly, x = x0 + lx;
+    if (y >= ny || x >= nx) return;
+    float acc = q[OFF_B4];
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const long qi = row + wrap1(xx + dx - 1, nx);
-                const int t = dy * 3 + dx;
+    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    const float4 v = *reinterpret_cast<const float4*>(a3 + ((long)g * HW + qi) * 4);
-                    acc += w[(4 * g) * 9 + t] * v.x + w[(4 * g + 1) * 9 + t] * v.y + w[(4 * g + 2) * 9 + t] * v.z +
-                           w[(4 * g + 3) * 9 + t] * v.w;
-                }
+        for (int dx = 0; dx < 3; ++dx) {
+            const int t = dy * 3 + dx;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const float4 v = join4(sm[ly + dy][g][lx + dx]);
+                acc += q[OFF_W4 + (4 * g) * 9 + t] * v.x + q[OFF_W4 + (4 * g + 1) * 9 + t] * v.y +
+                       q[OFF_W4 + (4 * g + 2) * 9 + t] * v.z + q[OFF_W4 + (4 * g + 3) * 9 + t] * v.w;
             }
         }
-        yout[p] = acc;
-    }
+    yout[(long)y * nx + x] = acc;
 }
 
 // dy = scale * 2 (y - t) / HW and per-block partials of sum (y - t)^2
@@ -227,37 +292,33 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
 __global__ __launch_bounds__(256) void k_out_bwd(const float* __restrict__ dy, const float* __restrict__ q,
                                                  const float* __restrict__ a3, float* __restrict__ g3, int ny,
                                                  int nx) {
-    __shared__ float w[WID * 9];
-    for (int i = threadIdx.x; i < WID * 9; i += blockDim.x) w[i] = q[OFF_W4 + i];
-    __syncthreads();
     const long HW = (long)ny * nx;
-    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
-        const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
-        float d[9];   // d[t'] = dy(p + off(t')), paired with the mirrored tap 8 - t'
+    const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;   // one cell per thread
+    if (p >= HW) return;
+    const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
+    float d[9];   // d[t'] = dy(p + off(t')), paired with the mirrored tap 8 - t'
 #pragma unroll
-        for (int dyo = 0; dyo < 3; ++dyo)
+    for (int dyo = 0; dyo < 3; ++dyo)
 #pragma unroll
-            for (int dxo = 0; dxo < 3; ++dxo)
-                d[dyo * 3 + dxo] = dy[(long)wrap1(y + dyo - 1, ny) * nx + wrap1(xx + dxo - 1, nx)];
-#pragma unroll 1
-        for (int g = 0; g < NG; ++g) {
-            const long o = ((long)g * HW + p) * 4;
-            const float4 a = *reinterpret_cast<const float4*>(a3 + o);
-            float r[4];
+        for (int dxo = 0; dxo < 3; ++dxo)
+            d[dyo * 3 + dxo] = dy[(long)wrap1(y + dyo - 1, ny) * nx + wrap1(xx + dxo - 1, nx)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = 4 * g + j;
-                float s = 0.f;
+    for (int g = 0; g < NG; ++g) {
+        const float4 a = join4(*grp(a3, g, HW, p));
+        float r[4];
 #pragma unroll
-                for (int t = 0; t < 9; ++t) s += w[c * 9 + (8 - t)] * d[t];
-                r[j] = s;
-            }
-            r[0] *= 1.f - a.x * a.x;
-            r[1] *= 1.f - a.y * a.y;
-            r[2] *= 1.f - a.z * a.z;
-            r[3] *= 1.f - a.w * a.w;
-            *reinterpret_cast<float4*>(g3 + o) = make_float4(r[0], r[1], r[2], r[3]);
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * g + j;
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) s += q[OFF_W4 + c * 9 + (8 - t)] * d[t];
+            r[j] = s;
         }
+        r[0] *= 1.f - a.x * a.x;
+        r[1] *= 1.f - a.y * a.y;
+        r[2] *= 1.f - a.z * a.z;
+        r[3] *= 1.f - a.w * a.w;
+        *grp(g3, g, HW, p) = split4(r[0], r[1], r[2], r[3]);
     }
 }
 
@@ -293,39 +354,37 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ g, cons
     for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int y = (int)(tile / ntx), x0 = (int)(tile - (long)y * ntx) * 64;
         __syncthreads();
-        for (int e = t; e < G * 64; e += 256) {
-            int oo, xl;
-            if (G == 32) {   // channel-in-group fastest: contiguous 16-byte groups
-                const int j = e & 3, rest = e >> 2;
-                xl = rest % 64;
-                oo = (rest / 64) * 4 + j;
-            } else {
-                oo = 0;
-                xl = e;
+        if (G == 32) {   // one 16-byte group (4 channels of a cell) per thread
+            for (int e = t; e < (G / 4) * 64; e += 256) {
+                const int xl = e % 64, gg = e / 64, x = x0 + xl;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (x < nx) v = join4(*grp(g, gg, HW, (long)y * nx + x));
+                gs[4 * gg][xl] = v.x;
+                gs[4 * gg + 1][xl] = v.y;
+                gs[4 * gg + 2][xl] = v.z;
+                gs[4 * gg + 3][xl] = v.w;
             }
-            const int x = x0 + xl;
-            float v = 0.f;
-            if (x < nx) {
-                const long pi = (long)y * nx + x;
-                v = G == 32 ? g[((long)(oo >> 2) * HW + pi) * 4 + (oo & 3)] : g[pi];
+        } else {
+            for (int e = t; e < 64; e += 256) {
+                const int x = x0 + e;
+                gs[0][e] = x < nx ? g[(long)y * nx + x] : 0.f;
             }
-            gs[oo][xl] = v;
         }
-        for (int e = t; e < A * 3 * 66; e += 256) {
-            int c, r, xl;
-            if (A == 32) {
-                const int j = e & 3, rest = e >> 2;
-                xl = rest % 66;
-                const int rr = rest / 66;
-                r = rr % 3;
-                c = (rr / 3) * 4 + j;
-            } else {
-                xl = e % 66;
-                r = (e / 66) % 3;
-                c = e / 198;
+        if (A == 32) {
+            for (int e = t; e < (A / 4) * 3 * 66; e += 256) {
+                const int xl = e % 66, r = (e / 66) % 3, gg = e / 198;
+                const long pi = (long)wrapm(y + r - 1, ny) * nx + wrapm(x0 + xl - 1, nx);
+                const float4 v = join4(*grp(a, gg, HW, pi));
+                as_[4 * gg][r][xl] = v.x;
+                as_[4 * gg + 1][r][xl] = v.y;
+                as_[4 * gg + 2][r][xl] = v.z;
+                as_[4 * gg + 3][r][xl] = v.w;
             }
-            const long pi = (long)wrapm(y + r - 1, ny) * nx + wrapm(x0 + xl - 1, nx);
-            as_[c][r][xl] = A == 32 ? a[((long)(c >> 2) * HW + pi) * 4 + (c & 3)] : a[(long)c * HW + pi];
+        } else {
+            for (int e = t; e < A * 3 * 66; e += 256) {
+                const int xl = e % 66, r = (e / 66) % 3, c = e / 198;
+                as_[c][r][xl] = a[(long)c * HW + (long)wrapm(y + r - 1, ny) * nx + wrapm(x0 + xl - 1, nx)];
+            }
         }
         __syncthreads();
         for (int xl = ph * XS; xl < (ph + 1) * XS; ++xl) {
@@ -409,6 +468,8 @@ __global__ void k_net_guess(const double* __restrict__ phi, const float* __restr
         X[i] = phi[i] + s_o * (double)y[i];
 }
 
+inline unsigned cell_grid(long n) { return (unsigned)((n + 255) / 256); }   // one cell per thread
+
 inline unsigned grid_for(long n, int per = 256, unsigned cap = 4096) {
     const long b = (n + per - 1) / per;
     return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
@@ -482,36 +543,37 @@ pfc_status ensure(pfc_net* net, long HW) {
 
 pfc_status prepare(pfc_net* net, hipStream_t s) {
     if (net->prepared) return PFC_OK;
-    hipLaunchKernelGGL(k_prepare, dim3((4 * PACK * 4 + 255) / 256), dim3(256), 0, s, net->d_theta, net->d_q,
+    hipLaunchKernelGGL(k_prepare, dim3((4 * PACK * 8 + 255) / 256), dim3(256), 0, s, net->d_theta, net->d_q,
                        net->d_pack);
     NETCHK(hipGetLastError());
     net->prepared = true;
     return PFC_OK;
 }
 
-const bf16x4* pack_of(const pfc_net* net, int set) {
-    return reinterpret_cast<const bf16x4*>(net->d_pack) + (long)set * PACK;
+const bf16x8* pack_of(const pfc_net* net, int set) {
+    return reinterpret_cast<const bf16x8*>(net->d_pack) + (long)set * PACK;
 }
 
-unsigned conv_grid(long HW) {
-    const long tiles = (HW + 31) / 32;
-    const long blocks = (tiles + 3) / 4;
-    return (unsigned)(blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks));
+unsigned tile_count(int ny, int nx) { return (unsigned)(((nx + CT_X - 1) / CT_X) * ((ny + CT_Y - 1) / CT_Y)); }
+
+unsigned conv_grid(int ny, int nx) {   // blocks walk the tiles: at most 1024 blocks
+    const unsigned t = tile_count(ny, nx);
+    return t < 1024 ? t : 1024;
 }
 
-// forward pass on stream s, activations kept in a1..a3, output in y_out
+// forward pass on stream s: activations a1..a3 (kept for a backward pass), output in y_out
 pfc_status forward_impl(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* y_out) {
     const long HW = (long)ny * nx;
     pfc_status st = ensure(net, HW);
     if (st != PFC_OK) return st;
     st = prepare(net, s);
     if (st != PFC_OK) return st;
-    hipLaunchKernelGGL(k_in_fwd, dim3(grid_for(HW)), dim3(256), 0, s, x, net->d_q, net->a1, ny, nx);
-    hipLaunchKernelGGL(k_conv32<0>, dim3(conv_grid(HW)), dim3(256), 0, s, net->a1, pack_of(net, 0),
+    hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, net->a1, ny, nx);
+    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->a1, pack_of(net, 0),
                        net->d_q + OFF_B2, nullptr, net->a2, ny, nx);
-    hipLaunchKernelGGL(k_conv32<0>, dim3(conv_grid(HW)), dim3(256), 0, s, net->a2, pack_of(net, 2),
+    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->a2, pack_of(net, 2),
                        net->d_q + OFF_B3, nullptr, net->a3, ny, nx);
-    hipLaunchKernelGGL(k_out_fwd, dim3(grid_for(HW)), dim3(256), 0, s, net->a3, net->d_q, y_out, ny, nx);
+    hipLaunchKernelGGL(k_out_fwd, dim3(tile_count(ny, nx)), dim3(256), 0, s, net->a3, net->d_q, y_out, ny, nx);
     NETCHK(hipGetLastError());
     return PFC_OK;
 }
@@ -555,7 +617,7 @@ pfc_status pfc_net_create(void* stream, pfc_net** out) {
     net->stream = (hipStream_t)stream;
     bool ok = hipMalloc((void**)&net->d_theta, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_q, sizeof(float) * NPARAM) == hipSuccess &&
-              hipMalloc((void**)&net->d_pack, sizeof(unsigned short) * 4 * PACK * 4) == hipSuccess &&
+              hipMalloc((void**)&net->d_pack, sizeof(unsigned short) * 4 * PACK * 8) == hipSuccess &&
               hipMalloc((void**)&net->d_grad, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_m, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_v, sizeof(float) * NPARAM) == hipSuccess &&
@@ -633,14 +695,14 @@ pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny
     NETCHK(hipGetLastError());
     // layer 4
     if ((st = wgrad<1, WID>(net, net->dy, net->a3, ny, nx, OFF_W4, accumulate)) != PFC_OK) return st;
-    hipLaunchKernelGGL(k_out_bwd, dim3(grid_for(HW)), dim3(256), 0, s, net->dy, net->d_q, net->a3, net->b1, ny, nx);
+    hipLaunchKernelGGL(k_out_bwd, dim3(cell_grid(HW)), dim3(256), 0, s, net->dy, net->d_q, net->a3, net->b1, ny, nx);
     // layer 3: g3 in b1
     if ((st = wgrad<WID, WID>(net, net->b1, net->a2, ny, nx, OFF_W3, accumulate)) != PFC_OK) return st;
-    hipLaunchKernelGGL(k_conv32<1>, dim3(conv_grid(HW)), dim3(256), 0, s, net->b1, pack_of(net, 3), nullptr, net->a2,
+    hipLaunchKernelGGL(k_conv32_bwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->b1, pack_of(net, 3), nullptr, net->a2,
                        net->b2, ny, nx);
     // layer 2: g2 in b2
     if ((st = wgrad<WID, WID>(net, net->b2, net->a1, ny, nx, OFF_W2, accumulate)) != PFC_OK) return st;
-    hipLaunchKernelGGL(k_conv32<1>, dim3(conv_grid(HW)), dim3(256), 0, s, net->b2, pack_of(net, 1), nullptr, net->a1,
+    hipLaunchKernelGGL(k_conv32_bwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->b2, pack_of(net, 1), nullptr, net->a1,
                        net->b1, ny, nx);
     // layer 1: g1 in b1
     if ((st = wgrad<WID, CIN>(net, net->b1, x, ny, nx, OFF_W1, accumulate)) != PFC_OK) return st;

@@ -140,7 +140,8 @@ inline hipError_t set_dynamic_lds_limit(const void* f) {
 
 // ---- stencil kernels (stencil.hip) ----
 // Reductions leave per-block partials (device_reduce.h); partial_count gives their number.
-int residual_partial_count(const pfc_ctx* c);   // blocks of the residual / energy kernels
+int residual_partial_count(const pfc_ctx* c);   // blocks of the residual kernel
+int energy_partial_count(const pfc_ctx* c);     // blocks of the energy kernel (two partials each)
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
                            const double* src, double* F, double* norm_part);
 hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, double* cbuf);

@@ -14,6 +14,7 @@
 
 namespace pfc {
 int residual_partial_count(const pfc_ctx* c);
+int energy_partial_count(const pfc_ctx* c);
 void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<int>* lptr,
                         std::vector<int>* lpts, std::vector<int8_t>* pair);
 hipError_t set_ilu_lds_limits();
@@ -391,7 +392,7 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
 }
 
 pfc_status energy_impl(pfc_ctx* c, const double* phi, double* e, double* m) {
-    const int np = residual_partial_count(c);
+    const int np = energy_partial_count(c);
     HIPCHK(launch_energy(c, phi, c->d_scal + SC_P));
     HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, c->d_scal + SC_P, 2 * sizeof(double) * np, hipMemcpyDeviceToHost,
                           c->stream));
@@ -590,7 +591,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     A(dalloc(c, &c->d_Z, (size_t)m * N));
     if (dim == 3) A(dalloc(c, &c->d_tmp3, 2 * (size_t)N));
     A(dalloc(c, &c->d_part, 128 * (size_t)kRedBlocks + 64 * (size_t)c->dec.nsub));
-    c->n_scal = SC_P + std::max(kRedBlocks, 2 * residual_partial_count(c));
+    c->n_scal = SC_P + std::max({kRedBlocks, residual_partial_count(c), 2 * energy_partial_count(c)});
     A(dalloc(c, &c->d_scal, (size_t)c->n_scal));
     A(dalloc(c, &c->d_flag, 1));
     if (op->sub_solver == PFC_SUB_ILU0) {

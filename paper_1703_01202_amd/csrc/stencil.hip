@@ -36,11 +36,41 @@ __device__ __forceinline__ int wrap1(int i, int n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+// Tile of this block in a 1-D launch over ntx x nty tiles.  Blocks are dispatched round-robin
+// over the 8 XCDs, each with its own L2; XCD k = b mod 8 is given a contiguous range of tiles
+// in row-major order, so vertically adjacent tiles (which share halo rows) run on the same
+// XCD and their halo reads hit its L2.  A bijection for any tile count.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb / 8, r = nb % 8, k = b % 8;
+    return k * q + (k < r ? k : r) + b / 8;
+}
+
+// Halo staging in two phases: each thread first issues all of its global loads (a fixed,
+// unrolled count), then writes them to LDS, so a block has every load in flight at once
+// instead of one round trip per loop iteration.
+constexpr int NE3 = (TY + 6) * (TX + 6);          // cells of the halo-3 tile
+constexpr int NIT3 = (NE3 + NT - 1) / NT;
+constexpr int NIT0 = (TY * TX + NT - 1) / NT;     // interior cells per thread
+
 #define LAP2(A, y, x)                                                     \
     (((A)[y][(x) + 1] + (A)[y][(x)-1] - 2.0 * (A)[y][x]) * p.ihx2 +       \
      ((A)[(y) + 1][x] + (A)[(y)-1][x] - 2.0 * (A)[y][x]) * p.ihy2)
 
-// F = (Phi - phi)/dt - Delta_d mu_d - src, plus per-block partial sums of F^2.
+// Tiles of a persistent block: block b (after the XCD remap) owns the contiguous range
+// [first, last) of the row-major tile order.
+struct TileRange {
+    int first, last;
+};
+__device__ __forceinline__ TileRange tile_range(int ntiles) {
+    const int L = xcd_tile(blockIdx.x, gridDim.x);
+    const int per = ntiles / gridDim.x, extra = ntiles % gridDim.x;
+    const int first = L * per + (L < extra ? L : extra);
+    return {first, first + per + (L < extra ? 1 : 0)};
+}
+
+// F = (Phi - phi)/dt - Delta_d mu_d - src, plus one partial sum of F^2 per block.
+// Persistent blocks walk their tiles; the halo of the next tile is loaded into registers
+// while the current one is computed from LDS.
 __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Phi,
                                                    const double* __restrict__ phi,
                                                    const double* __restrict__ src,
@@ -50,48 +80,73 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
     __shared__ double sl[TY + 4][TX + 4];     // Delta_d u, halo 2
     __shared__ double sm[TY + 2][TX + 2];     // cubic term q, then mu_d, halo 1
     __shared__ double red[NT / 64];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
+    const TileRange tr = tile_range(ntx * nty);
+    const int tid = threadIdx.x;
     const bool big = p.nx >= TX + 6 && p.ny >= TY + 6;   // one wrap step suffices
-
-    for (int e = tid; e < (TY + 6) * (TX + 6); e += NT) {
-        const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
-        const int gy = big ? wrap1(y0 + ly - 3, p.ny) : wrap(y0 + ly - 3, p.ny);
-        const int gx = big ? wrap1(x0 + lx - 3, p.nx) : wrap(x0 + lx - 3, p.nx);
-        const long gi = (long)gy * p.nx + gx;
-        const double a = Phi[gi], b = phi[gi];
-        su[ly][lx] = 0.5 * (a + b);
-        const int qy = ly - 2, qx = lx - 2;
-        if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2)
-            sm[qy][qx] = 0.25 * (a * a * a + a * a * b + a * b * b + b * b * b);
-    }
-    __syncthreads();
-    for (int e = tid; e < (TY + 4) * (TX + 4); e += NT) {
-        const int ly = e / (TX + 4), lx = e - ly * (TX + 4);
-        sl[ly][lx] = LAP2(su, ly + 1, lx + 1);
-    }
-    __syncthreads();
-    for (int e = tid; e < (TY + 2) * (TX + 2); e += NT) {
-        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
-        const double l = sl[ly + 1][lx + 1];
-        sm[ly][lx] += (1.0 - p.gamma) * su[ly + 2][lx + 2] + 2.0 * l + LAP2(sl, ly + 1, lx + 1);
-    }
-    __syncthreads();
+    double ra[NIT3], rb[NIT3];
+    auto load = [&](int tile) {
+        const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+#pragma unroll
+        for (int k = 0; k < NIT3; ++k) {
+            const int e = tid + k * NT;
+            if (e < NE3) {
+                const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
+                const int gy = big ? wrap1(y0 + ly - 3, p.ny) : wrap(y0 + ly - 3, p.ny);
+                const int gx = big ? wrap1(x0 + lx - 3, p.nx) : wrap(x0 + lx - 3, p.nx);
+                const long gi = (long)gy * p.nx + gx;
+                ra[k] = Phi[gi];
+                rb[k] = phi[gi];
+            }
+        }
+    };
     double acc = 0.0;
-    for (int e = tid; e < TY * TX; e += NT) {
-        const int ly = e / TX, lx = e - ly * TX;
-        const int gx = x0 + lx, gy = y0 + ly;
-        const double lm = LAP2(sm, ly + 1, lx + 1);
-        if (gx < p.nx && gy < p.ny) {
-            const long gi = (long)gy * p.nx + gx;
-            double f = (Phi[gi] - phi[gi]) * p.inv_dt - lm;     // re-read: these lines are in L2
-            if (src) f -= src[gi];
-            F[gi] = f;
-            acc += f * f;
+    if (tr.first < tr.last) load(tr.first);
+    for (int tile = tr.first; tile < tr.last; ++tile) {
+        const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+        __syncthreads();                      // the previous tile is done with the LDS arrays
+#pragma unroll
+        for (int k = 0; k < NIT3; ++k) {
+            const int e = tid + k * NT;
+            if (e < NE3) {
+                const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
+                const double a = ra[k], b = rb[k];
+                su[ly][lx] = 0.5 * (a + b);
+                const int qy = ly - 2, qx = lx - 2;
+                if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2)
+                    sm[qy][qx] = 0.25 * (a * a * a + a * a * b + a * b * b + b * b * b);
+            }
+        }
+        if (tile + 1 < tr.last) load(tile + 1);   // in flight during the passes below
+        __syncthreads();
+        for (int e = tid; e < (TY + 4) * (TX + 4); e += NT) {
+            const int ly = e / (TX + 4), lx = e - ly * (TX + 4);
+            sl[ly][lx] = LAP2(su, ly + 1, lx + 1);
+        }
+        __syncthreads();
+        for (int e = tid; e < (TY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const double l = sl[ly + 1][lx + 1];
+            sm[ly][lx] += (1.0 - p.gamma) * su[ly + 2][lx + 2] + 2.0 * l + LAP2(sl, ly + 1, lx + 1);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NIT0; ++k) {
+            const int e = tid + k * NT;
+            const int ly = e / TX, lx = e - ly * TX;
+            const int gx = x0 + lx, gy = y0 + ly;
+            if (e < TY * TX && gx < p.nx && gy < p.ny) {
+                const long gi = (long)gy * p.nx + gx;
+                double f = (Phi[gi] - phi[gi]) * p.inv_dt - LAP2(sm, ly + 1, lx + 1);   // re-read: in L2
+                if (src) f -= src[gi];
+                F[gi] = f;
+                acc += f * f;
+            }
         }
     }
     if (part) {
         const double s = block_sum_det(acc, red);
-        if (tid == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+        if (tid == 0) part[blockIdx.x] = s;
     }
 }
 
@@ -108,22 +163,39 @@ __global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
     __shared__ double sl[TY + 4][TX + 4];
     __shared__ double sn[TY + 2][TX + 2];     // c, then the inner operator, halo 1
     __shared__ double red[NT / 64];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    const int ntx = (p.nx + TX - 1) / TX;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, tid = threadIdx.x;
     double sh = 0.0;
     if (shift_part) {
         sh = shift_scale * sum_partials_bcast(shift_part, shift_n, red);
-        if (shift_out && tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) *shift_out = sh;
+        if (shift_out && tid == 0 && blockIdx.x == 0) *shift_out = sh;
     }
     const bool big = p.nx >= TX + 6 && p.ny >= TY + 6;
 
-    for (int e = tid; e < (TY + 6) * (TX + 6); e += NT) {
-        const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
-        const int gy = big ? wrap1(y0 + ly - 3, p.ny) : wrap(y0 + ly - 3, p.ny);
-        const int gx = big ? wrap1(x0 + lx - 3, p.nx) : wrap(x0 + lx - 3, p.nx);
-        const long gi = (long)gy * p.nx + gx;
-        sv[ly][lx] = v[gi] - sh;
-        const int qy = ly - 2, qx = lx - 2;
-        if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2) sn[qy][qx] = cc[gi];
+    double rv[NIT3], rc[NIT3];
+#pragma unroll
+    for (int k = 0; k < NIT3; ++k) {
+        const int e = tid + k * NT;
+        if (e < NE3) {
+            const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
+            const int gy = big ? wrap1(y0 + ly - 3, p.ny) : wrap(y0 + ly - 3, p.ny);
+            const int gx = big ? wrap1(x0 + lx - 3, p.nx) : wrap(x0 + lx - 3, p.nx);
+            const long gi = (long)gy * p.nx + gx;
+            rv[k] = v[gi];
+            const int qy = ly - 2, qx = lx - 2;
+            rc[k] = (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2) ? cc[gi] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NIT3; ++k) {
+        const int e = tid + k * NT;
+        if (e < NE3) {
+            const int ly = e / (TX + 6), lx = e - ly * (TX + 6);
+            sv[ly][lx] = rv[k] - sh;
+            const int qy = ly - 2, qx = lx - 2;
+            if (qy >= 0 && qy < TY + 2 && qx >= 0 && qx < TX + 2) sn[qy][qx] = rc[k];
+        }
     }
     __syncthreads();
     for (int e = tid; e < (TY + 4) * (TX + 4); e += NT) {
@@ -138,11 +210,13 @@ __global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
                      0.5 * LAP2(sl, ly + 1, lx + 1) + sn[ly][lx] * vv;
     }
     __syncthreads();
-    for (int e = tid; e < TY * TX; e += NT) {
+#pragma unroll
+    for (int k = 0; k < NIT0; ++k) {
+        const int e = tid + k * NT;
         const int ly = e / TX, lx = e - ly * TX;
         const int gx = x0 + lx, gy = y0 + ly;
-        const double ln = LAP2(sn, ly + 1, lx + 1);
-        if (gx < p.nx && gy < p.ny) Jv[(long)gy * p.nx + gx] = sv[ly + 3][lx + 3] * p.inv_dt - ln;
+        if (e < TY * TX && gx < p.nx && gy < p.ny)
+            Jv[(long)gy * p.nx + gx] = sv[ly + 3][lx + 3] * p.inv_dt - LAP2(sn, ly + 1, lx + 1);
     }
 }
 
@@ -151,7 +225,9 @@ __global__ __launch_bounds__(NT) void k_energy2d(const double* __restrict__ phi,
                                                  double* __restrict__ part, P p) {
     __shared__ double s[TY + 2][TX + 2];
     __shared__ double red[NT / 64];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    const int ntx = (p.nx + TX - 1) / TX;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY, tid = threadIdx.x;
     for (int e = tid; e < (TY + 2) * (TX + 2); e += NT) {
         const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
         s[ly][lx] = phi[(long)wrap(y0 + ly - 1, p.ny) * p.nx + wrap(x0 + lx - 1, p.nx)];
@@ -170,7 +246,7 @@ __global__ __launch_bounds__(NT) void k_energy2d(const double* __restrict__ phi,
             em += f;
         }
     }
-    const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int nb = gridDim.x, b = blockIdx.x;
     const double sg = block_sum_det(eg, red);
     if (tid == 0) part[b] = sg;
     const double sm = block_sum_det(em, red);
@@ -312,24 +388,25 @@ P make_params(const pfc_ctx* c, double dt) {
     return p;
 }
 
-dim3 tiles2d(const pfc_ctx* c) { return dim3((c->g.nx + TX - 1) / TX, (c->g.ny + TY - 1) / TY); }
+dim3 tiles2d(const pfc_ctx* c) { return dim3(((c->g.nx + TX - 1) / TX) * ((c->g.ny + TY - 1) / TY)); }
+// persistent grid of the residual: four resident blocks per CU (LDS-limited) on 256 CUs
+dim3 residual_grid(const pfc_ctx* c) {
+    const unsigned t = tiles2d(c).x;
+    return dim3(t < 1024u ? t : 1024u);
+}
 dim3 mp_grid(const pfc_ctx* c) { return dim3((c->g.nx + 63) / 64, (c->g.ny + 3) / 4, c->g.nz); }
 
 }  // namespace
 
-int residual_partial_count(const pfc_ctx* c) {
-    if (c->g.dim == 2) {
-        dim3 g = tiles2d(c);
-        return g.x * g.y;
-    }
-    return kRedBlocks;
-}
+int residual_partial_count(const pfc_ctx* c) { return c->g.dim == 2 ? (int)residual_grid(c).x : kRedBlocks; }
+
+int energy_partial_count(const pfc_ctx* c) { return c->g.dim == 2 ? (int)tiles2d(c).x : kRedBlocks; }
 
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
                            const double* src, double* F, double* norm_part) {
     const P p = make_params(c, dt);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_residual2d, tiles2d(c), dim3(NT), 0, c->stream, Phi, phi, src, F, norm_part, p);
+        hipLaunchKernelGGL(k_residual2d, residual_grid(c), dim3(NT), 0, c->stream, Phi, phi, src, F, norm_part, p);
         return hipGetLastError();
     }
     double* u = c->d_tmp3;

@@ -195,6 +195,39 @@ def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None):
     return res
 
 
+def batch_bench(steps, workers_list=(1, 16)):
+    """64 independent instances of uneven size (sides 128..512, gamma 0.1..0.4, mean
+    -0.35..-0.2, noise 0.05, h = pi/2), FP32 ILU(0) subdomain solves of 64^2-owned boxes,
+    extrapolated guess, adaptive dt: instance-steps/s with 1 and with several host workers."""
+    import torch
+    import paper_1703_01202_amd as pfc
+    import pfc_inputs as I
+    ws = I.batch_instances(64)
+    insts = [dict(shape=w.shape, lengths=w.lengths, gamma=w.gamma, sub=w.sub, overlap=w.overlap, dt_min=w.dt_min,
+                  dt_max=w.dt_max, eta=w.eta, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol,
+                  lin_rtol=w.lin_rtol, lin_atol=w.lin_atol, precond_fp32=True, guess="extrap") for w in ws]
+    dof = sum(w.shape[0] * w.shape[1] for w in ws)
+    out = {"instances": len(ws), "dof_total": dof, "steps": steps,
+           "sides": sorted(set(int(w.shape[0]) for w in ws)), "runs": {}}
+    for nw in workers_list:
+        b = pfc.Batch(insts, workers=nw)
+        phis = [torch.from_numpy(w.initial()).cuda() for w in ws]
+        b.step(phis)                                       # warm-up step (first factorisations)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        newton = 0
+        for _ in range(steps):
+            newton += sum(st["newton_its"] for st in b.step(phis))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        b.close()
+        out["runs"][str(nw)] = {"workers": nw, "seconds": el, "instance_steps_per_s": len(ws) * steps / el,
+                                "dof_steps_per_s": dof * steps / el, "newton_its": newton}
+        print(f"[bench] batch workers={nw}: {len(ws) * steps / el:.1f} instance-steps/s", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +237,8 @@ def main():
     ap.add_argument("--compare", default="plain", help="second variant timed beside (or 'none')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -226,6 +261,7 @@ def main():
     if args.compare != "none" and args.compare != args.variant:
         cmp_res = run_variant(args.compare, args.steps, args.warmup, net=net, net_meta=net_meta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
+    batch = None if args.no_batch else batch_bench(args.batch_steps)
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
@@ -256,6 +292,8 @@ def main():
                           "roofline": cmp_res["roofline"],
                           "speedup": main_res["steps_per_s"] / cmp_res["steps_per_s"]}
         out["detail"][args.compare] = cmp_res
+    if batch is not None:
+        out["detail"]["batch_64_ragged"] = batch
     print(json.dumps(out), flush=True)
 
 

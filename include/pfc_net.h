@@ -73,8 +73,12 @@ pfc_status pfc_net_adam(pfc_net* net, double lr, double beta1, double beta2, dou
 
 /* Attach a trained network to a solver context for PFC_GUESS_LEARNED (2-D grids only;
  * PFC_EUNSUP otherwise).  scales = {s_a, s_b, s_o}; dt_train is the time step of the
- * training data.  The context keeps the pointer, not a copy: the network must outlive
- * its use, and NULL detaches it. */
+ * training data.  Allocates the context's own inference buffers (~0.4 KB per cell), so
+ * several contexts, on different streams and host threads, may share one network; it
+ * prepares the network's inference copy of its parameters (synchronising the network's
+ * stream).  The context keeps the pointer, not a copy: the network must outlive its use
+ * and must not be trained while attached (a step then fails with PFC_EINVAL until the
+ * network is attached again).  NULL detaches. */
 pfc_status pfc_attach_net(pfc_ctx* ctx, pfc_net* net, const double* scales, double dt_train);
 
 #ifdef __cplusplus

@@ -13,13 +13,55 @@ import ctypes
 from . import _lib
 from ._lib import PfcError, PfcStepStats
 
-__all__ = ["Solver", "GuessNet", "PfcError", "PfcStepStats", "load"]
+__all__ = ["Solver", "GuessNet", "Batch", "PfcError", "PfcStepStats", "load"]
 
 load = _lib.load
 
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precond_fp32=False, dt_min=0.1,
+             dt_max=None, eta=0.0, newton_rtol=1e-8, newton_atol=1e-10, lin_rtol=1e-3, lin_atol=1e-11,
+             gmres_restart=30, gmres_maxit=300, newton_maxit=50, guess="previous", mass_project=True,
+             max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True):
+    """pfc_grid, pfc_model and pfc_opts for a grid given in array-axis order."""
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    if dim not in (2, 3):
+        raise ValueError("shape must be 2-D or 3-D")
+    g = _lib.PfcGrid()
+    g.dim = dim
+    rev = list(reversed(shape))
+    revL = list(reversed([float(x) for x in lengths]))
+    revS = list(reversed([int(x) for x in sub]))
+    for a in range(3):
+        g.n[a] = rev[a] if a < dim else 1
+        g.L[a] = revL[a] if a < dim else 1.0
+    m = _lib.PfcModel()
+    m.gamma = float(gamma)
+    m.mobility = 0
+    o = _lib.PfcOpts()
+    lib.pfc_default_opts(ctypes.byref(o))
+    o.newton_rtol, o.newton_atol = newton_rtol, newton_atol
+    o.lin_rtol, o.lin_atol = lin_rtol, lin_atol
+    o.newton_maxit, o.gmres_restart, o.gmres_maxit = newton_maxit, gmres_restart, gmres_maxit
+    for a in range(3):
+        o.sub[a] = revS[a] if a < dim else 1
+    o.overlap = int(overlap)
+    o.sub_solver = _lib.SUB_SOLVERS[sub_solver]
+    o.precond_fp32 = int(bool(precond_fp32))
+    o.mass_project = int(bool(mass_project))
+    o.guess = _lib.GUESS[guess]
+    o.dt_min = float(dt_min)
+    o.dt_max = float(dt_max if dt_max is not None else dt_min)
+    o.eta = float(eta)
+    o.max_retries = int(max_retries)
+    o.timing = int(bool(timing))
+    o.precond_lag = int(precond_lag)
+    o.newton_rel_ref = int(bool(newton_rel_ref))
+    return g, m, o
 
 
 class Solver:
@@ -29,47 +71,17 @@ class Solver:
     ``sub`` (subdomains per axis) too.  ``overlap`` is in mesh layers.
     """
 
-    def __init__(self, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precond_fp32=False,
-                 dt_min=0.1, dt_max=None, eta=0.0, newton_rtol=1e-8, newton_atol=1e-10,
-                 lin_rtol=1e-3, lin_atol=1e-11, gmres_restart=30, gmres_maxit=300, newton_maxit=50,
-                 guess="previous", mass_project=True, max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True, stream=None):
+    def __init__(self, shape, lengths, gamma, sub, overlap, stream=None, **options):
+        """Options (keywords, defaults as in pfc_default_opts unless given): sub_solver
+        ("ilu0" | "lu"), precond_fp32, dt_min (0.1), dt_max (= dt_min), eta, newton_rtol,
+        newton_atol, lin_rtol, lin_atol, gmres_restart, gmres_maxit, newton_maxit, guess
+        ("previous" | "extrap" | "learned"), mass_project, max_retries, timing, precond_lag,
+        newton_rel_ref."""
         import torch
         self._torch = torch
         self.lib = _lib.load()
         self.shape = tuple(int(s) for s in shape)
-        dim = len(self.shape)
-        if dim not in (2, 3):
-            raise ValueError("shape must be 2-D or 3-D")
-        g = _lib.PfcGrid()
-        g.dim = dim
-        rev = list(reversed(self.shape))
-        revL = list(reversed([float(x) for x in lengths]))
-        revS = list(reversed([int(x) for x in sub]))
-        for a in range(3):
-            g.n[a] = rev[a] if a < dim else 1
-            g.L[a] = revL[a] if a < dim else 1.0
-        m = _lib.PfcModel()
-        m.gamma = float(gamma)
-        m.mobility = 0
-        o = _lib.PfcOpts()
-        self.lib.pfc_default_opts(ctypes.byref(o))
-        o.newton_rtol, o.newton_atol = newton_rtol, newton_atol
-        o.lin_rtol, o.lin_atol = lin_rtol, lin_atol
-        o.newton_maxit, o.gmres_restart, o.gmres_maxit = newton_maxit, gmres_restart, gmres_maxit
-        for a in range(3):
-            o.sub[a] = revS[a] if a < dim else 1
-        o.overlap = int(overlap)
-        o.sub_solver = _lib.SUB_SOLVERS[sub_solver]
-        o.precond_fp32 = int(bool(precond_fp32))
-        o.mass_project = int(bool(mass_project))
-        o.guess = _lib.GUESS[guess]
-        o.dt_min = float(dt_min)
-        o.dt_max = float(dt_max if dt_max is not None else dt_min)
-        o.eta = float(eta)
-        o.max_retries = int(max_retries)
-        o.timing = int(bool(timing))
-        o.precond_lag = int(precond_lag)
-        o.newton_rel_ref = int(bool(newton_rel_ref))
+        g, m, o = _structs(self.lib, self.shape, lengths, gamma, sub, overlap, **options)
         self.opts = o
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
@@ -243,6 +255,74 @@ class GuessNet:
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pfc_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent instances of uneven size stepped together (``include/pfc_batch.h``).
+
+    ``instances`` is a list of dicts with the ``Solver`` arguments (shape, lengths, gamma,
+    sub, overlap and option keywords); ``workers`` host threads drive them.
+    """
+
+    def __init__(self, instances, workers=8):
+        self.lib = _lib.load()
+        n = len(instances)
+        G = (_lib.PfcGrid * n)()
+        M = (_lib.PfcModel * n)()
+        O = (_lib.PfcOpts * n)()
+        self.shapes = []
+        for i, inst in enumerate(instances):
+            kw = dict(inst)
+            shape, lengths, gamma = kw.pop("shape"), kw.pop("lengths"), kw.pop("gamma")
+            sub, overlap = kw.pop("sub"), kw.pop("overlap")
+            G[i], M[i], O[i] = _structs(self.lib, shape, lengths, gamma, sub, overlap, **kw)
+            self.shapes.append(tuple(int(x) for x in shape))
+        h = ctypes.c_void_p()
+        st = self.lib.pfc_batch_create(n, G, M, O, int(workers), ctypes.byref(h))
+        if st != _lib.PFC_OK:
+            raise PfcError(st, "pfc_batch_create failed (see stderr)")
+        self.handle = h
+        self.count = n
+
+    def _check(self, status):
+        if status != _lib.PFC_OK:
+            raise PfcError(status, self.lib.pfc_batch_last_error(self.handle).decode())
+
+    def step(self, phis):
+        """Advance every instance one step; phis: list of float64 CUDA tensors (in/out)."""
+        import torch
+        if len(phis) != self.count:
+            raise ValueError("one field per instance")
+        for t, shp in zip(phis, self.shapes):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                    and tuple(t.shape) == shp):
+                raise ValueError(f"fields must be contiguous float64 CUDA tensors of shapes {self.shapes}")
+        torch.cuda.current_stream().synchronize()          # the batch runs on its own streams
+        ptrs = (ctypes.c_void_p * self.count)(*[t.data_ptr() for t in phis])
+        st = (PfcStepStats * self.count)()
+        codes = (ctypes.c_int * self.count)()
+        self._check(self.lib.pfc_batch_step(self.handle, ptrs, st, codes))
+        return [s.as_dict() for s in st]
+
+    def reset(self):
+        self._check(self.lib.pfc_batch_reset(self.handle))
+
+    def attach_net(self, net, scales, dt_train):
+        sc = (ctypes.c_double * 3)(*[float(v) for v in scales])
+        self._check(self.lib.pfc_batch_attach_net(self.handle, net.handle if net is not None else None, sc,
+                                                  float(dt_train)))
+        self._net = net
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pfc_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

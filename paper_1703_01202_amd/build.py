@@ -8,11 +8,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["stencil.hip", "blas.hip", "ras_ilu.hip", "ras_lu.hip", "net.hip", "solver.hip"]
+SOURCES = ["stencil.hip", "blas.hip", "ras_ilu.hip", "ras_lu.hip", "net.hip", "solver.hip", "batch.hip"]
 LIB = os.path.join(HERE, "libpfc.so")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]

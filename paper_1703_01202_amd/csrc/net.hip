@@ -562,20 +562,27 @@ unsigned conv_grid(int ny, int nx) {   // blocks walk the tiles: at most 1024 bl
 }
 
 // forward pass on stream s: activations a1..a3 (kept for a backward pass), output in y_out
-pfc_status forward_impl(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* y_out) {
+// the four layers on stream s with activations in a1..a3 (parameters already prepared)
+pfc_status forward_into(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* y_out, float* a1,
+                        float* a2, float* a3) {
     const long HW = (long)ny * nx;
-    pfc_status st = ensure(net, HW);
+    hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, a1, ny, nx);
+    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, a1, pack_of(net, 0),
+                       net->d_q + OFF_B2, nullptr, a2, ny, nx);
+    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
+                       net->d_q + OFF_B3, nullptr, a3, ny, nx);
+    hipLaunchKernelGGL(k_out_fwd, dim3(tile_count(ny, nx)), dim3(256), 0, s, a3, net->d_q, y_out, ny, nx);
+    NETCHK(hipGetLastError());
+    return PFC_OK;
+}
+
+// forward pass on stream s with the network's own activation buffers (kept for a backward pass)
+pfc_status forward_impl(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* y_out) {
+    pfc_status st = ensure(net, (long)ny * nx);
     if (st != PFC_OK) return st;
     st = prepare(net, s);
     if (st != PFC_OK) return st;
-    hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, net->a1, ny, nx);
-    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->a1, pack_of(net, 0),
-                       net->d_q + OFF_B2, nullptr, net->a2, ny, nx);
-    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->a2, pack_of(net, 2),
-                       net->d_q + OFF_B3, nullptr, net->a3, ny, nx);
-    hipLaunchKernelGGL(k_out_fwd, dim3(tile_count(ny, nx)), dim3(256), 0, s, net->a3, net->d_q, y_out, ny, nx);
-    NETCHK(hipGetLastError());
-    return PFC_OK;
+    return forward_into(net, s, x, ny, nx, y_out, net->a1, net->a2, net->a3);
 }
 
 template <int G, int A>
@@ -593,15 +600,27 @@ pfc_status wgrad(pfc_net* net, const float* g, const float* a, int ny, int nx, i
 namespace pfc {
 // for the solver: learned initial guess X = phi + s_o * net(x(phi, prev)), before the mass shift
 pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
-                     double ratio, const double* scales, const double* sum_part, int np, float* xbuf, float* ybuf,
+                     double ratio, const double* scales, const double* sum_part, int np, const NetWork& w,
                      double* X) {
     const long n = (long)ny * nx;
+    if (!net->prepared) {
+        net->err = "network parameters changed since pfc_attach_net: attach it again";
+        return PFC_EINVAL;
+    }
     hipLaunchKernelGGL(k_net_input, dim3(grid_for(n)), dim3(256), 0, s, phi, prev, n, ratio, 1.0 / scales[0],
-                       1.0 / scales[1], sum_part, np, xbuf);
-    pfc_status st = forward_impl(net, s, xbuf, ny, nx, ybuf);
+                       1.0 / scales[1], sum_part, np, w.x);
+    const size_t act = (size_t)WID * n;
+    pfc_status st = forward_into(net, s, w.x, ny, nx, w.y, w.a, w.a + act, w.a + 2 * act);
     if (st != PFC_OK) return st;
-    hipLaunchKernelGGL(k_net_guess, dim3(grid_for(n)), dim3(256), 0, s, phi, ybuf, scales[2], X, n);
+    hipLaunchKernelGGL(k_net_guess, dim3(grid_for(n)), dim3(256), 0, s, phi, w.y, scales[2], X, n);
     NETCHK(hipGetLastError());
+    return PFC_OK;
+}
+
+pfc_status net_prepare(pfc_net* net) {
+    pfc_status st = prepare(net, net->stream);
+    if (st != PFC_OK) return st;
+    NETCHK(hipStreamSynchronize(net->stream));
     return PFC_OK;
 }
 

@@ -55,12 +55,13 @@ struct KernelTimer {
     double total_ms[4] = {0, 0, 0, 0};
 };
 
-// ---- learned initial guess (net.hip) ----
-// X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)); before the mass shift
-pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
-                     double ratio, const double* scales, const double* sum_part, int np, float* xbuf, float* ybuf,
-                     double* X);
-const char* net_error(const pfc_net* net);
+// Inference buffers of one solver context for the learned guess (the network's parameters
+// are shared read-only, so contexts on different streams and threads can use one network).
+struct NetWork {
+    float* x = nullptr;    // input planes [2][N]
+    float* y = nullptr;    // output [N]
+    float* a = nullptr;    // three activation buffers of 32 channels x N (16 bytes per 4 channels)
+};
 
 }  // namespace pfc
 
@@ -122,8 +123,7 @@ struct pfc_ctx {
     pfc_net* net = nullptr;
     double net_scale[3] = {1.0, 1.0, 1.0};   // s_a, s_b, s_o
     double net_dt = 0.0;                     // time step of the training data
-    float* d_netx = nullptr;                 // network input planes [2][N]
-    float* d_nety = nullptr;                 // network output [N]
+    pfc::NetWork netw;                       // inference buffers
 
     pfc::KernelTimer timer;
 };
@@ -175,10 +175,13 @@ hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
 
 // ---- learned initial guess (net.hip) ----
-// X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)); before the mass shift
+// X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)), using the buffers w;
+// before the mass shift.  The network must be prepared (net_prepare) and not trained meanwhile.
 pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
-                     double ratio, const double* scales, const double* sum_part, int np, float* xbuf, float* ybuf,
+                     double ratio, const double* scales, const double* sum_part, int np, const NetWork& w,
                      double* X);
+// Round and pack the current parameters for inference (synchronises the network's stream).
+pfc_status net_prepare(pfc_net* net);
 const char* net_error(const pfc_net* net);
 
 }  // namespace pfc

@@ -415,7 +415,7 @@ pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
 void free_all(pfc_ctx* c) {
     void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, c->d_fac, c->d_flag, c->d_c,
                     c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
-                    c->d_tmp3, c->d_part, c->d_scal, c->d_netx, c->d_nety};
+                    c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.y, c->netw.a};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_pin) hipHostFree(c->h_pin);
@@ -448,7 +448,7 @@ pfc_status make_guess(pfc_ctx* c, const double* phi, double dt, int used) {
         double* part = part_md1(c);
         HIPCHK(launch_dot(c->stream, phi, nullptr, N, part));
         pfc_status s = net_guess(c->net, c->stream, phi, c->d_prev, c->g.ny, c->g.nx, dt / c->dt_nm1, c->net_scale,
-                                 part, kRedBlocks, c->d_netx, c->d_nety, c->d_X);
+                                 part, kRedBlocks, c->netw, c->d_X);
         if (s != PFC_OK) return fail(c, s, std::string("learned guess: ") + net_error(c->net));
     }
     if (c->opts.mass_project) {   // restore the mass of phi^n exactly: X += mean(phi - X)
@@ -796,11 +796,14 @@ pfc_status pfc_attach_net(pfc_ctx* c, pfc_net* net, const double* scales, double
     if (c->g.dim != 2) return fail(c, PFC_EUNSUP, "the learned guess is built for 2-D grids");
     if (!scales || !(scales[0] > 0) || !(scales[1] > 0) || !(scales[2] > 0) || !(dt_train > 0))
         return fail(c, PFC_EINVAL, "scales and dt_train must be positive");
-    if (!c->d_netx) {
-        if (hipMalloc((void**)&c->d_netx, sizeof(float) * 2 * (size_t)c->g.N) != hipSuccess ||
-            hipMalloc((void**)&c->d_nety, sizeof(float) * (size_t)c->g.N) != hipSuccess)
-            return fail(c, PFC_ENOMEM, "out of device memory for the network planes");
+    if (!c->netw.x) {
+        const size_t N = (size_t)c->g.N;
+        if (hipMalloc((void**)&c->netw.x, sizeof(float) * 2 * N) != hipSuccess ||
+            hipMalloc((void**)&c->netw.y, sizeof(float) * N) != hipSuccess ||
+            hipMalloc((void**)&c->netw.a, sizeof(float) * 3 * PFC_NET_WIDTH * N) != hipSuccess)
+            return fail(c, PFC_ENOMEM, "out of device memory for the network buffers");
     }
+    if (net_prepare(net) != PFC_OK) return fail(c, PFC_EHIP, std::string("network: ") + net_error(net));
     c->net = net;
     for (int i = 0; i < 3; ++i) c->net_scale[i] = scales[i];
     c->net_dt = dt_train;

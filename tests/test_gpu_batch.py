@@ -1,0 +1,62 @@
+"""Batched ragged instances (include/pfc_batch.h): stepping many independent grids of uneven
+size from several host threads gives, instance by instance, exactly what stepping each one
+alone gives (same kernels, same reduction orders, only other streams)."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pfc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1703_01202_amd as m
+    return m
+
+
+def _instances():
+    from pfc_inputs import noise_ic
+    out = []
+    for i, (n, gamma, mean) in enumerate([(64, 0.25, -0.30), (96, 0.15, -0.25), (128, 0.35, -0.28),
+                                          (64, 0.30, -0.32), (160, 0.20, -0.22)]):
+        L = n * math.pi / 2
+        inst = dict(shape=(n, n), lengths=(L, L), gamma=gamma, sub=(n // 32, n // 32), overlap=2,
+                    dt_min=1e-2, dt_max=10.0, eta=5000.0, precond_fp32=True, guess="extrap")
+        out.append((inst, noise_ic((n, n), mean, 0.05, 3000 + i)))
+    return out
+
+
+def test_batch_matches_instances_stepped_alone(pfc):
+    insts = _instances()
+    batch = pfc.Batch([i for i, _ in insts], workers=3)
+    phis = [torch.from_numpy(p0).cuda() for _, p0 in insts]
+    batch_stats = [batch.step(phis) for _ in range(4)]
+    for k, (inst, p0) in enumerate(insts):
+        kw = dict(inst)
+        shape, lengths, gamma, sub, ov = (kw.pop(x) for x in ("shape", "lengths", "gamma", "sub", "overlap"))
+        s = pfc.Solver(shape, lengths, gamma, sub, ov, **kw)
+        phi = torch.from_numpy(p0).cuda()
+        for step in range(4):
+            st = s.step(phi)
+            assert st["newton_its"] == batch_stats[step][k]["newton_its"]
+            assert st["dt"] == batch_stats[step][k]["dt"]
+        assert torch.equal(phi, phis[k]), k
+        s.close()
+    batch.close()
+
+
+def test_batch_rejects_a_bad_instance_and_bad_fields(pfc):
+    insts = _instances()
+    bad = dict(insts[0][0])
+    bad["sub"] = (3, 3)                                # 3 does not divide 64
+    with pytest.raises(pfc.PfcError):
+        pfc.Batch([insts[1][0], bad], workers=2)
+    batch = pfc.Batch([insts[0][0]], workers=1)
+    with pytest.raises(ValueError):
+        batch.step([torch.zeros((8, 8), dtype=torch.float64, device="cuda")])
+    batch.close()

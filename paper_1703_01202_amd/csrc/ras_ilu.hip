@@ -106,15 +106,15 @@ __device__ __forceinline__ bool inbox(const Box& b, int x, int y, int z) {
     return x >= 0 && x < b.ex && y >= 0 && y < b.ey && z >= 0 && z < b.ez;
 }
 
-template <typename T>
+template <typename T, int S>
 __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ cc,
                                                     const int* __restrict__ lptr,
                                                     const int* __restrict__ lpts,
                                                     const int8_t* __restrict__ pair, double* __restrict__ work,
                                                     T* __restrict__ fac, int* __restrict__ flag, Box b,
                                                     StencilTable st, int nlev) {
-    __shared__ int8_t spair[kMaxStencil * kMaxStencil];
-    const int S = st.S, D = st.diag;
+    __shared__ int8_t spair[S * S];
+    constexpr int D = S / 2;                  // the zero offset sits in the middle (natural order)
     const int k = blockIdx.x;
     int ox, oy, oz;
     box_origin(b, k, &ox, &oy, &oz);
@@ -137,20 +137,31 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ c
             const int x = pk & 255, y = (pk >> 8) & 255, z = pk >> 16;
             const long i = ((long)z * b.ey + y) * b.ex + x;
             double* row = W + i * S;
+            // the row being eliminated lives in registers; the unrolled loops let every load
+            // of the earlier (pivot) rows it needs be in flight together
+            double r[S];
+            bool in[S];
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                r[t] = row[t];
+                in[t] = inbox(b, x + st.dx[t], y + st.dy[t], z + st.dz[t]);
+            }
+#pragma unroll
             for (int s = 0; s < D; ++s) {
-                if (!inbox(b, x + st.dx[s], y + st.dy[s], z + st.dz[s])) continue;
+                if (!in[s]) continue;
                 const long kk = i + ((long)st.dz[s] * b.ey + st.dy[s]) * b.ex + st.dx[s];
                 const double* rk = W + kk * S;
-                const double aik = row[s] / rk[D];
-                row[s] = aik;
+                const double aik = r[s] / rk[D];
+                r[s] = aik;
+#pragma unroll
                 for (int t = s + 1; t < S; ++t) {
                     const int u = spair[s * S + t];
-                    if (u < 0) continue;
-                    if (!inbox(b, x + st.dx[t], y + st.dy[t], z + st.dz[t])) continue;
-                    row[t] -= aik * rk[u];
+                    if (u >= 0 && in[t]) r[t] -= aik * rk[u];
                 }
             }
-            const double piv = row[D];
+#pragma unroll
+            for (int t = 0; t < S; ++t) row[t] = r[t];
+            const double piv = r[D];
             if (!(piv != 0.0) || !isfinite(piv)) *flag = 1;
         }
         __syncthreads();
@@ -171,56 +182,117 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ c
     }
 }
 
-template <typename T>
+// One wave per box: forward then backward substitution over the wavefront levels with the
+// box vector in LDS.  The stencil size is a template parameter so each row's factor loads
+// are unrolled, and the next level's row index and factors are fetched into registers
+// while the current level is computed (a level has at most 64 rows on the first pass;
+// larger levels take the remaining rows with direct loads).
+template <typename T, int S>
 __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, double* __restrict__ z,
                                                   const T* __restrict__ fac, const int* __restrict__ lptr,
                                                   const int* __restrict__ lpts, Box b, StencilTable st,
                                                   int nlev, double* __restrict__ sum_part) {
     extern __shared__ unsigned char smem_raw[];
     T* yv = reinterpret_cast<T*>(smem_raw);
-    const int S = st.S, D = st.diag;
+    constexpr int D = S / 2;                  // centre of the natural-order stencil
+    const int tid = threadIdx.x;
     const int k = blockIdx.x;
     int ox, oy, oz;
     box_origin(b, k, &ox, &oy, &oz);
-    for (int i = threadIdx.x; i < b.next; i += blockDim.x) {
+    for (int i = tid; i < b.next; i += blockDim.x) {
         const int x = i % b.ex, y = (i / b.ex) % b.ey, zz = i / (b.ex * b.ey);
         yv[i] = (T)r[gidx(b, ox, oy, oz, x, y, zz)];
     }
     __syncthreads();
     const T* F = fac + (long)k * b.next * S;
-    for (int lev = 0; lev < nlev; ++lev) {
-        const int p0 = lptr[lev], nl = lptr[lev + 1] - p0;
-        const T* base = F + (long)p0 * S;
-        for (int p = threadIdx.x; p < nl; p += blockDim.x) {
-            const int pk = lpts[p0 + p];
-            const int x = pk & 255, y = (pk >> 8) & 255, zc = pk >> 16;
-            const int i = (zc * b.ey + y) * b.ex + x;
-            T acc = yv[i];
-            for (int s = 0; s < D; ++s) {
-                const int xx = x + st.dx[s], yy = y + st.dy[s], zz = zc + st.dz[s];
-                const int j = inbox(b, xx, yy, zz) ? (zz * b.ey + yy) * b.ex + xx : i;
-                acc -= base[s * nl + p] * yv[j];
-            }
-            yv[i] = acc;
+    // row update: acc = yv[i] - sum_s f[s] yv[i + off(s)] over s in [s0, s0 + D)
+    auto update = [&](int pk, const T* f, int s0, bool scale_diag, T dinv) {
+        const int x = pk & 255, y = (pk >> 8) & 255, zc = pk >> 16;
+        const int i = (zc * b.ey + y) * b.ex + x;
+        T acc = yv[i];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const int s = s0 + q;
+            const int xx = x + st.dx[s], yy = y + st.dy[s], zz = zc + st.dz[s];
+            const int j = inbox(b, xx, yy, zz) ? (zz * b.ey + yy) * b.ex + xx : i;
+            acc -= f[q] * yv[j];
         }
-        __syncthreads();
+        yv[i] = scale_diag ? acc * dinv : acc;
+    };
+    // forward sweep (lower factors s < D)
+    {
+        int p0 = lptr[0], nl = lptr[1] - p0, pk = 0;
+        T f[D];
+        if (tid < nl) {
+            pk = lpts[p0 + tid];
+#pragma unroll
+            for (int q = 0; q < D; ++q) f[q] = F[(long)p0 * S + (long)q * nl + tid];
+        }
+        for (int lev = 0; lev < nlev; ++lev) {
+            int p0n = 0, nln = 0, pkn = 0;
+            T fn[D];
+            if (lev + 1 < nlev) {
+                p0n = lptr[lev + 1];
+                nln = lptr[lev + 2] - p0n;
+                if (tid < nln) {
+                    pkn = lpts[p0n + tid];
+#pragma unroll
+                    for (int q = 0; q < D; ++q) fn[q] = F[(long)p0n * S + (long)q * nln + tid];
+                }
+            }
+            if (tid < nl) update(pk, f, 0, false, T(0));
+            for (int p = tid + 64; p < nl; p += 64) {
+                T g[D];
+#pragma unroll
+                for (int q = 0; q < D; ++q) g[q] = F[(long)p0 * S + (long)q * nl + p];
+                update(lpts[p0 + p], g, 0, false, T(0));
+            }
+            __syncthreads();
+            p0 = p0n;
+            nl = nln;
+            pk = pkn;
+#pragma unroll
+            for (int q = 0; q < D; ++q) f[q] = fn[q];
+        }
     }
-    for (int lev = nlev - 1; lev >= 0; --lev) {
-        const int p0 = lptr[lev], nl = lptr[lev + 1] - p0;
-        const T* base = F + (long)p0 * S;
-        for (int p = threadIdx.x; p < nl; p += blockDim.x) {
-            const int pk = lpts[p0 + p];
-            const int x = pk & 255, y = (pk >> 8) & 255, zc = pk >> 16;
-            const int i = (zc * b.ey + y) * b.ex + x;
-            T acc = yv[i];
-            for (int s = D + 1; s < S; ++s) {
-                const int xx = x + st.dx[s], yy = y + st.dy[s], zz = zc + st.dz[s];
-                const int j = inbox(b, xx, yy, zz) ? (zz * b.ey + yy) * b.ex + xx : i;
-                acc -= base[s * nl + p] * yv[j];
-            }
-            yv[i] = acc * base[D * nl + p];
+    // backward sweep (upper factors s > D, then the stored reciprocal diagonal)
+    {
+        int p0 = lptr[nlev - 1], nl = lptr[nlev] - p0, pk = 0;
+        T f[D], dinv = T(0);
+        if (tid < nl) {
+            pk = lpts[p0 + tid];
+#pragma unroll
+            for (int q = 0; q < D; ++q) f[q] = F[(long)p0 * S + (long)(D + 1 + q) * nl + tid];
+            dinv = F[(long)p0 * S + (long)D * nl + tid];
         }
-        __syncthreads();
+        for (int lev = nlev - 1; lev >= 0; --lev) {
+            int p0n = 0, nln = 0, pkn = 0;
+            T fn[D], dn = T(0);
+            if (lev > 0) {
+                p0n = lptr[lev - 1];
+                nln = lptr[lev] - p0n;
+                if (tid < nln) {
+                    pkn = lpts[p0n + tid];
+#pragma unroll
+                    for (int q = 0; q < D; ++q) fn[q] = F[(long)p0n * S + (long)(D + 1 + q) * nln + tid];
+                    dn = F[(long)p0n * S + (long)D * nln + tid];
+                }
+            }
+            if (tid < nl) update(pk, f, D + 1, true, dinv);
+            for (int p = tid + 64; p < nl; p += 64) {
+                T g[D];
+#pragma unroll
+                for (int q = 0; q < D; ++q) g[q] = F[(long)p0 * S + (long)(D + 1 + q) * nl + p];
+                update(lpts[p0 + p], g, D + 1, true, F[(long)p0 * S + (long)D * nl + p]);
+            }
+            __syncthreads();
+            p0 = p0n;
+            nl = nln;
+            pk = pkn;
+            dinv = dn;
+#pragma unroll
+            for (int q = 0; q < D; ++q) f[q] = fn[q];
+        }
     }
     // restricted extension: write only the owned cells
     const int owx = b.ownx, owy = b.owny, owz = b.nz > 1 ? b.ownz : 1;
@@ -285,36 +357,58 @@ void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<in
         }
 }
 
-hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& st) {
-    const Box b = make_box(c);
+template <int S>
+hipError_t launch_ilu_factor_s(pfc_ctx* c, const StencilTable& st, const Box& b) {
     if (c->opts.precond_fp32)
-        hipLaunchKernelGGL(k_ilu_factor<float>, dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c, c->d_level_ptr,
-                           c->d_level_pts, c->d_pair, c->d_work, (float*)c->d_fac, c->d_flag, b, st, c->nlev);
+        hipLaunchKernelGGL((k_ilu_factor<float, S>), dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c,
+                           c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, (float*)c->d_fac, c->d_flag, b, st,
+                           c->nlev);
     else
-        hipLaunchKernelGGL(k_ilu_factor<double>, dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c, c->d_level_ptr,
-                           c->d_level_pts, c->d_pair, c->d_work, (double*)c->d_fac, c->d_flag, b, st, c->nlev);
+        hipLaunchKernelGGL((k_ilu_factor<double, S>), dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c,
+                           c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, (double*)c->d_fac, c->d_flag, b,
+                           st, c->nlev);
     return hipGetLastError();
 }
 
-hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {
+hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& st) {
     const Box b = make_box(c);
+    if (st.diag != st.S / 2) return hipErrorInvalidValue;   // natural order puts the centre in the middle
+    if (st.S == 25) return launch_ilu_factor_s<25>(c, st, b);
+    if (st.S == 63) return launch_ilu_factor_s<63>(c, st, b);
+    return hipErrorInvalidValue;
+}
+
+template <int S>
+hipError_t launch_ilu_apply_s(pfc_ctx* c, const double* r, double* z, double* sum_part, const Box& b) {
     const StencilTable& st = c->st;
     if (c->opts.precond_fp32) {
         const size_t sh = sizeof(float) * b.next;
-        hipLaunchKernelGGL(k_ilu_apply<float>, dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
+        hipLaunchKernelGGL((k_ilu_apply<float, S>), dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
                            (const float*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
     } else {
         const size_t sh = sizeof(double) * b.next;
-        hipLaunchKernelGGL(k_ilu_apply<double>, dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
+        hipLaunchKernelGGL((k_ilu_apply<double, S>), dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
                            (const double*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
     }
     return hipGetLastError();
 }
 
+hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {
+    const Box b = make_box(c);
+    if (c->st.diag != c->st.S / 2) return hipErrorInvalidValue;
+    if (c->st.S == 25) return launch_ilu_apply_s<25>(c, r, z, sum_part, b);
+    if (c->st.S == 63) return launch_ilu_apply_s<63>(c, r, z, sum_part, b);
+    return hipErrorInvalidValue;
+}
+
 hipError_t set_ilu_lds_limits() {
-    hipError_t e = set_dynamic_lds_limit((const void*)k_ilu_apply<double>);
-    if (e != hipSuccess) return e;
-    return set_dynamic_lds_limit((const void*)k_ilu_apply<float>);
+    const void* fs[] = {(const void*)k_ilu_apply<double, 25>, (const void*)k_ilu_apply<float, 25>,
+                        (const void*)k_ilu_apply<double, 63>, (const void*)k_ilu_apply<float, 63>};
+    for (const void* f : fs) {
+        const hipError_t e = set_dynamic_lds_limit(f);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace pfc

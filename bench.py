@@ -199,6 +199,37 @@ def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None):
     return res
 
 
+def run_3d(steps):
+    """128^3 noise workload on [0, 40 pi]^3 (gamma 0.56, mean -0.2 + U(+-0.1)), adaptive dt
+    0.1..10 (eta 500): FGMRES with FP32 ILU(0) subdomain solves on 8 x 8 x 8 boxes, overlap 2,
+    FP64 residual / Arnoldi / energy, extrapolated guess, factors lagged up to 10 steps."""
+    import torch
+    import paper_1703_01202_amd as pfc
+    import pfc_inputs as I
+    w = I.noise_3d_128()
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, precond_fp32=True, guess="extrap",
+                   dt_min=w.dt_min, dt_max=w.dt_max, eta=w.eta, newton_rtol=w.newton_rtol,
+                   newton_atol=w.newton_atol, lin_rtol=w.lin_rtol, lin_atol=w.lin_atol, precond_lag=10, timing=True)
+    phi = torch.from_numpy(w.initial()).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [s.step(phi) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {k: s.kernel_time(k) for k in range(4)}
+    s.close()
+    e = [st["energy"] for st in stats]
+    m = [st["mass"] for st in stats]
+    N = w.shape[0] * w.shape[1] * w.shape[2]
+    out = {"workload": "pfc3d_128_noise", "steps": steps, "seconds": el, "steps_per_s": steps / el,
+           "dof_steps_per_s": N * steps / el, "newton_its": sum(st["newton_its"] for st in stats),
+           "gmres_its": sum(st["gmres_its"] for st in stats), "rejected": sum(st["rejected"] for st in stats),
+           "t_end": stats[-1]["t"], "dt_last": stats[-1]["dt"], "energy_monotone": all(b <= a for a, b in zip(e, e[1:])),
+           "mass_drift_rel": max(abs(x - m[0]) for x in m) / abs(m[0]), "kernels": kt}
+    print(f"[bench] 3-D 128^3: {steps / el:.1f} steps/s", file=sys.stderr, flush=True)
+    return out
+
+
 def batch_bench(steps, workers_list=(1, 16)):
     """64 independent instances of uneven size (sides 128..512, gamma 0.1..0.4, mean
     -0.35..-0.2, noise 0.05, h = pi/2), adaptive dt, extrapolated guess, exact subdomain LU
@@ -244,6 +275,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
+    ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device-to-device copy first (reference for HBM counters)")
@@ -268,6 +301,7 @@ def main():
         cmp_res = run_variant(args.compare, args.steps, args.warmup, net=net, net_meta=net_meta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
     batch = None if args.no_batch else batch_bench(args.batch_steps)
+    three_d = None if args.no_3d else run_3d(args.steps_3d)
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
@@ -300,6 +334,8 @@ def main():
         out["detail"][args.compare] = cmp_res
     if batch is not None:
         out["detail"]["batch_64_ragged"] = batch
+    if three_d is not None:
+        out["detail"]["pfc3d_128_noise"] = three_d
     print(json.dumps(out), flush=True)
 
 

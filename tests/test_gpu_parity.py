@@ -263,6 +263,32 @@ def test_trajectory_small_noise_10_steps():
     s.close()
 
 
+def test_trajectory_3d_noise_fp32_ilu():
+    """3-D: 24^3 grid at the mesh size of the 128^3 workload (h = 40 pi / 128), gamma 0.56,
+    mean -0.2 + U(+-0.1); FP32 ILU(0) subdomain solves in FGMRES, 2 x 2 x 2 boxes, overlap 2,
+    4 steps of dt = 0.1, Newton to 1e-10: the oracle trajectory (FFT-preconditioned GMRES
+    Newton) to 1e-10, mass to 1e-12, energy non-increasing."""
+    pfc = _pfc()
+    n = 24
+    L = 40 * math.pi * n / 128
+    shape, lengths = (n, n, n), (L, L, L)
+    h = S.spacing(shape, lengths)
+    phi0 = I.noise_ic(shape, -0.2, 0.1, 7)
+    ref = S.run(phi0, 4, 0.56, h, 0.1, 0.1, linear="fftgmres")
+    s = pfc.Solver(shape, lengths, 0.56, (2, 2, 2), 2, precond_fp32=True, dt_min=0.1, newton_rtol=0.0,
+                   newton_atol=1e-10, guess="extrap")
+    phi = T(phi0)
+    m0 = S.mass(phi0, h)
+    e_prev = S.free_energy(phi0, 0.56, h)
+    for k in range(4):
+        st = s.step(phi)
+        assert rel(N(phi), ref.phis[k + 1]) < 1e-10, k
+        assert abs(st["mass"] - m0) <= 1e-12 * abs(m0)
+        assert st["energy"] <= e_prev + 1e-10 * abs(e_prev)
+        e_prev = st["energy"]
+    s.close()
+
+
 @pytest.mark.parametrize("lag,fp32,guess", [(5, False, "previous"), (20, True, "extrap")])
 def test_trajectory_lagged_factors_fp32_extrapolation(lag, fp32, guess):
     """Factors kept across steps, FP32 factors and extrapolated guesses change the work,

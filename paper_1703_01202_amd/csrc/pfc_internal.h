@@ -105,6 +105,7 @@ struct pfc_ctx {
     double* d_part = nullptr;          // partials summed on the device (Gram-Schmidt, apply sums)
     double* d_scal = nullptr;          // device scalars, then partials summed on the host
     double* h_pin = nullptr;           // pinned host mirror of d_scal
+    double* h_y = nullptr;             // pinned staging of the FGMRES update coefficients
     int n_scal = 0;                    // doubles in d_scal / h_pin
 
     // time history
@@ -142,8 +143,9 @@ inline hipError_t set_dynamic_lds_limit(const void* f) {
 // Reductions leave per-block partials (device_reduce.h); partial_count gives their number.
 int residual_partial_count(const pfc_ctx* c);   // blocks of the residual kernel
 int energy_partial_count(const pfc_ctx* c);     // blocks of the energy kernel (two partials each)
+// F and per-block partials of ||F||^2 (norm_part) and of ||Phi||^2 (xnorm_part); both nullable
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
-                           const double* src, double* F, double* norm_part);
+                           const double* src, double* F, double* norm_part, double* xnorm_part);
 hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, double* cbuf);
 // Jv of (v - s), s = shift_scale * sum(shift_part[0..shift_n)) (no shift if shift_part is null);
 // s is stored in *shift_out when given.

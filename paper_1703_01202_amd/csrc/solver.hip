@@ -137,7 +137,7 @@ pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, doubl
                          double* F, double* nrm) {
     int ts;
     timer_begin(c, 1, &ts);
-    HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_scal + SC_P : nullptr));
+    HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_scal + SC_P : nullptr, nullptr));
     timer_end(c, ts);
     if (!nrm) return PFC_OK;
     const int np = residual_partial_count(c);
@@ -216,14 +216,16 @@ pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
 
 // Right-preconditioned flexible GMRES(m) from x = 0 on J x = b (Sec. 4, Eq. (21)).
 // Classical Gram-Schmidt with one re-orthogonalisation pass; Givens rotations on the host.
+// bnorm_in >= 0 is ||b|| when the caller knows it (saves one synchronisation).  Returns with
+// work still enqueued: the caller synchronises before reading x on the host.
 pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol, double atol, int* its,
-                  double* res_out) {
+                  double* res_out, double bnorm_in = -1.0) {
     const long N = c->g.N;
     const int m = c->opts.gmres_restart;
     const int maxit = c->opts.gmres_maxit;
     const bool proj = c->opts.mass_project;
-    double bnorm;
-    CHK(norm2(c, b, &bnorm));
+    double bnorm = bnorm_in;
+    if (bnorm < 0.0) CHK(norm2(c, b, &bnorm));
     const double target = std::max(rtol * bnorm, atol);
     HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
     *its = 0;
@@ -309,11 +311,13 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
         if (proj)
             for (int i = 0; i < jdone; ++i) shift += y[i] * c->h_pin[SC_M + i];
         y[SC_SHIFT - SC_Y] = shift;
-        HIPCHK(hipMemcpyAsync(c->d_scal + SC_Y, y.data(), sizeof(double) * (SC_SHIFT - SC_Y + 1),
-                              hipMemcpyHostToDevice, c->stream));
+        // staged through pinned memory: the copy runs asynchronously, and h_y is not written
+        // again before a later synchronisation (the next cycle's or the caller's norm)
+        std::copy(y.begin(), y.end(), c->h_y);
+        HIPCHK(hipMemcpyAsync(c->d_scal + SC_Y, c->h_y, sizeof(double) * (SC_SHIFT - SC_Y + 1), hipMemcpyHostToDevice,
+                              c->stream));
         HIPCHK(launch_maxpy(c->stream, Z, N, jdone, c->d_scal + SC_Y, 1, 1.0, x, N, nullptr, nullptr));
         if (proj) HIPCHK(launch_shift(c->stream, x, c->d_scal + SC_SHIFT, 1, -1.0, N));
-        CHK(sync(c));   // y lives in host memory until the copy has run
         if (conv || total >= maxit) break;
     }
     *its = total;
@@ -330,22 +334,37 @@ double residual_floor(const pfc_ctx* c, double dt, double xnorm) {
     return 2.220446049250313e-16 * op * xnorm;
 }
 
-// ||F(phi^n)||: the residual of the paper's initial guess Phi_0 = phi^n, the reference of the
-// relative Newton test when opts.newton_rel_ref is set (uses d_r as scratch).
-pfc_status reference_norm(pfc_ctx* c, const double* phi, double dt, double* out) {
-    return residual_impl(c, phi, phi, dt, nullptr, c->d_r, out);
+// First evaluation of a solve, one synchronisation: F = F(X) into d_F with ||F|| and ||X||
+// (for the rounding floor) and, with want_ref, the reference ||F(phi^n)|| of the relative
+// test (the residual of the paper's initial guess Phi_0 = phi^n; d_r is its scratch).
+pfc_status first_residual(pfc_ctx* c, const double* phi, double dt, bool want_ref, double* fn, double* xnorm,
+                          double* fref) {
+    const int np = residual_partial_count(c);
+    double* part = c->d_scal + SC_P;
+    int ts;
+    timer_begin(c, 1, &ts);
+    if (want_ref) HIPCHK(launch_residual(c, phi, phi, dt, nullptr, c->d_r, part + 2 * np, nullptr));
+    HIPCHK(launch_residual(c, c->d_X, phi, dt, nullptr, c->d_F, part, part + np));
+    timer_end(c, ts);
+    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, part, sizeof(double) * (want_ref ? 3 : 2) * np, hipMemcpyDeviceToHost,
+                          c->stream));
+    CHK(sync(c));
+    *fn = std::sqrt(host_sum(c, 0, np));
+    *xnorm = std::sqrt(host_sum(c, np, np));
+    *fref = want_ref ? std::sqrt(host_sum(c, 2 * np, np)) : *fn;
+    if (!std::isfinite(*fn) || !std::isfinite(*fref)) return fail(c, PFC_ENAN, "non-finite residual norm");
+    return PFC_OK;
 }
 
 // Newton from the iterate in d_X.  The stop test of Eq. (20) is
-// ||F|| <= max(eps_r * fref, eps_a, rounding floor) with fref = ||F(Phi_0)|| unless a
-// reference fref >= 0 is given.
+// ||F|| <= max(eps_r * fref, eps_a, rounding floor) with fref = ||F(Phi_0)||, or with
+// want_ref the reference ||F(phi^n)|| (returned in *fref_out when given).
 pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats* st, bool reuse = false,
-                       double fref = -1.0) {
+                       bool want_ref = false, double* fref_out = nullptr) {
     const long N = c->g.N;
-    double fn, xnorm;
-    CHK(residual_impl(c, c->d_X, phi, dt, nullptr, c->d_F, &fn));
-    CHK(norm2(c, c->d_X, &xnorm));
-    if (fref < 0.0) fref = fn;
+    double fn, xnorm, fref;
+    CHK(first_residual(c, phi, dt, want_ref, &fn, &xnorm, &fref));
+    if (fref_out) *fref_out = fref;
     const double target = std::max({c->opts.newton_rtol * fref, c->opts.newton_atol, residual_floor(c, dt, xnorm)});
     st->res0 = fn;
     st->newton_its = 0;
@@ -363,7 +382,7 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
         HIPCHK(launch_scale(c->stream, c->d_F, -1.0, c->d_T, N));
         int its = 0;
         double lres = 0;
-        pfc_status s = fgmres(c, c->d_T, c->d_S, dt, c->opts.lin_rtol, c->opts.lin_atol, &its, &lres);
+        pfc_status s = fgmres(c, c->d_T, c->d_S, dt, c->opts.lin_rtol, c->opts.lin_atol, &its, &lres, fn);
         st->gmres_its += its;
         if (s != PFC_OK && s != PFC_EKRYLOV) return s;
         // backtracking line search on ||F||
@@ -419,6 +438,7 @@ void free_all(pfc_ctx* c) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_pin) hipHostFree(c->h_pin);
+    if (c->h_y) hipHostFree(c->h_y);
     for (auto e : c->timer.pool) hipEventDestroy(e);
 }
 
@@ -591,7 +611,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     A(dalloc(c, &c->d_Z, (size_t)m * N));
     if (dim == 3) A(dalloc(c, &c->d_tmp3, 2 * (size_t)N));
     A(dalloc(c, &c->d_part, 128 * (size_t)kRedBlocks + 64 * (size_t)c->dec.nsub));
-    c->n_scal = SC_P + std::max({kRedBlocks, residual_partial_count(c), 2 * energy_partial_count(c)});
+    c->n_scal = SC_P + std::max({kRedBlocks, 3 * residual_partial_count(c), 2 * energy_partial_count(c)});
     A(dalloc(c, &c->d_scal, (size_t)c->n_scal));
     A(dalloc(c, &c->d_flag, 1));
     if (op->sub_solver == PFC_SUB_ILU0) {
@@ -619,7 +639,8 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (s == PFC_OK) {
         if (hipMalloc(&c->d_fac, esz * c->fac_elems) != hipSuccess) s = fail(c, PFC_ENOMEM, "factor allocation failed");
     }
-    if (s == PFC_OK && hipHostMalloc((void**)&c->h_pin, sizeof(double) * c->n_scal) != hipSuccess)
+    if (s == PFC_OK && (hipHostMalloc((void**)&c->h_pin, sizeof(double) * c->n_scal) != hipSuccess ||
+                        hipHostMalloc((void**)&c->h_y, sizeof(double) * (SC_SHIFT - SC_Y + 1)) != hipSuccess))
         s = fail(c, PFC_ENOMEM, "pinned allocation failed");
     if (s == PFC_OK && (set_ilu_lds_limits() != hipSuccess || set_lu_lds_limits() != hipSuccess))
         s = fail(c, PFC_EHIP, "cannot raise the LDS limit");
@@ -677,17 +698,18 @@ pfc_status pfc_gmres(pfc_ctx* c, const double* Phi, const double* phi, double dt
         return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
     HIPCHK(launch_coef(c, Phi, phi, c->d_c));
     HIPCHK(hipMemcpyAsync(c->d_w, b, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
-    return fgmres(c, c->d_w, x, dt, rtol, atol, its, res);
+    const pfc_status s = fgmres(c, c->d_w, x, dt, rtol, atol, its, res);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return s;
 }
 
 pfc_status pfc_newton(pfc_ctx* c, const double* phi, double dt, double* Phi, pfc_step_stats* st) {
     if (!c || !phi || !Phi || !st || !(dt > 0)) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
     std::memset(st, 0, sizeof(*st));
-    double fref = -1.0;
-    if (c->opts.newton_rel_ref) CHK(reference_norm(c, phi, dt, &fref));
+    double fref = 0.0;
     HIPCHK(hipMemcpyAsync(c->d_X, Phi, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
-    pfc_status s = newton_impl(c, phi, dt, st, false, fref);
-    st->res_ref = fref >= 0.0 ? fref : st->res0;
+    pfc_status s = newton_impl(c, phi, dt, st, false, c->opts.newton_rel_ref != 0, &fref);
+    st->res_ref = fref;
     HIPCHK(hipMemcpyAsync(Phi, c->d_X, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     st->dt = dt;
@@ -716,11 +738,11 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
         CHK(make_guess(c, phi, dt, used));
         pfc_step_stats tmp;
         std::memset(&tmp, 0, sizeof(tmp));
-        double fref = -1.0;
-        if (o.newton_rel_ref && used != PFC_GUESS_PREVIOUS) CHK(reference_norm(c, phi, dt, &fref));
+        double fref = 0.0;
+        const bool want_ref = o.newton_rel_ref && used != PFC_GUESS_PREVIOUS;
         const bool reuse = may_reuse_factors(c, dt);
         const long fac_before = c->fac_step;
-        s = newton_impl(c, phi, dt, &tmp, reuse, fref);
+        s = newton_impl(c, phi, dt, &tmp, reuse, want_ref, &fref);
         if (s != PFC_OK && reuse && (s == PFC_ENOTCONV || s == PFC_EKRYLOV)) {
             // lagged factors did not do: same dt, fresh factors
             st->newton_its += tmp.newton_its;
@@ -728,7 +750,7 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
             CHK(make_guess(c, phi, dt, used));
             std::memset(&tmp, 0, sizeof(tmp));
             c->fac_valid = false;
-            s = newton_impl(c, phi, dt, &tmp, false, fref);
+            s = newton_impl(c, phi, dt, &tmp, false, want_ref, &fref);
         }
         if (s == PFC_OK && tmp.newton_its > 0) {
             const double gpn = (double)tmp.gmres_its / tmp.newton_its;
@@ -740,7 +762,7 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
         st->ls_cuts += tmp.ls_cuts;
         st->res0 = tmp.res0;
         st->res_final = tmp.res_final;
-        st->res_ref = fref >= 0.0 ? fref : tmp.res0;
+        st->res_ref = fref;
         st->guess_used = used;
         if (s == PFC_OK) break;
         if ((s != PFC_ENOTCONV && s != PFC_EKRYLOV) || attempt >= o.max_retries || dt <= o.dt_min / 16) return s;

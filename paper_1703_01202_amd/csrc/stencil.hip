@@ -68,14 +68,15 @@ __device__ __forceinline__ TileRange tile_range(int ntiles) {
     return {first, first + per + (L < extra ? 1 : 0)};
 }
 
-// F = (Phi - phi)/dt - Delta_d mu_d - src, plus one partial sum of F^2 per block.
+// F = (Phi - phi)/dt - Delta_d mu_d - src, plus one partial sum of F^2 per block (and of
+// Phi^2 in xpart when given).
 // Persistent blocks walk their tiles; the halo of the next tile is loaded into registers
 // while the current one is computed from LDS.
 __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Phi,
                                                    const double* __restrict__ phi,
                                                    const double* __restrict__ src,
                                                    double* __restrict__ F,
-                                                   double* __restrict__ part, P p) {
+                                                   double* __restrict__ part, double* __restrict__ xpart, P p) {
     __shared__ double su[TY + 6][TX + 6];     // u = (Phi + phi)/2, halo 3
     __shared__ double sl[TY + 4][TX + 4];     // Delta_d u, halo 2
     __shared__ double sm[TY + 2][TX + 2];     // cubic term q, then mu_d, halo 1
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
             }
         }
     };
-    double acc = 0.0;
+    double acc = 0.0, accx = 0.0;
     if (tr.first < tr.last) load(tr.first);
     for (int tile = tr.first; tile < tr.last; ++tile) {
         const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
@@ -137,16 +138,22 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
             const int gx = x0 + lx, gy = y0 + ly;
             if (e < TY * TX && gx < p.nx && gy < p.ny) {
                 const long gi = (long)gy * p.nx + gx;
-                double f = (Phi[gi] - phi[gi]) * p.inv_dt - LAP2(sm, ly + 1, lx + 1);   // re-read: in L2
+                const double a = Phi[gi];             // re-read: in L2
+                double f = (a - phi[gi]) * p.inv_dt - LAP2(sm, ly + 1, lx + 1);
                 if (src) f -= src[gi];
                 F[gi] = f;
                 acc += f * f;
+                accx += a * a;
             }
         }
     }
     if (part) {
         const double s = block_sum_det(acc, red);
         if (tid == 0) part[blockIdx.x] = s;
+    }
+    if (xpart) {
+        const double s = block_sum_det(accx, red);
+        if (tid == 0) xpart[blockIdx.x] = s;
     }
 }
 
@@ -403,12 +410,14 @@ int residual_partial_count(const pfc_ctx* c) { return c->g.dim == 2 ? (int)resid
 int energy_partial_count(const pfc_ctx* c) { return c->g.dim == 2 ? (int)tiles2d(c).x : kRedBlocks; }
 
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
-                           const double* src, double* F, double* norm_part) {
+                           const double* src, double* F, double* norm_part, double* xnorm_part) {
     const P p = make_params(c, dt);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_residual2d, residual_grid(c), dim3(NT), 0, c->stream, Phi, phi, src, F, norm_part, p);
+        hipLaunchKernelGGL(k_residual2d, residual_grid(c), dim3(NT), 0, c->stream, Phi, phi, src, F, norm_part,
+                           xnorm_part, p);
         return hipGetLastError();
     }
+    if (xnorm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, Phi, c->g.N, xnorm_part);
     double* u = c->d_tmp3;
     double* Lu = c->d_tmp3 + c->g.N;
     hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, Phi, phi, nullptr, 0, 0.0, nullptr, 0, u,

@@ -30,16 +30,15 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (calibrated against a known-size copy; see profiles/), valid only for the kernel source
 # they were taken on: the sha256 prefix of the source file must match.
-_LU_FP32_24x72 = {"file": "paper_1703_01202_amd/csrc/ras_lu.hip", "sha": "421a0d1982949a3a", "bytes": 1.2231e9}
-MEASURED_TRAFFIC = {   # the fast and learned variants run the same apply kernel on the same boxes
-    ("fast", "ras_apply"): _LU_FP32_24x72,
-    ("learned", "ras_apply"): _LU_FP32_24x72,
+MEASURED_TRAFFIC = {   # keyed by kernel and decomposition: (kernel, sub, overlap, sub_solver, fp32)
+    ("ras_apply", (16, 64), 4, "lu", True): {"file": "paper_1703_01202_amd/csrc/ras_lu.hip",
+                                             "sha": "421a0d1982949a3a", "bytes": 1.2231e9},
 }
 
 
-def measured_traffic(variant, kernel):
+def measured_traffic(v, kernel):
     import hashlib
-    m = MEASURED_TRAFFIC.get((variant, kernel))
+    m = MEASURED_TRAFFIC.get((kernel, tuple(v["sub"]), v["overlap"], v["sub_solver"], v["precond_fp32"]))
     if not m:
         return None
     try:
@@ -102,6 +101,26 @@ def cpu_baseline(nsteps=2):
                       f"Newton + FFT-preconditioned GMRES, scipy/numpy FP64, {el:.1f} s"}
 
 
+def tune_variant(name, net, net_meta, steps=30):
+    """Untimed autotuning of the decomposition and factor lag for a variant (first steps of the
+    same run); returns (best, table)."""
+    import torch
+    import pfc_inputs as I
+    from paper_1703_01202_amd import autotune as A
+    w = I.crystal_growth_1024()
+    v = VARIANTS[name]
+    kw = dict(sub_solver=v["sub_solver"], precond_fp32=v["precond_fp32"], guess=v["guess"], dt_min=w.dt_min,
+              dt_max=w.dt_max, eta=w.eta, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol,
+              lin_rtol=w.lin_rtol, lin_atol=w.lin_atol)
+    cands = [(sub, ov, lag) for sub, ov in A.box_candidates(w.shape) for lag in (20, 50, 100)]
+    phi0 = torch.tensor(w.initial(), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    best, table = A.autotune(w.shape, w.lengths, w.gamma, phi0, kw, cands, steps=steps, net=net,
+                             net_meta=net_meta,
+                             log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    return best, {"candidates": table, "best": best, "seconds": time.perf_counter() - t0, "steps_each": steps}
+
+
 def train_guess_net(cfg):
     """Train the learned-guess network (untimed set-up of the "learned" variant)."""
     import torch
@@ -134,12 +153,14 @@ def train_guess_net(cfg):
     return net, meta
 
 
-def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None):
+def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None, tuned=None):
     import torch
     import paper_1703_01202_amd as pfc
     import pfc_inputs as I
     w = I.crystal_growth_1024()
-    v = VARIANTS[name]
+    v = dict(VARIANTS[name])
+    if tuned:
+        v.update(sub=tuple(tuned["sub"]), overlap=tuned["overlap"], precond_lag=tuned["precond_lag"])
     phi0 = torch.tensor(w.initial(), dtype=torch.float64, device="cuda")
     s = pfc.Solver(w.shape, w.lengths, w.gamma, v["sub"], v["overlap"], sub_solver=v["sub_solver"],
                    precond_fp32=v["precond_fp32"], guess=v["guess"], dt_min=w.dt_min, dt_max=w.dt_max,
@@ -193,7 +214,7 @@ def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None):
     gbs = bytes_per[dom] / avg_s / 1e9 if cnt else 0.0
     res["roofline"] = {"kernel": names[dom], "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                       "traffic": measured_traffic(name, names[dom]),
+                       "traffic": measured_traffic(v, names[dom]),
                        "bytes_per_launch": bytes_per[dom], "avg_launch_us": avg_s * 1e6, "launches": cnt,
                        "factorisation_ms_total": kt[3][1]}
     return res
@@ -275,6 +296,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
+    ap.add_argument("--no-autotune", action="store_true", help="use the variant's fixed decomposition")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -295,7 +317,12 @@ def main():
     net = net_meta = None
     if "learned" in (args.variant, args.compare):
         net, net_meta = train_guess_net(LEARNED_TRAINING)
-    main_res = run_variant(args.variant, args.steps, args.warmup, net=net, net_meta=net_meta)
+    tuned = tune_info = None
+    if not args.no_autotune and VARIANTS[args.variant]["sub_solver"] == "lu" and VARIANTS[args.variant]["precond_fp32"]:
+        tuned, tune_info = tune_variant(args.variant, net, net_meta)
+    main_res = run_variant(args.variant, args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)
+    if tune_info is not None:
+        main_res["autotune"] = tune_info
     cmp_res = None
     if args.compare != "none" and args.compare != args.variant:
         cmp_res = run_variant(args.compare, args.steps, args.warmup, net=net, net_meta=net_meta)

@@ -117,3 +117,13 @@ def test_opts_struct_size_matches_header():
     assert int(out[1]) == _lib.PfcOpts.newton_rel_ref.offset
     assert int(out[2]) == ctypes.sizeof(_lib.PfcStepStats)
     assert int(out[3]) == ctypes.sizeof(_lib.PfcGrid)
+
+
+def test_autotune_box_candidates_tile_the_grid():
+    from paper_1703_01202_amd import autotune as A
+    cands = A.box_candidates((1024, 1024))
+    assert ((16, 64), 4) in cands and ((32, 64), 4) in cands
+    for (sy, sx), ov in cands:
+        assert 1024 % sy == 0 and 1024 % sx == 0
+        assert 1024 // sx + 2 * ov in (24, 40)          # extended box widths asked for
+    assert A.box_candidates((100, 100)) == []            # nothing divides: no candidates

@@ -58,6 +58,9 @@ VARIANTS = {
     # as "fast" with the learned initial guess (include/pfc_net.h), trained before the timed
     # region on solver trajectories of the same physics on 512^2 grids
     "learned": dict(sub=(16, 64), overlap=4, sub_solver="lu", precond_fp32=True, guess="learned", precond_lag=20),
+    # as "learned" with the Arnoldi steps replayed from HIP graphs (own stream)
+    "learned_graph": dict(sub=(16, 64), overlap=4, sub_solver="lu", precond_fp32=True, guess="learned",
+                          precond_lag=20, use_graph=True),
 }
 LEARNED_TRAINING = dict(n=512, trajectories=10, steps=201, epochs=8, lr=3e-3)
 
@@ -155,17 +158,30 @@ def train_guess_net(cfg):
 
 def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None, tuned=None):
     import torch
+    v = dict(VARIANTS[name])
+    if not v.get("use_graph"):
+        return _run_variant(name, v, steps, warmup, timing, net, net_meta, tuned, None)
+    # graph replay needs a stream of its own; per-kernel event timing is off for it
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        res = _run_variant(name, v, steps, warmup, False, net, net_meta, tuned, stream.cuda_stream)
+    stream.synchronize()
+    return res
+
+
+def _run_variant(name, v, steps, warmup, timing, net, net_meta, tuned, stream):
+    import torch
     import paper_1703_01202_amd as pfc
     import pfc_inputs as I
     w = I.crystal_growth_1024()
-    v = dict(VARIANTS[name])
     if tuned:
         v.update(sub=tuple(tuned["sub"]), overlap=tuned["overlap"], precond_lag=tuned["precond_lag"])
     phi0 = torch.tensor(w.initial(), dtype=torch.float64, device="cuda")
     s = pfc.Solver(w.shape, w.lengths, w.gamma, v["sub"], v["overlap"], sub_solver=v["sub_solver"],
                    precond_fp32=v["precond_fp32"], guess=v["guess"], dt_min=w.dt_min, dt_max=w.dt_max,
                    eta=w.eta, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol, lin_rtol=w.lin_rtol,
-                   lin_atol=w.lin_atol, timing=timing, precond_lag=v.get("precond_lag", 0))
+                   lin_atol=w.lin_atol, timing=timing, precond_lag=v.get("precond_lag", 0),
+                   use_graph=v.get("use_graph", False), stream=stream)
     if v["guess"] == "learned":
         s.attach_net(net, net_meta["scales"], net_meta["dt_train"])
     phi = phi0.clone()
@@ -193,7 +209,7 @@ def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None, tuned
                   f"newton={st['newton_its']} gmres={st['gmres_its']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    kt = {k: s.kernel_time(k) for k in range(4)}
+    kt = {k: s.kernel_time(k) for k in range(5)}
     s.close()
     N = w.shape[0] * w.shape[1]
     res = {"steps": steps, "seconds": el, "steps_per_s": steps / el, "dof_steps_per_s": N * steps / el,
@@ -208,6 +224,9 @@ def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None, tuned
     names = {0: "ras_apply", 1: "residual", 2: "jacobian_action", 3: "factorisation"}
     bytes_per = {0: apply_bytes(w.shape, v["sub"], v["overlap"], v["sub_solver"], v["precond_fp32"]),
                  1: 24 * N, 2: 24 * N}
+    if not timing:
+        res["roofline"] = None
+        return res
     dom = max((k for k in (0, 1, 2)), key=lambda k: kt[k][1])
     cnt, ms = kt[dom]
     avg_s = ms / 1e3 / max(cnt, 1)
@@ -297,6 +316,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     ap.add_argument("--no-autotune", action="store_true", help="use the variant's fixed decomposition")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay run of the variant")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -323,6 +343,9 @@ def main():
     main_res = run_variant(args.variant, args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)
     if tune_info is not None:
         main_res["autotune"] = tune_info
+    graph_res = None
+    if not args.no_graph and args.variant == "learned":
+        graph_res = run_variant("learned_graph", args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)
     cmp_res = None
     if args.compare != "none" and args.compare != args.variant:
         cmp_res = run_variant(args.compare, args.steps, args.warmup, net=net, net_meta=net_meta)
@@ -359,6 +382,8 @@ def main():
                           "roofline": cmp_res["roofline"],
                           "speedup": main_res["steps_per_s"] / cmp_res["steps_per_s"]}
         out["detail"][args.compare] = cmp_res
+    if graph_res is not None:
+        out["detail"]["learned_graph"] = graph_res
     if batch is not None:
         out["detail"]["batch_64_ragged"] = batch
     if three_d is not None:

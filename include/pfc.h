@@ -97,6 +97,12 @@ typedef struct {
                                          residual of the paper's initial guess Phi_0 = phi^n, whatever
                                          guess starts the iteration, so every guess meets the same
                                          target; 0: ||F|| at the guess actually used */
+    int use_graph;                    /* 1: each Arnoldi step (preconditioner apply, J v, both Gram-Schmidt
+                                         passes, the copy of the Hessenberg column) is captured once per
+                                         Krylov index and time step size as a HIP graph and replayed with
+                                         one launch; needs a non-default stream (PFC_EINVAL otherwise) and
+                                         is ignored while timing is on.  Results are bitwise those of the
+                                         launches made one by one. */
 } pfc_opts;
 
 /* Per-step statistics.  res0 = ||F|| at the initial guess, res_final at the accepted
@@ -168,7 +174,8 @@ pfc_status pfc_reset(pfc_ctx* ctx);
 
 /* Per-kernel timing (opts.timing = 1): which = 0 preconditioner apply, 1 residual,
  * 2 Jacobian action, 3 factorisation.  Returns the launch count and the summed
- * event-measured duration in milliseconds since the last pfc_reset. */
+ * event-measured duration in milliseconds since the last pfc_reset.  which = 4 gives the
+ * number of Arnoldi-step graph launches (opts.use_graph) and 0 ms. */
 pfc_status pfc_kernel_time(pfc_ctx* ctx, int which, long* count, double* total_ms);
 
 #ifdef __cplusplus

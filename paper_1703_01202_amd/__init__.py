@@ -25,7 +25,7 @@ def _ptr(t):
 def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precond_fp32=False, dt_min=0.1,
              dt_max=None, eta=0.0, newton_rtol=1e-8, newton_atol=1e-10, lin_rtol=1e-3, lin_atol=1e-11,
              gmres_restart=30, gmres_maxit=300, newton_maxit=50, guess="previous", mass_project=True,
-             max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True):
+             max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True, use_graph=False):
     """pfc_grid, pfc_model and pfc_opts for a grid given in array-axis order."""
     shape = tuple(int(s) for s in shape)
     dim = len(shape)
@@ -61,6 +61,7 @@ def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precon
     o.timing = int(bool(timing))
     o.precond_lag = int(precond_lag)
     o.newton_rel_ref = int(bool(newton_rel_ref))
+    o.use_graph = int(bool(use_graph))
     return g, m, o
 
 
@@ -76,7 +77,7 @@ class Solver:
         ("ilu0" | "lu"), precond_fp32, dt_min (0.1), dt_max (= dt_min), eta, newton_rtol,
         newton_atol, lin_rtol, lin_atol, gmres_restart, gmres_maxit, newton_maxit, guess
         ("previous" | "extrap" | "learned"), mass_project, max_retries, timing, precond_lag,
-        newton_rel_ref."""
+        newton_rel_ref, use_graph (needs ``stream``: a non-default stream handle)."""
         import torch
         self._torch = torch
         self.lib = _lib.load()

@@ -40,7 +40,7 @@ class PfcOpts(ctypes.Structure):
         ("guess", ctypes.c_int),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double), ("eta", ctypes.c_double),
         ("max_retries", ctypes.c_int), ("timing", ctypes.c_int), ("precond_lag", ctypes.c_int),
-        ("newton_rel_ref", ctypes.c_int),
+        ("newton_rel_ref", ctypes.c_int), ("use_graph", ctypes.c_int),
     ]
 
 

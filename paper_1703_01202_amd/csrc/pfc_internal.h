@@ -126,6 +126,11 @@ struct pfc_ctx {
     double net_dt = 0.0;                     // time step of the training data
     pfc::NetWork netw;                       // inference buffers
 
+    // HIP graphs of the Arnoldi steps (opts.use_graph): one per Krylov index, valid for arn_dt
+    std::vector<hipGraphExec_t> arn_graph;
+    double arn_dt = -1.0;
+    long graph_launches = 0;
+
     pfc::KernelTimer timer;
 };
 

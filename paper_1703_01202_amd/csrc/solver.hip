@@ -214,6 +214,75 @@ pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
     return PFC_OK;
 }
 
+// One Arnoldi step j of FGMRES, enqueued: z_j = H^-1 v_j, w = J z_j, two classical
+// Gram-Schmidt passes against v_0..v_j (norm partials fused), then the copy of the
+// coefficients and partials to the host.
+pfc_status enqueue_arnoldi_step(pfc_ctx* c, int j, double dt) {
+    const long N = c->g.N;
+    const bool proj = c->opts.mass_project;
+    double* V = c->d_V;
+    double* zj = c->d_Z + (long)j * N;
+    double* w = V + (long)(j + 1) * N;
+    // z_j = H^-1 v_j, kept unprojected; its mean m_j is removed on the fly (Jv load
+    // shift, and once from the update), which is the zero-mean projection of R12
+    double* pj = proj ? part_apply(c, j) : nullptr;
+    CHK(apply_raw(c, V + (long)j * N, zj, pj));
+    CHK(jv_impl(c, zj, dt, pj, c->d_scal + SC_M + j, w));
+    // CGS2: h = V^T w ; w -= V h ; h2 = V^T w ; w -= V h2 (norm fused)
+    HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md1(c)));
+    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, nullptr, c->d_scal + SC_H));
+    HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md2(c)));
+    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_scal + SC_P,
+                        c->d_scal + SC_H2));
+    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal, sizeof(double) * (SC_P + kRedBlocks), hipMemcpyDeviceToHost,
+                          c->stream));
+    return PFC_OK;
+}
+
+void drop_graphs(pfc_ctx* c) {
+    for (hipGraphExec_t& e : c->arn_graph)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    c->arn_dt = -1.0;
+}
+
+// The Arnoldi step, launched eagerly or (opts.use_graph) as a graph captured on first use for
+// this j and dt.  Every kernel argument of the step is fixed for a given j except the 1/dt of
+// J v, so the cache is dropped when dt changes.  If capture fails the context goes on eagerly.
+pfc_status arnoldi_step(pfc_ctx* c, int j, double dt) {
+    if (!c->opts.use_graph || c->opts.timing) return enqueue_arnoldi_step(c, j, dt);
+    if (c->arn_dt != dt) {
+        drop_graphs(c);
+        c->arn_graph.assign(c->opts.gmres_restart, nullptr);
+        c->arn_dt = dt;
+    }
+    if (!c->arn_graph[j]) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        const pfc_status s = enqueue_arnoldi_step(c, j, dt);
+        const hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (s != PFC_OK || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            c->opts.use_graph = 0;
+            c->err.clear();
+            return enqueue_arnoldi_step(c, j, dt);
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            c->opts.use_graph = 0;
+            return enqueue_arnoldi_step(c, j, dt);
+        }
+        c->arn_graph[j] = exec;
+    }
+    HIPCHK(hipGraphLaunch(c->arn_graph[j], c->stream));
+    c->graph_launches++;
+    return PFC_OK;
+}
+
 // Right-preconditioned flexible GMRES(m) from x = 0 on J x = b (Sec. 4, Eq. (21)).
 // Classical Gram-Schmidt with one re-orthogonalisation pass; Givens rotations on the host.
 // bnorm_in >= 0 is ||b|| when the caller knows it (saves one synchronisation).  Returns with
@@ -257,22 +326,8 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
         int jdone = 0;
         bool conv = false;
         for (int j = 0; j < m; ++j) {
-            double* zj = Z + (long)j * N;
             double* w = V + (long)(j + 1) * N;
-            // z_j = H^-1 v_j, kept unprojected; its mean m_j is removed on the fly (Jv load
-            // shift, and once from the update), which is the zero-mean projection of R12
-            double* pj = proj ? part_apply(c, j) : nullptr;
-            CHK(apply_raw(c, V + (long)j * N, zj, pj));
-            CHK(jv_impl(c, zj, dt, pj, c->d_scal + SC_M + j, w));
-            // CGS2: h = V^T w ; w -= V h ; h2 = V^T w ; w -= V h2 (norm fused)
-            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md1(c)));
-            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, nullptr,
-                                c->d_scal + SC_H));
-            HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md2(c)));
-            HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_scal + SC_P,
-                                c->d_scal + SC_H2));
-            HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal, sizeof(double) * (SC_P + kRedBlocks), hipMemcpyDeviceToHost,
-                                  c->stream));
+            CHK(arnoldi_step(c, j, dt));
             CHK(sync(c));
             const double hn = std::sqrt(host_sum(c, 0, kRedBlocks));
             if (!std::isfinite(hn)) return fail(c, PFC_ENAN, "non-finite Arnoldi norm");
@@ -437,6 +492,7 @@ void free_all(pfc_ctx* c) {
                     c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.y, c->netw.a};
     for (void* p : ptrs)
         if (p) hipFree(p);
+    drop_graphs(c);
     if (c->h_pin) hipHostFree(c->h_pin);
     if (c->h_y) hipHostFree(c->h_y);
     for (auto e : c->timer.pool) hipEventDestroy(e);
@@ -505,6 +561,7 @@ void pfc_default_opts(pfc_opts* o) {
     o->timing = 0;
     o->precond_lag = 0;
     o->newton_rel_ref = 1;
+    o->use_graph = 0;
 }
 
 pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* op, void* stream,
@@ -537,6 +594,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (s == PFC_OK && (op->gmres_restart < 1 || op->gmres_restart > 60)) s = bad("gmres_restart must be 1..60");
     if (s == PFC_OK && (op->gmres_maxit < 1 || op->newton_maxit < 1)) s = bad("iteration limits must be >= 1");
     if (s == PFC_OK && op->precond_lag < 0) s = bad("precond_lag must be >= 0");
+    if (s == PFC_OK && op->use_graph && !stream) s = bad("use_graph needs a non-default stream (graph capture)");
     if (s == PFC_OK && op->ras_kind != PFC_RAS_LEFT) s = bad("only left-RAS is built");
     if (s == PFC_OK && op->sub_solver != PFC_SUB_ILU0 && op->sub_solver != PFC_SUB_LU) s = bad("bad sub_solver");
     if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && dim != 2) {
@@ -799,11 +857,17 @@ pfc_status pfc_reset(pfc_ctx* c) {
         c->timer.count[i] = 0;
         c->timer.total_ms[i] = 0.0;
     }
+    c->graph_launches = 0;
     return PFC_OK;
 }
 
 pfc_status pfc_kernel_time(pfc_ctx* c, int which, long* count, double* total_ms) {
-    if (!c || which < 0 || which > 3 || !count || !total_ms) return PFC_EINVAL;
+    if (!c || which < 0 || which > 4 || !count || !total_ms) return PFC_EINVAL;
+    if (which == 4) {
+        *count = c->graph_launches;
+        *total_ms = 0.0;
+        return PFC_OK;
+    }
     *count = c->timer.count[which];
     *total_ms = c->timer.total_ms[which];
     return PFC_OK;

@@ -171,6 +171,12 @@ class Solver:
     def reset(self):
         self._check(self.lib.pfc_reset(self.ctx))
 
+    def checkpoint_save(self, phi, path):
+        self._check(self.lib.pfc_checkpoint_save(self.ctx, self._field(phi, "phi"), str(path).encode()))
+
+    def checkpoint_load(self, phi, path):
+        self._check(self.lib.pfc_checkpoint_load(self.ctx, self._field(phi, "phi"), str(path).encode()))
+
     def attach_net(self, net, scales, dt_train):
         """Use ``net`` (a GuessNet) for ``guess="learned"``; scales = (s_a, s_b, s_o)."""
         sc = (ctypes.c_double * 3)(*[float(v) for v in scales])

@@ -861,6 +861,83 @@ pfc_status pfc_reset(pfc_ctx* c) {
     return PFC_OK;
 }
 
+namespace {
+// checkpoint file: header, then phi (N doubles) and, if have_prev, phi^(n-1) (N doubles)
+struct CkptHeader {
+    char magic[8];                 // "PFCCKPT1"
+    int32_t dim, n[3];
+    double L[3], gamma;
+    int64_t step;
+    double t, F_n, F_nm1, dt_nm1;
+    int32_t have_prev, have_energy;
+};
+const char kMagic[8] = {'P', 'F', 'C', 'C', 'K', 'P', 'T', '1'};
+}  // namespace
+
+pfc_status pfc_checkpoint_save(pfc_ctx* c, const double* phi, const char* path) {
+    if (!c || !phi || !path) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    const size_t N = (size_t)c->g.N;
+    std::vector<double> buf(N * (c->have_prev ? 2 : 1));
+    HIPCHK(hipMemcpyAsync(buf.data(), phi, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+    if (c->have_prev)
+        HIPCHK(hipMemcpyAsync(buf.data() + N, c->d_prev, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+    CHK(sync(c));
+    CkptHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kMagic, 8);
+    h.dim = c->grid.dim;
+    for (int a = 0; a < 3; ++a) {
+        h.n[a] = c->grid.n[a];
+        h.L[a] = c->grid.L[a];
+    }
+    h.gamma = c->model.gamma;
+    h.step = c->step;
+    h.t = c->t;
+    h.F_n = c->F_n;
+    h.F_nm1 = c->F_nm1;
+    h.dt_nm1 = c->dt_nm1;
+    h.have_prev = c->have_prev;
+    h.have_energy = c->have_energy;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(c, PFC_EINVAL, std::string("cannot open ") + path);
+    const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(buf.data(), sizeof(double), buf.size(), f) == buf.size();
+    if (std::fclose(f) != 0 || !ok) return fail(c, PFC_EINVAL, std::string("cannot write ") + path);
+    return PFC_OK;
+}
+
+pfc_status pfc_checkpoint_load(pfc_ctx* c, double* phi, const char* path) {
+    if (!c || !phi || !path) return c ? fail(c, PFC_EINVAL, "bad argument") : PFC_EINVAL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(c, PFC_EINVAL, std::string("cannot open ") + path);
+    CkptHeader h;
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.dim == c->grid.dim &&
+              h.gamma == c->model.gamma && (h.have_prev == 0 || h.have_prev == 1);
+    for (int a = 0; ok && a < 3; ++a) ok = h.n[a] == c->grid.n[a] && h.L[a] == c->grid.L[a];
+    const size_t N = (size_t)c->g.N;
+    std::vector<double> buf;
+    if (ok) {
+        buf.resize(N * (h.have_prev ? 2 : 1));
+        ok = std::fread(buf.data(), sizeof(double), buf.size(), f) == buf.size();
+    }
+    std::fclose(f);
+    if (!ok) return fail(c, PFC_EINVAL, std::string("not a checkpoint of this grid and model: ") + path);
+    HIPCHK(hipMemcpyAsync(phi, buf.data(), sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+    if (h.have_prev)
+        HIPCHK(hipMemcpyAsync(c->d_prev, buf.data() + N, sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+    CHK(sync(c));
+    c->step = h.step;
+    c->t = h.t;
+    c->F_n = h.F_n;
+    c->F_nm1 = h.F_nm1;
+    c->dt_nm1 = h.dt_nm1;
+    c->have_prev = h.have_prev != 0;
+    c->have_energy = h.have_energy != 0;
+    c->fac_valid = false;
+    c->fac_step = -1;
+    c->fac_gpn = c->last_gpn = 0.0;
+    return PFC_OK;
+}
+
 pfc_status pfc_kernel_time(pfc_ctx* c, int which, long* count, double* total_ms) {
     if (!c || which < 0 || which > 4 || !count || !total_ms) return PFC_EINVAL;
     if (which == 4) {

@@ -327,3 +327,32 @@ def test_adaptive_steps_follow_energy_history():
         E.append(S.free_energy(N(phi), w.gamma, h))
         assert abs(st["energy"] - E[-1]) <= 1e-10 * abs(E[-1])
     s.close()
+
+
+def test_checkpoint_restart_continues_exactly(tmp_path):
+    """Save after 3 adaptive steps (extrapolated guess, so phi^(n-1) matters), continue 3 steps;
+    a fresh context loading the checkpoint takes the same 3 steps bitwise."""
+    pfc = _pfc()
+    w = I.small_noise_64()
+    kw = dict(dt_min=w.dt_min, dt_max=1.0, eta=50.0, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol,
+              guess="extrap")
+    s1 = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, **kw)
+    phi = T(w.initial())
+    for _ in range(3):
+        s1.step(phi)
+    path = tmp_path / "pfc.ckpt"
+    s1.checkpoint_save(phi, path)
+    saved = phi.clone()
+    cont = [s1.step(phi) for _ in range(3)]
+    s2 = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, **kw)
+    phi2 = torch.zeros_like(phi)
+    s2.checkpoint_load(phi2, path)
+    assert torch.equal(phi2, saved)
+    rest = [s2.step(phi2) for _ in range(3)]
+    assert torch.equal(phi2, phi)
+    assert [(a["dt"], a["t"], a["newton_its"]) for a in cont] == [(b["dt"], b["t"], b["newton_its"]) for b in rest]
+    other = pfc.Solver(w.shape, w.lengths, w.gamma + 0.01, w.sub, w.overlap, **kw)
+    with pytest.raises(pfc.PfcError):
+        other.checkpoint_load(phi2, path)
+    for s in (s1, s2, other):
+        s.close()

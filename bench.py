@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 # they were taken on: the sha256 prefix of the source file must match.
 MEASURED_TRAFFIC = {   # keyed by kernel and decomposition: (kernel, sub, overlap, sub_solver, fp32)
     ("ras_apply", (16, 64), 4, "lu", True): {"file": "paper_1703_01202_amd/csrc/ras_lu.hip",
-                                             "sha": "421a0d1982949a3a", "bytes": 1.2231e9},
+                                             "sha": "943eb6daba582fbb", "bytes": 1.2233e9},
 }
 
 
@@ -115,7 +115,7 @@ def tune_variant(name, net, net_meta, steps=30):
     kw = dict(sub_solver=v["sub_solver"], precond_fp32=v["precond_fp32"], guess=v["guess"], dt_min=w.dt_min,
               dt_max=w.dt_max, eta=w.eta, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol,
               lin_rtol=w.lin_rtol, lin_atol=w.lin_atol)
-    cands = [(sub, ov, lag) for sub, ov in A.box_candidates(w.shape) for lag in (20, 50, 100)]
+    cands = [(sub, ov, lag) for sub, ov in A.box_candidates(w.shape) for lag in (50, 100)]
     phi0 = torch.tensor(w.initial(), dtype=torch.float64, device="cuda")
     t0 = time.perf_counter()
     best, table = A.autotune(w.shape, w.lengths, w.gamma, phi0, kw, cands, steps=steps, net=net,
@@ -317,6 +317,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     ap.add_argument("--no-autotune", action="store_true", help="use the variant's fixed decomposition")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay run of the variant")
+    ap.add_argument("--train-trajectories", type=int, default=LEARNED_TRAINING["trajectories"])
+    ap.add_argument("--train-epochs", type=int, default=LEARNED_TRAINING["epochs"])
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -336,7 +338,8 @@ def main():
         del src, dst
     net = net_meta = None
     if "learned" in (args.variant, args.compare):
-        net, net_meta = train_guess_net(LEARNED_TRAINING)
+        net, net_meta = train_guess_net(dict(LEARNED_TRAINING, trajectories=args.train_trajectories,
+                                             epochs=args.train_epochs))
     tuned = tune_info = None
     if not args.no_autotune and VARIANTS[args.variant]["sub_solver"] == "lu" and VARIANTS[args.variant]["precond_fp32"]:
         tuned, tune_info = tune_variant(args.variant, net, net_meta)

@@ -15,7 +15,7 @@ import time
 from . import PfcError, Solver
 
 
-def box_candidates(shape, widths=(24, 40), heights=(64, 32), overlaps=(3, 4)):
+def box_candidates(shape, widths=(24, 28, 32, 40), heights=(64, 32), overlaps=(4, 6, 8)):
     """(sub, overlap) pairs whose boxes have the given extended width (x) and owned height (y)."""
     ny, nx = shape
     out = []

@@ -581,6 +581,7 @@ LuBox make_lubox(const pfc_ctx* c, const StencilTable& st) {
 }
 
 // Launch shape of the solve for box width W; NPL covers ceil(4W / G), G = threads / W:
+//   W <= 24: 256 threads, G >= 10 -> NPL 10, prefetch 3 rows (FP32) / 1 row (FP64)  (measured best)
 //   W <= 32: 256 threads, G >= 8  -> NPL 16, prefetch 2 rows (FP32) / 1 row (FP64)
 //   W <= 72: 1024 threads, G >= 14 -> NPL 21, prefetch 1 row (FP32) / none (FP64)
 template <typename T>
@@ -588,10 +589,14 @@ hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b
     constexpr bool f32 = sizeof(T) == 4;
     const int threads = b.W <= 32 ? 256 : 1024;
     const int G = threads / b.W;
+    const int npl = b.W <= 24 ? 10 : (b.W <= 32 ? 16 : 21);
+    if (G * npl < 4 * b.W) return hipErrorInvalidValue;   // a block row's columns must be covered
     const size_t sh = sizeof(T) * ((size_t)b.W * b.H + (size_t)G * b.W);
     const T* f = (const T*)c->d_fac;
     const dim3 grid(c->dec.nsub), blk(threads);
-    if (b.W <= 32)
+    if (b.W <= 24)
+        hipLaunchKernelGGL((k_lu_apply<T, 10, f32 ? 3 : 1>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
+    else if (b.W <= 32)
         hipLaunchKernelGGL((k_lu_apply<T, 16, f32 ? 2 : 1>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
     else
         hipLaunchKernelGGL((k_lu_apply<T, 21, f32 ? 1 : 0>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
@@ -648,6 +653,7 @@ hipError_t set_lu_lds_limits() {
     const void* fns[] = {(const void*)k_lu_factor_lds<double, 24>, (const void*)k_lu_factor_lds<float, 24>,
                          (const void*)k_lu_factor_lds<double, kSmallW>, (const void*)k_lu_factor_lds<float, kSmallW>,
                          (const void*)k_lu_factor_wide<double>, (const void*)k_lu_factor_wide<float>,
+                         (const void*)k_lu_apply<double, 10, 1>, (const void*)k_lu_apply<float, 10, 3>,
                          (const void*)k_lu_apply<double, 16, 1>, (const void*)k_lu_apply<float, 16, 2>,
                          (const void*)k_lu_apply<double, 21, 0>, (const void*)k_lu_apply<float, 21, 1>};
     for (const void* f : fns) {

@@ -181,6 +181,8 @@ def test_ras_ilu0_3d_sampled_subdomains():
     (256, 100.0, (4, 4), 4, 10.0, False, 1e-9),        # 72 x 72 boxes at the 1024^2 mesh size
     (256, 100.0, (4, 16), 4, 10.0, False, 1e-9),       # 24-wide boxes
     (256, 100.0, (4, 16), 4, 10.0, True, 1e-4),
+    (256, 100.0, (4, 16), 8, 10.0, False, 1e-9),       # 32-wide boxes
+    (256, 100.0, (8, 16), 8, 10.0, True, 1e-4),
 ])
 def test_ras_exact_lu_2d(n, L, sub, ov, dt, fp32, tol):
     pfc = _pfc()

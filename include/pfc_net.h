@@ -15,7 +15,9 @@
  *   Convolution weights are rounded to bfloat16 (nearest, ties to even) for every use;
  *   accumulation is FP32; biases and the master weights stay FP32.  The two inner 32 -> 32
  *   layers run on the matrix cores with each FP32 activation split into two bfloat16
- *   parts (so the products carry about 16 significant bits of the activation).
+ *   parts (so the products carry about 16 significant bits of the activation); in a
+ *   forward (inference) pass the output layer is formed the same way, as per-tap sums
+ *   of the third layer's activations that are added up over the 3x3 neighbourhood.
  *   Parameters, flat FP32, PFC_NET_NPARAM of them, in this order:
  *       W1[32][2][3][3] b1[32] W2[32][32][3][3] b2[32] W3[32][32][3][3] b3[32] W4[1][32][3][3] b4[1]
  *   Loss of one sample: mean over cells of (y - t)^2.
@@ -54,7 +56,8 @@ pfc_status pfc_net_set_params(pfc_net* net, const float* host_params);
 pfc_status pfc_net_get_params(pfc_net* net, float* host_params);
 
 /* y = network(x).  x: device [2][ny][nx], y: device [ny][nx]; ny, nx >= 3.  Grows the
- * activation workspace to the largest grid seen (PFC_ENOMEM on failure). */
+ * activation workspace to the largest grid seen (PFC_ENOMEM on failure).  An inference
+ * pass: the activations are not kept (pfc_net_gradient runs its own forward pass). */
 pfc_status pfc_net_forward(pfc_net* net, const float* x, int ny, int nx, float* y);
 
 /* Gradient of scale * loss(network(x), t) with respect to the parameters (taken at the

@@ -35,11 +35,14 @@ constexpr int NPARAM = PFC_NET_NPARAM;
 static_assert(OFF_B4 + 1 == NPARAM, "parameter layout");
 constexpr int KSTEPS = 18;                 // 9 taps x 2 blocks of 16 input channels
 constexpr int PACK = KSTEPS * 64;          // packed A operands (8 bf16 each) per layer and direction
+constexpr int PACK4 = 2 * 64;              // packed A operands of the output layer's tap sums
+constexpr int PACK_ALL = 4 * PACK + PACK4;
 constexpr int WG_BLOCKS = 256;             // fixed grid of the weight-gradient kernels
 constexpr int WG_MAXOUT = WID * WID * 9 + WID;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // staging registers (a native vector stays in VGPRs)
 
 __device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest, ties to even
     unsigned u = __float_as_uint(f);
@@ -50,12 +53,19 @@ __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 __device__ __forceinline__ int wrapm(int i, int n) { return ((i % n) + n) % n; }
 
-// four activations -> hi/lo bf16 pairs in one 16-byte word (see the layout above)
+// four activations -> hi/lo bf16 pairs in one 16-byte word (see the layout above); the
+// conversions are gfx950's packed FP32 -> bf16 instruction (round to nearest, ties to even,
+// the same rounding as f2bf for finite values)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pk_bf16(float a, float b) {
+    const bf16x2 h = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(unsigned, h);
+}
 __device__ __forceinline__ uint4 split4(float a0, float a1, float a2, float a3) {
-    const unsigned h0 = f2bf(a0), h1 = f2bf(a1), h2 = f2bf(a2), h3 = f2bf(a3);
-    const unsigned l0 = f2bf(a0 - bf2f(h0)), l1 = f2bf(a1 - bf2f(h1)), l2 = f2bf(a2 - bf2f(h2)),
-                   l3 = f2bf(a3 - bf2f(h3));
-    return make_uint4(h0 | (h1 << 16), h2 | (h3 << 16), l0 | (l1 << 16), l2 | (l3 << 16));
+    const unsigned h01 = pk_bf16(a0, a1), h23 = pk_bf16(a2, a3);
+    const unsigned l01 = pk_bf16(a0 - __uint_as_float(h01 << 16), a1 - __uint_as_float(h01 & 0xFFFF0000u));
+    const unsigned l23 = pk_bf16(a2 - __uint_as_float(h23 << 16), a3 - __uint_as_float(h23 & 0xFFFF0000u));
+    return make_uint4(h01, h23, l01, l23);
 }
 __device__ __forceinline__ float4 join4(uint4 u) {
     return make_float4(__uint_as_float(u.x << 16) + __uint_as_float(u.z << 16),
@@ -85,6 +95,9 @@ __device__ __forceinline__ bool is_weight_index(int i) {
 // [set][s][lane][e], step s = tap * 2 + j, row m = lane % 32, k = 16 j + 8 (lane / 32) + e:
 //   forward  A[m = out ch][k = in ch] = W[m][k][tap]
 //   backward A[m = in ch][k = out ch] = W[k][m][8 - tap]  (adjoint: swap channels, mirror taps)
+// Then the output layer's operand [j][lane][e] (j = 0, 1), row m = tap (zero for m >= 9):
+//   A[m][k] = W4[c(k)][m],  k = 16 j + 8 h + e,  c(k) = 16 j + 8 (e / 4) + 4 h + e % 4,  h = lane / 32,
+// the channel order in which a lane of the inner layers' accumulator holds its outputs.
 __global__ void k_prepare(const float* __restrict__ theta, float* __restrict__ q, unsigned short* __restrict__ pack) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < NPARAM) q[i] = is_weight_index(i) ? bf2f(f2bf(theta[i])) : theta[i];
@@ -96,6 +109,12 @@ __global__ void k_prepare(const float* __restrict__ theta, float* __restrict__ q
         const int woff = set < 2 ? OFF_W2 : OFF_W3;
         const int idx = (set & 1) ? woff + (k * WID + m) * 9 + (8 - tap) : woff + (m * WID + k) * 9 + tap;
         pack[i] = f2bf(theta[idx]);
+    } else if (i < PACK_ALL * 8) {
+        const int r = i - 4 * PACK * 8;
+        const int j = r / 512, lane = (r / 8) % 64, e = r % 8;
+        const int m = lane % 32, h = lane / 32;
+        const int c = 16 * j + 8 * (e / 4) + 4 * h + e % 4;
+        pack[i] = m < 9 ? f2bf(theta[OFF_W4 + c * 9 + m]) : (unsigned short)0;
     }
 }
 
@@ -148,9 +167,34 @@ __global__ __launch_bounds__(256) void k_in_fwd(const float* __restrict__ x, con
 // contiguous bytes per operand and global memory is read once per tile.
 constexpr int CT_X = 32, CT_Y = 8, CT_R = CT_Y + 2, CT_C = CT_X + 2;
 
+constexpr int ST_N = CT_R * NG * CT_C;        // 16-byte groups of a staged tile
+constexpr int ST_IT = (ST_N + 255) / 256;     // per thread of a 256-thread block
+
+// Halo staging in two phases: each thread issues its ST_IT global loads into registers
+// (tile_load), and only then writes them to LDS (tile_store), so the whole tile is in flight
+// at once; a persistent block loads its next tile while it computes the current one.  The
+// registers are a native vector type, which the compiler keeps in VGPRs (an array of the
+// HIP uint4 class was left in scratch memory).
+// Grids of at least CT_R rows and CT_C columns: every halo index is within [-n, 2n), one
+// select each way wraps it (no division, no branch, so the unrolled loads stay in registers).
+__device__ __forceinline__ void tile_load(u32x4 (&v)[ST_IT], const float* __restrict__ in, long HW, int ny, int nx,
+                                          int y0, int x0) {
+#pragma unroll
+    for (int k = 0; k < ST_IT; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        const int c = e % CT_C, g = (e / CT_C) % NG, r = e / (CT_C * NG);
+        int yy = y0 + r - 1, xx = x0 + c - 1;
+        yy += yy < 0 ? ny : 0;
+        yy -= yy >= ny ? ny : 0;
+        xx += xx < 0 ? nx : 0;
+        xx -= xx >= nx ? nx : 0;
+        if (k < ST_IT - 1 || e < ST_N) v[k] = *reinterpret_cast<const u32x4*>(grp(in, g, HW, (long)yy * nx + xx));
+    }
+}
+// Any grid size, one load at a time (small grids only).
 __device__ __forceinline__ void stage_tile(uint4 (*sm)[NG][CT_C], const float* __restrict__ in, long HW, int ny,
                                            int nx, int y0, int x0) {
-    const bool one_wrap = ny >= CT_R && nx >= CT_C;   // halo indices then stay within [-n, 2n)
+    const bool one_wrap = ny >= CT_R && nx >= CT_C;
     for (int e = threadIdx.x; e < CT_R * NG * CT_C; e += blockDim.x) {
         const int c = e % CT_C, g = (e / CT_C) % NG, r = e / (CT_C * NG);
         const int yy = one_wrap ? wrap1(y0 + r - 1, ny) : wrapm(y0 + r - 1, ny);
@@ -158,16 +202,30 @@ __device__ __forceinline__ void stage_tile(uint4 (*sm)[NG][CT_C], const float* _
         sm[r][g][c] = *grp(in, g, HW, (long)yy * nx + xx);
     }
 }
+__device__ __forceinline__ void tile_store(uint4 (*sm)[NG][CT_C], const u32x4 (&v)[ST_IT]) {
+    u32x4* flat = reinterpret_cast<u32x4*>(&sm[0][0][0]);   // flat index e = (r * NG + g) * CT_C + c
+#pragma unroll
+    for (int k = 0; k < ST_IT; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < ST_N) flat[e] = v[k];
+    }
+}
 
 // inner layers on the matrix cores.  MODE 0: out = tanh(conv(in) + bias) (forward);
-// MODE 1: out = conv(in) * (1 - aux^2) (backward through the previous tanh, aux = its output).
+// MODE 1: out = conv(in) * (1 - aux^2) (backward through the previous tanh, aux = its output);
+// MODE 2: the last inner layer of an inference pass: a = tanh(conv(in) + bias) stays in
+// registers and the output layer's per-tap sums s_t(p) = sum_c W4[c][t] a[c](p) are written
+// instead, out = planar FP32 [9][HW] (a 32x32x16 product with the taps as rows, pack4).
 // Each of the 4 waves computes two rows of 32 cells x 32 output channels of a block tile,
-// reading each of the 4 input rows it needs once for both; blocks walk the tiles so that
-// the 18 A operands stay in registers across tiles.
+// reading each of the 4 input rows it needs once for both.  Persistent blocks walk a
+// tiles with a stride of the grid size (so the tiles in work at any time form one band of the
+// image), with the 18 A operands in registers, loading the next tile's halo while they
+// compute the current one.
 template <int MODE>
 __device__ __forceinline__ void conv32_body(const float* __restrict__ in, const bf16x8* __restrict__ pack,
                                             const float* __restrict__ bias, const float* __restrict__ aux,
-                                            float* __restrict__ out, int ny, int nx) {
+                                            const bf16x8* __restrict__ pack4, float* __restrict__ out, int ny,
+                                            int nx) {
     __shared__ uint4 sm[CT_R][NG][CT_C];
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31, wv = threadIdx.x >> 6;
     const long HW = (long)ny * nx;
@@ -176,12 +234,33 @@ __device__ __forceinline__ void conv32_body(const float* __restrict__ in, const 
     bf16x8 A[KSTEPS];
 #pragma unroll
     for (int s = 0; s < KSTEPS; ++s) A[s] = pack[s * 64 + lane];
+    bf16x8 A4[2];
+    if (MODE == 2) {
+        A4[0] = pack4[lane];
+        A4[1] = pack4[64 + lane];
+    }
+    const bool big = ny >= CT_R && nx >= CT_C;   // block-uniform: two-phase staging applies
+    u32x4 pre[ST_IT];
+    if (big && (int)blockIdx.x < ntiles) {
+        const int ty = blockIdx.x / ntx;
+        tile_load(pre, in, HW, ny, nx, ty * CT_Y, (blockIdx.x - ty * ntx) * CT_X);
+    }
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int ty = tile / ntx, tx = tile - ty * ntx;
         const int x0 = tx * CT_X, y0 = ty * CT_Y;
-        __syncthreads();
-        stage_tile(sm, in, HW, ny, nx, y0, x0);
-        __syncthreads();
+        __syncthreads();                        // LDS reads of the previous tile are done
+        if (big) {
+            tile_store(sm, pre);
+            __syncthreads();
+            const int t1 = tile + gridDim.x;    // next tile's halo, in flight during the compute
+            if (t1 < ntiles) {
+                const int ty1 = t1 / ntx;
+                tile_load(pre, in, HW, ny, nx, ty1 * CT_Y, (t1 - ty1 * ntx) * CT_X);
+            }
+        } else {
+            stage_tile(sm, in, HW, ny, nx, y0, x0);
+            __syncthreads();
+        }
         const int ly0 = 2 * wv;                 // this wave's rows ly0, ly0 + 1 (CT_Y = 8)
         f32x16 acc2[2] = {{}, {}};
 #pragma unroll
@@ -209,11 +288,37 @@ __device__ __forceinline__ void conv32_body(const float* __restrict__ in, const 
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr) {
             const f32x16& acc = acc2[rr];
-            const int ly = ly0 + rr;
-            const int y = y0 + ly, x = x0 + col;
-            if (y >= ny || x >= nx) continue;
+            const int y = y0 + ly0 + rr, x = x0 + col;
+            const bool inside = y < ny && x < nx;
             const long p = (long)y * nx + x;
             // lane holds cell p and output channels 8 (r / 4) + 4 half + r % 4, r = 0..15
+            if (MODE == 2) {
+                float a[16];
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) a[4 * q4 + e] = tanh_fast(acc[4 * q4 + e] + bias[4 * (2 * q4 + half) + e]);
+                // B operand j holds a[8 j .. 8 j + 7], the channel order the pack4 rows assume;
+                // every lane takes part in the product, only cells of the grid are stored
+                f32x16 d = {};
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint4 u0 = split4(a[8 * j], a[8 * j + 1], a[8 * j + 2], a[8 * j + 3]);
+                    const uint4 u1 = split4(a[8 * j + 4], a[8 * j + 5], a[8 * j + 6], a[8 * j + 7]);
+                    const bf16x8 hi = __builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y));
+                    const bf16x8 lo = __builtin_bit_cast(bf16x8, make_uint4(u0.z, u0.w, u1.z, u1.w));
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A4[j], hi, d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A4[j], lo, d, 0, 0, 0);
+                }
+                // d[i] is tap row 8 (i / 4) + 4 half + i % 4: taps 0-3 and 8 (half 0), 4-7 (half 1)
+                if (inside) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) out[(4 * half + i) * HW + p] = d[i];
+                    if (half == 0) out[8 * HW + p] = d[4];
+                }
+                continue;
+            }
+            if (!inside) continue;
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) {
                 const int cg = 2 * q4 + half;
@@ -239,10 +344,20 @@ static_assert(CT_Y == 8, "conv32_body gives each of its 4 waves two rows");
 
 #define CONV32_ARGS                                                                                        \
     const float *__restrict__ in, const bf16x8 *__restrict__ pack, const float *__restrict__ bias,          \
-        const float *__restrict__ aux, float *__restrict__ out, int ny, int nx
-// 43.5 KB of LDS per block: three blocks per CU, so ask for registers to match
-__global__ __launch_bounds__(256, 3) void k_conv32_fwd(CONV32_ARGS) { conv32_body<0>(in, pack, bias, aux, out, ny, nx); }
-__global__ __launch_bounds__(256, 3) void k_conv32_bwd(CONV32_ARGS) { conv32_body<1>(in, pack, bias, aux, out, ny, nx); }
+        const float *__restrict__ aux, const bf16x8 *__restrict__ pack4, float *__restrict__ out, int ny, int nx
+// 43.5 KB of LDS per block.  The next tile's loads are in flight during the compute, so two
+// blocks per CU (with registers for the prefetch, the 18 A operands and both accumulators)
+// keep the loads going; three would spill.
+constexpr int CONV_OCC = 2;
+__global__ __launch_bounds__(256, CONV_OCC) void k_conv32_fwd(CONV32_ARGS) {
+    conv32_body<0>(in, pack, bias, aux, pack4, out, ny, nx);
+}
+__global__ __launch_bounds__(256, CONV_OCC) void k_conv32_bwd(CONV32_ARGS) {
+    conv32_body<1>(in, pack, bias, aux, pack4, out, ny, nx);
+}
+__global__ __launch_bounds__(256, CONV_OCC) void k_conv32_taps(CONV32_ARGS) {
+    conv32_body<2>(in, pack, bias, aux, pack4, out, ny, nx);
+}
 
 // layer 4: y = conv(a3; W4) + b4, one cell per thread of a block tile staged in LDS
 __global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a3, const float* __restrict__ q,
@@ -252,7 +367,13 @@ __global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a3, c
     const int ntx = (nx + CT_X - 1) / CT_X;
     const int ty = blockIdx.x / ntx, tx = blockIdx.x - ty * ntx;
     const int x0 = tx * CT_X, y0 = ty * CT_Y;
-    stage_tile(sm, a3, HW, ny, nx, y0, x0);
+    if (ny >= CT_R && nx >= CT_C) {
+        u32x4 v[ST_IT];
+        tile_load(v, a3, HW, ny, nx, y0, x0);
+        tile_store(sm, v);
+    } else {
+        stage_tile(sm, a3, HW, ny, nx, y0, x0);
+    }
     __syncthreads();
     const int ly = threadIdx.x / CT_X, lx = threadIdx.x % CT_X;
     const int y = y0 + ly, x = x0 + lx;
@@ -271,6 +392,28 @@ __global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a3, c
             }
         }
     yout[(long)y * nx + x] = acc;
+}
+
+// layer 4 of an inference pass from the per-tap sums: y(p) = b4 + sum_t s_t(p + off(t)),
+// off(t) = (t / 3 - 1, t % 3 - 1).  Writes y, or X = phi + s_o y when X is given.
+__global__ __launch_bounds__(256) void k_out_sum(const float* __restrict__ s, const float* __restrict__ q, int ny,
+                                                 int nx, float* __restrict__ yout, const double* __restrict__ phi,
+                                                 double s_o, double* __restrict__ X) {
+    const long HW = (long)ny * nx;
+    const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;   // one cell per thread
+    if (p >= HW) return;
+    const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
+    float acc = q[OFF_B4];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+        const long row = (long)wrap1(y + dy - 1, ny) * nx;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) acc += s[(dy * 3 + dx) * HW + row + wrap1(xx + dx - 1, nx)];
+    }
+    if (X)
+        X[p] = phi[p] + s_o * (double)acc;
+    else
+        yout[p] = acc;
 }
 
 // dy = scale * 2 (y - t) / HW and per-block partials of sum (y - t)^2
@@ -462,12 +605,6 @@ __global__ __launch_bounds__(256) void k_net_input(const double* __restrict__ ph
     }
 }
 
-__global__ void k_net_guess(const double* __restrict__ phi, const float* __restrict__ y, double s_o,
-                            double* __restrict__ X, long n) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        X[i] = phi[i] + s_o * (double)y[i];
-}
-
 inline unsigned cell_grid(long n) { return (unsigned)((n + 255) / 256); }   // one cell per thread
 
 inline unsigned grid_for(long n, int per = 256, unsigned cap = 4096) {
@@ -494,6 +631,7 @@ struct pfc_net {
     long cap = 0;               // cells the activation buffers hold
     float *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *b1 = nullptr, *b2 = nullptr, *y = nullptr, *dy = nullptr;
     long step = 0;
+    int conv_res = 0;           // conv32 blocks resident on the device at once
     bool prepared = false;
     std::string err;
 };
@@ -543,7 +681,7 @@ pfc_status ensure(pfc_net* net, long HW) {
 
 pfc_status prepare(pfc_net* net, hipStream_t s) {
     if (net->prepared) return PFC_OK;
-    hipLaunchKernelGGL(k_prepare, dim3((4 * PACK * 8 + 255) / 256), dim3(256), 0, s, net->d_theta, net->d_q,
+    hipLaunchKernelGGL(k_prepare, dim3((PACK_ALL * 8 + 255) / 256), dim3(256), 0, s, net->d_theta, net->d_q,
                        net->d_pack);
     NETCHK(hipGetLastError());
     net->prepared = true;
@@ -556,9 +694,9 @@ const bf16x8* pack_of(const pfc_net* net, int set) {
 
 unsigned tile_count(int ny, int nx) { return (unsigned)(((nx + CT_X - 1) / CT_X) * ((ny + CT_Y - 1) / CT_Y)); }
 
-unsigned conv_grid(int ny, int nx) {   // blocks walk the tiles: at most 1024 blocks
+unsigned conv_grid(const pfc_net* net, int ny, int nx) {   // persistent: one block per resident slot
     const unsigned t = tile_count(ny, nx);
-    return t < 1024 ? t : 1024;
+    return t < (unsigned)net->conv_res ? t : (unsigned)net->conv_res;
 }
 
 // forward pass on stream s: activations a1..a3 (kept for a backward pass), output in y_out
@@ -567,11 +705,27 @@ pfc_status forward_into(pfc_net* net, hipStream_t s, const float* x, int ny, int
                         float* a2, float* a3) {
     const long HW = (long)ny * nx;
     hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, a1, ny, nx);
-    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, a1, pack_of(net, 0),
-                       net->d_q + OFF_B2, nullptr, a2, ny, nx);
-    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
-                       net->d_q + OFF_B3, nullptr, a3, ny, nx);
+    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a1, pack_of(net, 0),
+                       net->d_q + OFF_B2, nullptr, nullptr, a2, ny, nx);
+    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
+                       net->d_q + OFF_B3, nullptr, nullptr, a3, ny, nx);
     hipLaunchKernelGGL(k_out_fwd, dim3(tile_count(ny, nx)), dim3(256), 0, s, a3, net->d_q, y_out, ny, nx);
+    NETCHK(hipGetLastError());
+    return PFC_OK;
+}
+
+// inference pass on stream s: a1, a2 as workspace (32 HW floats each), taps (9 HW floats)
+// for the output layer's per-tap sums; the last inner layer's activations are never stored.
+// Output y_out, or X = phi + s_o y when X is given.
+pfc_status infer_into(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* a1, float* a2,
+                      float* taps, float* y_out, const double* phi, double s_o, double* X) {
+    const long HW = (long)ny * nx;
+    hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, a1, ny, nx);
+    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a1, pack_of(net, 0),
+                       net->d_q + OFF_B2, nullptr, nullptr, a2, ny, nx);
+    hipLaunchKernelGGL(k_conv32_taps, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
+                       net->d_q + OFF_B3, nullptr, pack_of(net, 4), taps, ny, nx);
+    hipLaunchKernelGGL(k_out_sum, dim3(cell_grid(HW)), dim3(256), 0, s, taps, net->d_q, ny, nx, y_out, phi, s_o, X);
     NETCHK(hipGetLastError());
     return PFC_OK;
 }
@@ -610,11 +764,7 @@ pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const doubl
     hipLaunchKernelGGL(k_net_input, dim3(grid_for(n)), dim3(256), 0, s, phi, prev, n, ratio, 1.0 / scales[0],
                        1.0 / scales[1], sum_part, np, w.x);
     const size_t act = (size_t)WID * n;
-    pfc_status st = forward_into(net, s, w.x, ny, nx, w.y, w.a, w.a + act, w.a + 2 * act);
-    if (st != PFC_OK) return st;
-    hipLaunchKernelGGL(k_net_guess, dim3(grid_for(n)), dim3(256), 0, s, phi, w.y, scales[2], X, n);
-    NETCHK(hipGetLastError());
-    return PFC_OK;
+    return infer_into(net, s, w.x, ny, nx, w.a, w.a + act, w.a + 2 * act, nullptr, phi, scales[2], X);
 }
 
 pfc_status net_prepare(pfc_net* net) {
@@ -636,7 +786,7 @@ pfc_status pfc_net_create(void* stream, pfc_net** out) {
     net->stream = (hipStream_t)stream;
     bool ok = hipMalloc((void**)&net->d_theta, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_q, sizeof(float) * NPARAM) == hipSuccess &&
-              hipMalloc((void**)&net->d_pack, sizeof(unsigned short) * 4 * PACK * 8) == hipSuccess &&
+              hipMalloc((void**)&net->d_pack, sizeof(unsigned short) * PACK_ALL * 8) == hipSuccess &&
               hipMalloc((void**)&net->d_grad, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_m, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_v, sizeof(float) * NPARAM) == hipSuccess &&
@@ -648,6 +798,13 @@ pfc_status pfc_net_create(void* stream, pfc_net** out) {
              hipMemset(net->d_grad, 0, sizeof(float) * NPARAM) == hipSuccess &&
              hipMemset(net->d_m, 0, sizeof(float) * NPARAM) == hipSuccess &&
              hipMemset(net->d_v, 0, sizeof(float) * NPARAM) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
+    if (ok) {   // the three conv32 kernels share launch bounds and LDS size
+        int dev = 0, cus = 0, occ = 0;
+        ok = hipGetDevice(&dev) == hipSuccess &&
+             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_conv32_fwd, 256, 0) == hipSuccess;
+        net->conv_res = (occ < 1 ? 1 : occ) * (cus < 1 ? 1 : cus);
     }
     if (!ok) {
         pfc_net_destroy(net);
@@ -693,7 +850,11 @@ pfc_status pfc_net_forward(pfc_net* net, const float* x, int ny, int nx, float* 
         net->err = "bad argument";
         return PFC_EINVAL;
     }
-    return forward_impl(net, net->stream, x, ny, nx, y);
+    pfc_status st = ensure(net, (long)ny * nx);
+    if (st != PFC_OK) return st;
+    st = prepare(net, net->stream);
+    if (st != PFC_OK) return st;
+    return infer_into(net, net->stream, x, ny, nx, net->a1, net->a2, net->a3, y, nullptr, 0.0, nullptr);
 }
 
 pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny, int nx, double scale,
@@ -717,12 +878,12 @@ pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny
     hipLaunchKernelGGL(k_out_bwd, dim3(cell_grid(HW)), dim3(256), 0, s, net->dy, net->d_q, net->a3, net->b1, ny, nx);
     // layer 3: g3 in b1
     if ((st = wgrad<WID, WID>(net, net->b1, net->a2, ny, nx, OFF_W3, accumulate)) != PFC_OK) return st;
-    hipLaunchKernelGGL(k_conv32_bwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->b1, pack_of(net, 3), nullptr, net->a2,
-                       net->b2, ny, nx);
+    hipLaunchKernelGGL(k_conv32_bwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, net->b1, pack_of(net, 3), nullptr, net->a2,
+                       nullptr, net->b2, ny, nx);
     // layer 2: g2 in b2
     if ((st = wgrad<WID, WID>(net, net->b2, net->a1, ny, nx, OFF_W2, accumulate)) != PFC_OK) return st;
-    hipLaunchKernelGGL(k_conv32_bwd, dim3(conv_grid(ny, nx)), dim3(256), 0, s, net->b2, pack_of(net, 1), nullptr, net->a1,
-                       net->b1, ny, nx);
+    hipLaunchKernelGGL(k_conv32_bwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, net->b2, pack_of(net, 1), nullptr, net->a1,
+                       nullptr, net->b1, ny, nx);
     // layer 1: g1 in b1
     if ((st = wgrad<WID, CIN>(net, net->b1, x, ny, nx, OFF_W1, accumulate)) != PFC_OK) return st;
     NETCHK(hipGetLastError());

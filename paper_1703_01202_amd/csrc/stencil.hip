@@ -9,6 +9,7 @@
 // 3-D: three seven-point passes through global memory (L2-resident neighbours).
 #include "device_reduce.h"
 #include "pfc_internal.h"
+#include "tiling.h"
 
 namespace pfc {
 namespace {
@@ -36,15 +37,6 @@ __device__ __forceinline__ int wrap1(int i, int n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
-// Tile of this block in a 1-D launch over ntx x nty tiles.  Blocks are dispatched round-robin
-// over the 8 XCDs, each with its own L2; XCD k = b mod 8 is given a contiguous range of tiles
-// in row-major order, so vertically adjacent tiles (which share halo rows) run on the same
-// XCD and their halo reads hit its L2.  A bijection for any tile count.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int q = nb / 8, r = nb % 8, k = b % 8;
-    return k * q + (k < r ? k : r) + b / 8;
-}
-
 // Halo staging in two phases: each thread first issues all of its global loads (a fixed,
 // unrolled count), then writes them to LDS, so a block has every load in flight at once
 // instead of one round trip per loop iteration.
@@ -55,18 +47,6 @@ constexpr int NIT0 = (TY * TX + NT - 1) / NT;     // interior cells per thread
 #define LAP2(A, y, x)                                                     \
     (((A)[y][(x) + 1] + (A)[y][(x)-1] - 2.0 * (A)[y][x]) * p.ihx2 +       \
      ((A)[(y) + 1][x] + (A)[(y)-1][x] - 2.0 * (A)[y][x]) * p.ihy2)
-
-// Tiles of a persistent block: block b (after the XCD remap) owns the contiguous range
-// [first, last) of the row-major tile order.
-struct TileRange {
-    int first, last;
-};
-__device__ __forceinline__ TileRange tile_range(int ntiles) {
-    const int L = xcd_tile(blockIdx.x, gridDim.x);
-    const int per = ntiles / gridDim.x, extra = ntiles % gridDim.x;
-    const int first = L * per + (L < extra ? L : extra);
-    return {first, first + per + (L < extra ? 1 : 0)};
-}
 
 // F = (Phi - phi)/dt - Delta_d mu_d - src, plus one partial sum of F^2 per block (and of
 // Phi^2 in xpart when given).

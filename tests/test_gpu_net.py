@@ -1,7 +1,8 @@
 """GPU parity of the learned-guess network (include/pfc_net.h) against the FP64 oracle.
 
 Tolerances.  The GPU network rounds the convolution weights to bfloat16 exactly as the
-oracle does; what differs is (i) FP32 accumulation, (ii) the inner layers' activations
+oracle does; what differs is (i) FP32 accumulation and its order (the inference pass
+forms the output layer as per-tap sums added over the neighbourhood), (ii) the activations
 entering the matrix cores as hi + lo bfloat16 parts, |a - hi - lo| <= 2^-17 |a|, and (iii)
 tanh from one exponential (absolute error ~1e-7).  Each layer's error is thus a few 1e-5 of the sum of |w a| it accumulates; through
 four layers the output agrees to ~1e-4 of its scale, and the gradients, which go through
@@ -45,7 +46,9 @@ def _cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-SHAPES = [(48, 80), (37, 53), (3, 3)]
+# (300, 523): 646 tiles of 32 x 8 cells, more than the persistent conv kernels' resident
+# blocks, so blocks walk several tiles and prefetch the next one; ragged in both axes
+SHAPES = [(48, 80), (37, 53), (3, 3), (300, 523)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -60,7 +63,7 @@ def test_forward_matches_oracle(pfc, shape):
     assert np.linalg.norm(y - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("shape", SHAPES[:2])
+@pytest.mark.parametrize("shape", [SHAPES[0], SHAPES[1], SHAPES[3]])
 def test_gradient_and_loss_match_oracle(pfc, shape):
     theta = _params(3)
     x, t = _data(shape, 4)

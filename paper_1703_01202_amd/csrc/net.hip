@@ -36,7 +36,8 @@ static_assert(OFF_B4 + 1 == NPARAM, "parameter layout");
 constexpr int KSTEPS = 18;                 // 9 taps x 2 blocks of 16 input channels
 constexpr int PACK = KSTEPS * 64;          // packed A operands (8 bf16 each) per layer and direction
 constexpr int PACK4 = 2 * 64;              // packed A operands of the output layer's tap sums
-constexpr int PACK_ALL = 4 * PACK + PACK4;
+constexpr int PACK1 = 2 * 64;              // packed A operands of the first layer (inference)
+constexpr int PACK_ALL = 4 * PACK + PACK4 + PACK1;
 constexpr int WG_BLOCKS = 256;             // fixed grid of the weight-gradient kernels
 constexpr int WG_MAXOUT = WID * WID * 9 + WID;
 
@@ -98,6 +99,8 @@ __device__ __forceinline__ bool is_weight_index(int i) {
 // Then the output layer's operand [j][lane][e] (j = 0, 1), row m = tap (zero for m >= 9):
 //   A[m][k] = W4[c(k)][m],  k = 16 j + 8 h + e,  c(k) = 16 j + 8 (e / 4) + 4 h + e % 4,  h = lane / 32,
 // the channel order in which a lane of the inner layers' accumulator holds its outputs.
+// Last the first layer's operand [j][lane][e], row m = out channel, k = 16 j + 8 h + e:
+//   A[m][k] = W1[m][k % 2][k / 2] for k < 18 (tap k / 2, input channel k % 2), zero beyond.
 __global__ void k_prepare(const float* __restrict__ theta, float* __restrict__ q, unsigned short* __restrict__ pack) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < NPARAM) q[i] = is_weight_index(i) ? bf2f(f2bf(theta[i])) : theta[i];
@@ -109,12 +112,17 @@ __global__ void k_prepare(const float* __restrict__ theta, float* __restrict__ q
         const int woff = set < 2 ? OFF_W2 : OFF_W3;
         const int idx = (set & 1) ? woff + (k * WID + m) * 9 + (8 - tap) : woff + (m * WID + k) * 9 + tap;
         pack[i] = f2bf(theta[idx]);
-    } else if (i < PACK_ALL * 8) {
+    } else if (i < (4 * PACK + PACK4) * 8) {
         const int r = i - 4 * PACK * 8;
         const int j = r / 512, lane = (r / 8) % 64, e = r % 8;
         const int m = lane % 32, h = lane / 32;
         const int c = 16 * j + 8 * (e / 4) + 4 * h + e % 4;
         pack[i] = m < 9 ? f2bf(theta[OFF_W4 + c * 9 + m]) : (unsigned short)0;
+    } else if (i < PACK_ALL * 8) {
+        const int r = i - (4 * PACK + PACK4) * 8;
+        const int j = r / 512, lane = (r / 8) % 64, e = r % 8;
+        const int m = lane % 32, k = 16 * j + 8 * (lane / 32) + e;
+        pack[i] = k < 2 * 9 ? f2bf(theta[OFF_W1 + (m * CIN + k % 2) * 9 + k / 2]) : (unsigned short)0;
     }
 }
 
@@ -211,6 +219,94 @@ __device__ __forceinline__ void tile_store(uint4 (*sm)[NG][CT_C], const u32x4 (&
     }
 }
 
+// One block tile of an inner layer from the staged halo tile sm: the matrix-core product
+// and the MODE's epilogue (see conv32_body).
+template <int MODE>
+__device__ __forceinline__ void conv_tile(const uint4 (*sm)[NG][CT_C], const bf16x8 (&A)[KSTEPS],
+                                          const bf16x8 (&A4)[2], const float* __restrict__ bias,
+                                          const float* __restrict__ aux, float* __restrict__ out, long HW, int ny,
+                                          int nx, int x0, int y0) {
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31, wv = threadIdx.x >> 6;
+    const int ly0 = 2 * wv;                 // this wave's rows ly0, ly0 + 1 (CT_Y = 8)
+    f32x16 acc2[2] = {{}, {}};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                // channels 16 j + 8 half + 0..7 = groups 4 j + 2 half and the next one
+                const uint4 u0 = sm[ly0 + r][4 * j + 2 * half][col + dx];
+                const uint4 u1 = sm[ly0 + r][4 * j + 2 * half + 1][col + dx];
+                const bf16x8 hi = __builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y));
+                const bf16x8 lo = __builtin_bit_cast(bf16x8, make_uint4(u0.z, u0.w, u1.z, u1.w));
+                if (r <= 2) {                // row ly0, tap dy = r
+                    const int s = (r * 3 + dx) * 2 + j;
+                    acc2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], hi, acc2[0], 0, 0, 0);
+                    acc2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], lo, acc2[0], 0, 0, 0);
+                }
+                if (r >= 1) {                // row ly0 + 1, tap dy = r - 1
+                    const int s = ((r - 1) * 3 + dx) * 2 + j;
+                    acc2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], hi, acc2[1], 0, 0, 0);
+                    acc2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], lo, acc2[1], 0, 0, 0);
+                }
+            }
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+        const f32x16& acc = acc2[rr];
+        const int y = y0 + ly0 + rr, x = x0 + col;
+        const bool inside = y < ny && x < nx;
+        const long p = (long)y * nx + x;
+        // lane holds cell p and output channels 8 (r / 4) + 4 half + r % 4, r = 0..15
+        if (MODE == 2) {
+            float a[16];
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[4 * q4 + e] = tanh_fast(acc[4 * q4 + e] + bias[4 * (2 * q4 + half) + e]);
+            // B operand j holds a[8 j .. 8 j + 7], the channel order the pack4 rows assume;
+            // every lane takes part in the product, only cells of the grid are stored
+            f32x16 d = {};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint4 u0 = split4(a[8 * j], a[8 * j + 1], a[8 * j + 2], a[8 * j + 3]);
+                const uint4 u1 = split4(a[8 * j + 4], a[8 * j + 5], a[8 * j + 6], a[8 * j + 7]);
+                const bf16x8 hi = __builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y));
+                const bf16x8 lo = __builtin_bit_cast(bf16x8, make_uint4(u0.z, u0.w, u1.z, u1.w));
+                d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A4[j], hi, d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A4[j], lo, d, 0, 0, 0);
+            }
+            // d[i] is tap row 8 (i / 4) + 4 half + i % 4: taps 0-3 and 8 (half 0), 4-7 (half 1)
+            if (inside) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) out[(4 * half + i) * HW + p] = d[i];
+                if (half == 0) out[8 * HW + p] = d[4];
+            }
+            continue;
+        }
+        if (!inside) continue;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            const int cg = 2 * q4 + half;
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = acc[4 * q4 + e];
+            if (MODE == 0) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = tanh_fast(v[e] + bias[4 * cg + e]);
+            } else {
+                const float4 a = join4(*grp(aux, cg, HW, p));
+                v[0] *= 1.f - a.x * a.x;
+                v[1] *= 1.f - a.y * a.y;
+                v[2] *= 1.f - a.z * a.z;
+                v[3] *= 1.f - a.w * a.w;
+            }
+            *grp(out, cg, HW, p) = split4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+static_assert(CT_Y == 8, "conv_tile gives each of its 4 waves two rows");
+
 // inner layers on the matrix cores.  MODE 0: out = tanh(conv(in) + bias) (forward);
 // MODE 1: out = conv(in) * (1 - aux^2) (backward through the previous tanh, aux = its output);
 // MODE 2: the last inner layer of an inference pass: a = tanh(conv(in) + bias) stays in
@@ -227,7 +323,7 @@ __device__ __forceinline__ void conv32_body(const float* __restrict__ in, const 
                                             const bf16x8* __restrict__ pack4, float* __restrict__ out, int ny,
                                             int nx) {
     __shared__ uint4 sm[CT_R][NG][CT_C];
-    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const long HW = (long)ny * nx;
     const int ntx = (nx + CT_X - 1) / CT_X, nty = (ny + CT_Y - 1) / CT_Y;
     const int ntiles = ntx * nty;
@@ -261,86 +357,9 @@ __device__ __forceinline__ void conv32_body(const float* __restrict__ in, const 
             stage_tile(sm, in, HW, ny, nx, y0, x0);
             __syncthreads();
         }
-        const int ly0 = 2 * wv;                 // this wave's rows ly0, ly0 + 1 (CT_Y = 8)
-        f32x16 acc2[2] = {{}, {}};
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    // channels 16 j + 8 half + 0..7 = groups 4 j + 2 half and the next one
-                    const uint4 u0 = sm[ly0 + r][4 * j + 2 * half][col + dx];
-                    const uint4 u1 = sm[ly0 + r][4 * j + 2 * half + 1][col + dx];
-                    const bf16x8 hi = __builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y));
-                    const bf16x8 lo = __builtin_bit_cast(bf16x8, make_uint4(u0.z, u0.w, u1.z, u1.w));
-                    if (r <= 2) {                // row ly0, tap dy = r
-                        const int s = (r * 3 + dx) * 2 + j;
-                        acc2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], hi, acc2[0], 0, 0, 0);
-                        acc2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], lo, acc2[0], 0, 0, 0);
-                    }
-                    if (r >= 1) {                // row ly0 + 1, tap dy = r - 1
-                        const int s = ((r - 1) * 3 + dx) * 2 + j;
-                        acc2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], hi, acc2[1], 0, 0, 0);
-                        acc2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], lo, acc2[1], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-            const f32x16& acc = acc2[rr];
-            const int y = y0 + ly0 + rr, x = x0 + col;
-            const bool inside = y < ny && x < nx;
-            const long p = (long)y * nx + x;
-            // lane holds cell p and output channels 8 (r / 4) + 4 half + r % 4, r = 0..15
-            if (MODE == 2) {
-                float a[16];
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) a[4 * q4 + e] = tanh_fast(acc[4 * q4 + e] + bias[4 * (2 * q4 + half) + e]);
-                // B operand j holds a[8 j .. 8 j + 7], the channel order the pack4 rows assume;
-                // every lane takes part in the product, only cells of the grid are stored
-                f32x16 d = {};
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const uint4 u0 = split4(a[8 * j], a[8 * j + 1], a[8 * j + 2], a[8 * j + 3]);
-                    const uint4 u1 = split4(a[8 * j + 4], a[8 * j + 5], a[8 * j + 6], a[8 * j + 7]);
-                    const bf16x8 hi = __builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y));
-                    const bf16x8 lo = __builtin_bit_cast(bf16x8, make_uint4(u0.z, u0.w, u1.z, u1.w));
-                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A4[j], hi, d, 0, 0, 0);
-                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A4[j], lo, d, 0, 0, 0);
-                }
-                // d[i] is tap row 8 (i / 4) + 4 half + i % 4: taps 0-3 and 8 (half 0), 4-7 (half 1)
-                if (inside) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) out[(4 * half + i) * HW + p] = d[i];
-                    if (half == 0) out[8 * HW + p] = d[4];
-                }
-                continue;
-            }
-            if (!inside) continue;
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const int cg = 2 * q4 + half;
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = acc[4 * q4 + e];
-                if (MODE == 0) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = tanh_fast(v[e] + bias[4 * cg + e]);
-                } else {
-                    const float4 a = join4(*grp(aux, cg, HW, p));
-                    v[0] *= 1.f - a.x * a.x;
-                    v[1] *= 1.f - a.y * a.y;
-                    v[2] *= 1.f - a.z * a.z;
-                    v[3] *= 1.f - a.w * a.w;
-                }
-                *grp(out, cg, HW, p) = split4(v[0], v[1], v[2], v[3]);
-            }
-        }
+        conv_tile<MODE>(sm, A, A4, bias, aux, out, HW, ny, nx, x0, y0);
     }
 }
-static_assert(CT_Y == 8, "conv32_body gives each of its 4 waves two rows");
 
 #define CONV32_ARGS                                                                                        \
     const float *__restrict__ in, const bf16x8 *__restrict__ pack, const float *__restrict__ bias,          \
@@ -357,6 +376,131 @@ __global__ __launch_bounds__(256, CONV_OCC) void k_conv32_bwd(CONV32_ARGS) {
 }
 __global__ __launch_bounds__(256, CONV_OCC) void k_conv32_taps(CONV32_ARGS) {
     conv32_body<2>(in, pack, bias, aux, pack4, out, ny, nx);
+}
+
+// Layers 1 and 2 of an inference pass in one kernel.  A block stages the network input x
+// of its tile with a two-cell halo (12 x 36 cells, both channels as one 8-byte pair), forms
+// layer 1 on the 10 x 34 halo tile that layer 2 needs directly into LDS, and then runs
+// layer 2 as k_conv32_fwd does; a1 never leaves the chip.  Layer 1 on the matrix cores:
+// rows = 32 output channels, columns = 32 halo cells, K = 18 (9 taps x 2 channels, padded
+// to two steps of 16) with x split into hi + lo bfloat16 parts like the activations.
+constexpr int XS_R = CT_R + 2, XS_C = CT_C + 2, XS_N = XS_R * XS_C;
+constexpr int XS_IT = (XS_N + 255) / 256;
+constexpr int L1_CELLS = CT_R * CT_C, L1_CHUNKS = (L1_CELLS + 31) / 32;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void xs_load(f32x2 (&v)[XS_IT], const float* __restrict__ x, long HW, int ny, int nx,
+                                        int y0, int x0) {
+#pragma unroll
+    for (int k = 0; k < XS_IT; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < XS_N) {
+            const int r = e / XS_C, c = e - r * XS_C;
+            const long q = (long)wrapm(y0 - 2 + r, ny) * nx + wrapm(x0 - 2 + c, nx);
+            v[k] = f32x2{x[q], x[HW + q]};
+        }
+    }
+}
+
+__device__ __forceinline__ bf16x8 pk8(const float (&b)[8]) {
+    return __builtin_bit_cast(bf16x8, make_uint4(pk_bf16(b[0], b[1]), pk_bf16(b[2], b[3]), pk_bf16(b[4], b[5]),
+                                                 pk_bf16(b[6], b[7])));
+}
+
+// a1 = tanh(conv(x; W1) + b1) on the halo tile, into sm; wave wv takes chunks wv, wv + 4, ...
+// of 32 halo cells in row-major order (the last chunk is partial)
+__device__ __forceinline__ void layer1_to_lds(uint4 (*sm)[NG][CT_C], const f32x2 (*xs)[XS_C],
+                                              const bf16x8 (&A1)[2], const float* __restrict__ b1) {
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31, wv = threadIdx.x >> 6;
+    for (int k = wv; k < L1_CHUNKS; k += 4) {
+        const int q0 = 32 * k + col;
+        const bool ok = q0 < L1_CELLS;
+        const int q = ok ? q0 : L1_CELLS - 1;
+        const int r = q / CT_C, c = q - r * CT_C;
+        // B operands: step 0 holds taps 4 half .. 4 half + 3, step 1 tap 8 (half 0), else zero
+        float b0[8], b1v[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = 4 * half + i;
+            const f32x2 v = xs[r + t / 3][c + t % 3];
+            b0[2 * i] = v.x;
+            b0[2 * i + 1] = v.y;
+        }
+        const f32x2 v8 = xs[r + 2][c + 2];
+        b1v[0] = half == 0 ? v8.x : 0.f;
+        b1v[1] = half == 0 ? v8.y : 0.f;
+#pragma unroll
+        for (int e = 2; e < 8; ++e) b1v[e] = 0.f;
+        float l0[8], l1[8];
+        const bf16x8 h0 = pk8(b0), h1 = pk8(b1v);
+        const uint4 uh0 = __builtin_bit_cast(uint4, h0), uh1 = __builtin_bit_cast(uint4, h1);
+        const unsigned w0[4] = {uh0.x, uh0.y, uh0.z, uh0.w}, w1[4] = {uh1.x, uh1.y, uh1.z, uh1.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            l0[2 * e] = b0[2 * e] - __uint_as_float(w0[e] << 16);
+            l0[2 * e + 1] = b0[2 * e + 1] - __uint_as_float(w0[e] & 0xFFFF0000u);
+            l1[2 * e] = b1v[2 * e] - __uint_as_float(w1[e] << 16);
+            l1[2 * e + 1] = b1v[2 * e + 1] - __uint_as_float(w1[e] & 0xFFFF0000u);
+        }
+        f32x16 d = {};
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[0], h0, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[0], pk8(l0), d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[1], h1, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[1], pk8(l1), d, 0, 0, 0);
+        // lane holds halo cell q and channels 8 (i / 4) + 4 half + i % 4
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            const int cg = 2 * q4 + half;
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = tanh_fast(d[4 * q4 + e] + b1[4 * cg + e]);
+            if (ok) sm[r][cg][c] = split4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+// x planar FP32 [2][HW] -> a2 (grouped, split); pack: layer 2 forward, pack1: layer 1
+__global__ __launch_bounds__(256, CONV_OCC) void k_conv12_fwd(const float* __restrict__ x,
+                                                             const bf16x8* __restrict__ pack1,
+                                                             const float* __restrict__ b1,
+                                                             const bf16x8* __restrict__ pack,
+                                                             const float* __restrict__ b2, float* __restrict__ out,
+                                                             int ny, int nx) {
+    __shared__ uint4 sm[CT_R][NG][CT_C];
+    __shared__ f32x2 xs[XS_R][XS_C];
+    const int lane = threadIdx.x & 63;
+    const long HW = (long)ny * nx;
+    const int ntx = (nx + CT_X - 1) / CT_X, nty = (ny + CT_Y - 1) / CT_Y;
+    const int ntiles = ntx * nty;
+    bf16x8 A[KSTEPS];
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) A[s] = pack[s * 64 + lane];
+    const bf16x8 A1[2] = {pack1[lane], pack1[64 + lane]};
+    const bf16x8 A4[2] = {};
+    f32x2 pre[XS_IT];
+    if ((int)blockIdx.x < ntiles) {
+        const int ty = blockIdx.x / ntx;
+        xs_load(pre, x, HW, ny, nx, ty * CT_Y, (blockIdx.x - ty * ntx) * CT_X);
+    }
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int ty = tile / ntx, tx = tile - ty * ntx;
+        const int x0 = tx * CT_X, y0 = ty * CT_Y;
+        __syncthreads();                        // LDS reads of the previous tile are done
+#pragma unroll
+        for (int k = 0; k < XS_IT; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            if (e < XS_N) (&xs[0][0])[e] = pre[k];
+        }
+        __syncthreads();
+        const int t1 = tile + gridDim.x;
+        if (t1 < ntiles) {
+            const int ty1 = t1 / ntx;
+            xs_load(pre, x, HW, ny, nx, ty1 * CT_Y, (t1 - ty1 * ntx) * CT_X);
+        }
+        layer1_to_lds(sm, xs, A1, b1);
+        __syncthreads();
+        conv_tile<0>(sm, A, A4, b2, nullptr, out, HW, ny, nx, x0, y0);
+    }
 }
 
 // layer 4: y = conv(a3; W4) + b4, one cell per thread of a block tile staged in LDS
@@ -691,6 +835,7 @@ pfc_status prepare(pfc_net* net, hipStream_t s) {
 const bf16x8* pack_of(const pfc_net* net, int set) {
     return reinterpret_cast<const bf16x8*>(net->d_pack) + (long)set * PACK;
 }
+const bf16x8* pack1_of(const pfc_net* net) { return reinterpret_cast<const bf16x8*>(net->d_pack) + 4 * PACK + PACK4; }
 
 unsigned tile_count(int ny, int nx) { return (unsigned)(((nx + CT_X - 1) / CT_X) * ((ny + CT_Y - 1) / CT_Y)); }
 
@@ -714,15 +859,14 @@ pfc_status forward_into(pfc_net* net, hipStream_t s, const float* x, int ny, int
     return PFC_OK;
 }
 
-// inference pass on stream s: a1, a2 as workspace (32 HW floats each), taps (9 HW floats)
-// for the output layer's per-tap sums; the last inner layer's activations are never stored.
-// Output y_out, or X = phi + s_o y when X is given.
-pfc_status infer_into(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* a1, float* a2,
-                      float* taps, float* y_out, const double* phi, double s_o, double* X) {
+// inference pass on stream s, three kernels: layers 1-2 (a1 stays in LDS) into a2 (32 HW
+// floats), layer 3 with the output layer's per-tap sums into taps (9 HW floats; a3 is never
+// stored), and the output sum.  Output y_out, or X = phi + s_o y when X is given.
+pfc_status infer_into(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* a2, float* taps,
+                      float* y_out, const double* phi, double s_o, double* X) {
     const long HW = (long)ny * nx;
-    hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, a1, ny, nx);
-    hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a1, pack_of(net, 0),
-                       net->d_q + OFF_B2, nullptr, nullptr, a2, ny, nx);
+    hipLaunchKernelGGL(k_conv12_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, x, pack1_of(net),
+                       net->d_q + OFF_B1, pack_of(net, 0), net->d_q + OFF_B2, a2, ny, nx);
     hipLaunchKernelGGL(k_conv32_taps, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
                        net->d_q + OFF_B3, nullptr, pack_of(net, 4), taps, ny, nx);
     hipLaunchKernelGGL(k_out_sum, dim3(cell_grid(HW)), dim3(256), 0, s, taps, net->d_q, ny, nx, y_out, phi, s_o, X);
@@ -763,8 +907,8 @@ pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const doubl
     }
     hipLaunchKernelGGL(k_net_input, dim3(grid_for(n)), dim3(256), 0, s, phi, prev, n, ratio, 1.0 / scales[0],
                        1.0 / scales[1], sum_part, np, w.x);
-    const size_t act = (size_t)WID * n;
-    return infer_into(net, s, w.x, ny, nx, w.a, w.a + act, w.a + 2 * act, nullptr, phi, scales[2], X);
+    static_assert(kNetWorkFloats == WID + 9, "inference workspace: a2, then the tap sums");
+    return infer_into(net, s, w.x, ny, nx, w.a, w.a + (size_t)WID * n, nullptr, phi, scales[2], X);
 }
 
 pfc_status net_prepare(pfc_net* net) {
@@ -799,11 +943,13 @@ pfc_status pfc_net_create(void* stream, pfc_net** out) {
              hipMemset(net->d_m, 0, sizeof(float) * NPARAM) == hipSuccess &&
              hipMemset(net->d_v, 0, sizeof(float) * NPARAM) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     }
-    if (ok) {   // the three conv32 kernels share launch bounds and LDS size
-        int dev = 0, cus = 0, occ = 0;
+    if (ok) {   // the persistent conv kernels share launch bounds; the fused one has more LDS
+        int dev = 0, cus = 0, occ = 0, occ12 = 0;
         ok = hipGetDevice(&dev) == hipSuccess &&
              hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-             hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_conv32_fwd, 256, 0) == hipSuccess;
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_conv32_fwd, 256, 0) == hipSuccess &&
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ12, k_conv12_fwd, 256, 0) == hipSuccess;
+        occ = occ12 < occ ? occ12 : occ;
         net->conv_res = (occ < 1 ? 1 : occ) * (cus < 1 ? 1 : cus);
     }
     if (!ok) {
@@ -854,7 +1000,7 @@ pfc_status pfc_net_forward(pfc_net* net, const float* x, int ny, int nx, float* 
     if (st != PFC_OK) return st;
     st = prepare(net, net->stream);
     if (st != PFC_OK) return st;
-    return infer_into(net, net->stream, x, ny, nx, net->a1, net->a2, net->a3, y, nullptr, 0.0, nullptr);
+    return infer_into(net, net->stream, x, ny, nx, net->a2, net->a3, y, nullptr, 0.0, nullptr);
 }
 
 pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny, int nx, double scale,

@@ -59,9 +59,10 @@ struct KernelTimer {
 // are shared read-only, so contexts on different streams and threads can use one network).
 struct NetWork {
     float* x = nullptr;    // input planes [2][N]
-    float* y = nullptr;    // output [N]
-    float* a = nullptr;    // three activation buffers of 32 channels x N (16 bytes per 4 channels)
+    float* a = nullptr;    // second-layer activations, 32 channels x N (16 bytes per 4 channels),
+                           // then the output layer's 9 per-tap sum planes of N
 };
+constexpr int kNetWorkFloats = 32 + 9;   // floats of NetWork::a per cell
 
 }  // namespace pfc
 

@@ -489,7 +489,7 @@ pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
 void free_all(pfc_ctx* c) {
     void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, c->d_fac, c->d_flag, c->d_c,
                     c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
-                    c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.y, c->netw.a};
+                    c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.a};
     for (void* p : ptrs)
         if (p) hipFree(p);
     drop_graphs(c);
@@ -962,8 +962,7 @@ pfc_status pfc_attach_net(pfc_ctx* c, pfc_net* net, const double* scales, double
     if (!c->netw.x) {
         const size_t N = (size_t)c->g.N;
         if (hipMalloc((void**)&c->netw.x, sizeof(float) * 2 * N) != hipSuccess ||
-            hipMalloc((void**)&c->netw.y, sizeof(float) * N) != hipSuccess ||
-            hipMalloc((void**)&c->netw.a, sizeof(float) * 3 * PFC_NET_WIDTH * N) != hipSuccess)
+            hipMalloc((void**)&c->netw.a, sizeof(float) * kNetWorkFloats * N) != hipSuccess)
             return fail(c, PFC_ENOMEM, "out of device memory for the network buffers");
     }
     if (net_prepare(net) != PFC_OK) return fail(c, PFC_EHIP, std::string("network: ") + net_error(net));

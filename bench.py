@@ -156,7 +156,15 @@ def train_guess_net(cfg):
     return net, meta
 
 
-def run_variant(name, steps, warmup, timing=True, net=None, net_meta=None, tuned=None):
+# Event timing of the headline run: the preconditioner apply (the roofline kernel) and the
+# factorisation, every launch (pfc_opts.timing bits 1 and 8).  Timing every kind costs ~4% of
+# the step (a few microseconds per timed dispatch), so the per-kernel breakdown of the other
+# kinds comes from a shorter run of its own.
+TIMING_HEADLINE = 1 | 8
+TIMING_ALL = 0xF
+
+
+def run_variant(name, steps, warmup, timing=TIMING_HEADLINE, net=None, net_meta=None, tuned=None):
     import torch
     v = dict(VARIANTS[name])
     if not v.get("use_graph"):
@@ -346,6 +354,10 @@ def main():
     main_res = run_variant(args.variant, args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)
     if tune_info is not None:
         main_res["autotune"] = tune_info
+    brk = run_variant(args.variant, min(args.steps, 50), args.warmup, timing=TIMING_ALL, net=net, net_meta=net_meta,
+                      tuned=tuned)
+    main_res["kernel_breakdown"] = {"steps": brk["steps"], "steps_per_s_all_kinds_timed": brk["steps_per_s"],
+                                    "kernels": brk["kernels"]}
     graph_res = None
     if not args.no_graph and args.variant == "learned":
         graph_res = run_variant("learned_graph", args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)

@@ -86,7 +86,9 @@ typedef struct {
     int guess;                        /* PFC_GUESS_* */
     double dt_min, dt_max, eta;       /* Eq. (16); dt_min == dt_max gives a fixed step */
     int max_retries;                  /* dt halvings after a failed Newton solve, default 4 */
-    int timing;                       /* 1: time every preconditioner/stencil launch with events */
+    int timing;                       /* bitmask of the launches timed with events (pfc_kernel_time):
+                                         1 preconditioner apply, 2 residual, 4 Jacobian action,
+                                         8 factorisation; 0 off */
     int precond_lag;                  /* 0: factor at the first Newton step of every time step (the
                                          paper's reuse); L > 0: pfc_step keeps the factors for up to L
                                          time steps while dt stays within 20% of the dt they were built
@@ -183,10 +185,13 @@ pfc_status pfc_reset(pfc_ctx* ctx);
 pfc_status pfc_checkpoint_save(pfc_ctx* ctx, const double* phi, const char* path);
 pfc_status pfc_checkpoint_load(pfc_ctx* ctx, double* phi, const char* path);
 
-/* Per-kernel timing (opts.timing = 1): which = 0 preconditioner apply, 1 residual,
+/* Per-kernel timing (bit which of opts.timing): which = 0 preconditioner apply, 1 residual,
  * 2 Jacobian action, 3 factorisation.  Returns the launch count and the summed
- * event-measured duration in milliseconds since the last pfc_reset.  which = 4 gives the
- * number of Arnoldi-step graph launches (opts.use_graph) and 0 ms. */
+ * event-measured duration in milliseconds since the last pfc_reset.  Single-kernel regions
+ * (2-D residual and Jacobian action, every apply) are timed by the kernel dispatch itself
+ * (hipExtLaunchKernel start/stop events); the others by events recorded around them.
+ * Synchronises the context stream.  which = 4 gives the number of Arnoldi-step graph
+ * launches (opts.use_graph) and 0 ms. */
 pfc_status pfc_kernel_time(pfc_ctx* ctx, int which, long* count, double* total_ms);
 
 #ifdef __cplusplus

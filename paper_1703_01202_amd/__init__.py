@@ -58,7 +58,7 @@ def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precon
     o.dt_max = float(dt_max if dt_max is not None else dt_min)
     o.eta = float(eta)
     o.max_retries = int(max_retries)
-    o.timing = int(bool(timing))
+    o.timing = 0xF if timing is True else int(timing)   # True: every kind; else the C bitmask
     o.precond_lag = int(precond_lag)
     o.newton_rel_ref = int(bool(newton_rel_ref))
     o.use_graph = int(bool(use_graph))
@@ -76,7 +76,8 @@ class Solver:
         """Options (keywords, defaults as in pfc_default_opts unless given): sub_solver
         ("ilu0" | "lu"), precond_fp32, dt_min (0.1), dt_max (= dt_min), eta, newton_rtol,
         newton_atol, lin_rtol, lin_atol, gmres_restart, gmres_maxit, newton_maxit, guess
-        ("previous" | "extrap" | "learned"), mass_project, max_retries, timing, precond_lag,
+        ("previous" | "extrap" | "learned"), mass_project, max_retries, timing (True, or the
+        bitmask of pfc_opts.timing), precond_lag,
         newton_rel_ref, use_graph (needs ``stream``: a non-default stream handle)."""
         import torch
         self._torch = torch

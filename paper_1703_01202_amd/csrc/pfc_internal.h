@@ -1,10 +1,13 @@
 // Internal declarations of libpfc (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/pfc.h"
@@ -46,13 +49,22 @@ struct Decomp {
     int next;                          // cells per extended box
 };
 
-// Event-pair timer for per-kernel durations on the context stream.
+// Event-pair timer for per-kernel durations on the context stream.  A region of one kernel
+// hands its event pair to that kernel's launch (launch_k), whose dispatch records both, so
+// timing adds no packets to the queue; regions of several kernels record the events around
+// them.
+// Elapsed times are read one synchronisation late: the pairs completed at the previous
+// synchronisation are read just before the next one waits, while the GPU still runs the work
+// enqueued in between, so the queries stay off the critical path.
 struct KernelTimer {
     std::vector<hipEvent_t> pool;
-    std::vector<std::pair<int, int>> pending;   // (start idx, kind)
-    int used = 0;
+    std::vector<int> free;                       // unused pairs (index of the start event)
+    std::vector<std::pair<int, int>> pending;   // (start idx, kind) recorded since the last synchronisation
+    std::vector<std::pair<int, int>> done;      // complete at the last synchronisation, not yet read
     long count[4] = {0, 0, 0, 0};
     double total_ms[4] = {0, 0, 0, 0};
+    bool ext = false;                            // the open region is timed by its launch
+    mutable hipEvent_t launch_ev[2] = {nullptr, nullptr};   // pair for the next launch_k
 };
 
 // Inference buffers of one solver context for the learned guess (the network's parameters
@@ -136,6 +148,28 @@ struct pfc_ctx {
 };
 
 namespace pfc {
+
+template <typename Tup, size_t... I>
+inline void arg_ptrs(Tup& t, void** p, std::index_sequence<I...>) {
+    ((p[I] = (void*)&std::get<I>(t)), ...);
+}
+
+// Launch kern on c's stream.  If a timed region left an event pair for it, the launch goes
+// through hipExtLaunchKernel, whose dispatch records the start and stop events itself.
+template <typename... K, typename... A>
+inline hipError_t launch_k(const pfc_ctx* c, void (*kern)(K...), dim3 grid, dim3 block, size_t sh, A... args) {
+    hipEvent_t* ev = c->timer.launch_ev;
+    if (!ev[0]) {
+        hipLaunchKernelGGL(kern, grid, block, sh, c->stream, args...);
+        return hipGetLastError();
+    }
+    const hipEvent_t e0 = ev[0], e1 = ev[1];
+    ev[0] = ev[1] = nullptr;
+    std::tuple<K...> t{static_cast<K>(args)...};
+    void* p[sizeof...(K) > 0 ? sizeof...(K) : 1];
+    arg_ptrs(t, p, std::index_sequence_for<K...>{});
+    return hipExtLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, p, sh, c->stream, e0, e1, 0);
+}
 
 // Allow a kernel the whole 160 KB LDS of a gfx950 CU minus its static LDS.
 inline hipError_t set_dynamic_lds_limit(const void* f) {

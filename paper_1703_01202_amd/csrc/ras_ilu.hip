@@ -383,14 +383,13 @@ hipError_t launch_ilu_apply_s(pfc_ctx* c, const double* r, double* z, double* su
     const StencilTable& st = c->st;
     if (c->opts.precond_fp32) {
         const size_t sh = sizeof(float) * b.next;
-        hipLaunchKernelGGL((k_ilu_apply<float, S>), dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
-                           (const float*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
+        return launch_k(c, k_ilu_apply<float, S>, dim3(c->dec.nsub), dim3(64), sh, r, z, (const float*)c->d_fac,
+                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
     } else {
         const size_t sh = sizeof(double) * b.next;
-        hipLaunchKernelGGL((k_ilu_apply<double, S>), dim3(c->dec.nsub), dim3(64), sh, c->stream, r, z,
-                           (const double*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
+        return launch_k(c, k_ilu_apply<double, S>, dim3(c->dec.nsub), dim3(64), sh, r, z, (const double*)c->d_fac,
+                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {

@@ -595,12 +595,9 @@ hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b
     const T* f = (const T*)c->d_fac;
     const dim3 grid(c->dec.nsub), blk(threads);
     if (b.W <= 24)
-        hipLaunchKernelGGL((k_lu_apply<T, 10, f32 ? 3 : 1>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
-    else if (b.W <= 32)
-        hipLaunchKernelGGL((k_lu_apply<T, 16, f32 ? 2 : 1>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
-    else
-        hipLaunchKernelGGL((k_lu_apply<T, 21, f32 ? 1 : 0>), grid, blk, sh, c->stream, r, z, f, b, sum_part);
-    return hipGetLastError();
+        return launch_k(c, k_lu_apply<T, 10, f32 ? 3 : 1>, grid, blk, sh, r, z, f, b, sum_part);
+    if (b.W <= 32) return launch_k(c, k_lu_apply<T, 16, f32 ? 2 : 1>, grid, blk, sh, r, z, f, b, sum_part);
+    return launch_k(c, k_lu_apply<T, 21, f32 ? 1 : 0>, grid, blk, sh, r, z, f, b, sum_part);
 }
 
 }  // namespace

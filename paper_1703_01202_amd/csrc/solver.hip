@@ -73,44 +73,75 @@ pfc_status fail(pfc_ctx* c, pfc_status s, const std::string& msg) {
 }
 
 // ---- per-kernel timing ----
-void timer_begin(pfc_ctx* c, int kind, int* slot) {
+// one_kernel: the region is a single launch_k launch, which records the events itself
+void timer_begin(pfc_ctx* c, int kind, int* slot, bool one_kernel = false) {
     *slot = -1;
-    if (!c->opts.timing) return;
+    if (!(c->opts.timing & (1 << kind))) return;
     auto& T = c->timer;
-    if (T.used + 2 > (int)T.pool.size()) {
-        for (int i = 0; i < 64; ++i) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return;
-            T.pool.push_back(e);
+    if (T.free.empty()) {
+        // timing-only events: no system-scope fence (cache writeback and invalidation) when
+        // they complete; the host reads results after stream synchronisations, not events
+        hipEvent_t e0, e1;
+        if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess) return;
+        if (hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return;
         }
+        T.free.push_back((int)T.pool.size());
+        T.pool.push_back(e0);
+        T.pool.push_back(e1);
     }
-    *slot = T.used;
-    T.used += 2;
-    hipEventRecord(T.pool[*slot], c->stream);
+    *slot = T.free.back();
+    T.free.pop_back();
+    T.ext = one_kernel;
+    if (one_kernel) {
+        T.launch_ev[0] = T.pool[*slot];
+        T.launch_ev[1] = T.pool[*slot + 1];
+    } else {
+        hipEventRecord(T.pool[*slot], c->stream);
+    }
     T.pending.push_back({*slot, kind});
 }
 
 void timer_end(pfc_ctx* c, int slot) {
     if (slot < 0) return;
-    hipEventRecord(c->timer.pool[slot + 1], c->stream);
+    auto& T = c->timer;
+    if (!T.ext) {
+        hipEventRecord(T.pool[slot + 1], c->stream);
+    } else if (T.launch_ev[0]) {   // no launch took the pair: the region is not counted
+        T.launch_ev[0] = T.launch_ev[1] = nullptr;
+        T.pending.pop_back();
+        T.free.push_back(slot);
+    }
+    T.ext = false;
 }
 
-void timer_flush(pfc_ctx* c) {   // call after a stream synchronisation
+// add the elapsed times of completed pairs to the totals and free the pairs
+void timer_read(pfc_ctx* c, std::vector<std::pair<int, int>>& list) {
     auto& T = c->timer;
-    for (auto& pr : T.pending) {
+    for (auto& pr : list) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, T.pool[pr.first], T.pool[pr.first + 1]) == hipSuccess) {
             T.total_ms[pr.second] += ms;
             T.count[pr.second] += 1;
         }
+        T.free.push_back(pr.first);
     }
-    T.pending.clear();
-    T.used = 0;
+    list.clear();
 }
 
 pfc_status sync(pfc_ctx* c) {
+    timer_read(c, c->timer.done);   // complete since the last synchronisation
     HIPCHK(hipStreamSynchronize(c->stream));
-    timer_flush(c);
+    c->timer.done.swap(c->timer.pending);
+    return PFC_OK;
+}
+
+// every recorded pair read (synchronises)
+pfc_status timer_drain(pfc_ctx* c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    timer_read(c, c->timer.done);
+    timer_read(c, c->timer.pending);
     return PFC_OK;
 }
 
@@ -136,7 +167,7 @@ pfc_status shift_by_sum(pfc_ctx* c, double* x, const double* y, double scale) {
 pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* src,
                          double* F, double* nrm) {
     int ts;
-    timer_begin(c, 1, &ts);
+    timer_begin(c, 1, &ts, c->g.dim == 2);
     HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_scal + SC_P : nullptr, nullptr));
     timer_end(c, ts);
     if (!nrm) return PFC_OK;
@@ -153,7 +184,7 @@ pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, doubl
 pfc_status jv_impl(pfc_ctx* c, const double* v, double dt, const double* shift_part, double* shift_out,
                    double* out) {
     int ts;
-    timer_begin(c, 2, &ts);
+    timer_begin(c, 2, &ts, c->g.dim == 2);
     HIPCHK(launch_jv(c, v, c->d_c, dt, shift_part, c->dec.nsub, 1.0 / (double)c->g.N, shift_out, out));
     timer_end(c, ts);
     return PFC_OK;
@@ -198,7 +229,7 @@ bool may_reuse_factors(const pfc_ctx* c, double dt) {
 // z = H^-1 r; with sum_part the apply kernel also leaves one partial sum of z per subdomain.
 pfc_status apply_raw(pfc_ctx* c, const double* r, double* z, double* sum_part) {
     int ts;
-    timer_begin(c, 0, &ts);
+    timer_begin(c, 0, &ts, true);
     if (c->opts.sub_solver == PFC_SUB_LU)
         HIPCHK(launch_lu_apply(c, r, z, sum_part));
     else
@@ -853,6 +884,7 @@ pfc_status pfc_reset(pfc_ctx* c) {
     c->fac_valid = false;
     c->fac_step = -1;
     c->fac_gpn = c->last_gpn = 0.0;
+    CHK(timer_drain(c));
     for (int i = 0; i < 4; ++i) {
         c->timer.count[i] = 0;
         c->timer.total_ms[i] = 0.0;
@@ -945,6 +977,7 @@ pfc_status pfc_kernel_time(pfc_ctx* c, int which, long* count, double* total_ms)
         *total_ms = 0.0;
         return PFC_OK;
     }
+    CHK(timer_drain(c));
     *count = c->timer.count[which];
     *total_ms = c->timer.total_ms[which];
     return PFC_OK;

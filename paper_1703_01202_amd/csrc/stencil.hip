@@ -393,9 +393,7 @@ hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* ph
                            const double* src, double* F, double* norm_part, double* xnorm_part) {
     const P p = make_params(c, dt);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_residual2d, residual_grid(c), dim3(NT), 0, c->stream, Phi, phi, src, F, norm_part,
-                           xnorm_part, p);
-        return hipGetLastError();
+        return launch_k(c, k_residual2d, residual_grid(c), dim3(NT), 0, Phi, phi, src, F, norm_part, xnorm_part, p);
     }
     if (xnorm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, Phi, c->g.N, xnorm_part);
     double* u = c->d_tmp3;
@@ -420,9 +418,8 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
                      int shift_n, double shift_scale, double* shift_out, double* Jv) {
     const P p = make_params(c, dt);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_jv2d, tiles2d(c), dim3(NT), 0, c->stream, v, cbuf, shift_part, shift_n, shift_scale,
-                           shift_out, Jv, p);
-        return hipGetLastError();
+        return launch_k(c, k_jv2d, tiles2d(c), dim3(NT), 0, v, cbuf, shift_part, shift_n, shift_scale, shift_out,
+                        Jv, p);
     }
     double* u = c->d_tmp3;
     double* Lu = c->d_tmp3 + c->g.N;

@@ -183,6 +183,10 @@ def test_ras_ilu0_3d_sampled_subdomains():
     (256, 100.0, (4, 16), 4, 10.0, True, 1e-4),
     (256, 100.0, (4, 16), 8, 10.0, False, 1e-9),       # 32-wide boxes
     (256, 100.0, (8, 16), 8, 10.0, True, 1e-4),
+    (256, 100.0, (4, 32), 2, 10.0, False, 1e-9),       # 12-wide boxes (8 owned columns, overlap 2)
+    (256, 100.0, (4, 32), 2, 10.0, True, 1e-4),
+    (256, 100.0, (2, 16), 3, 10.0, False, 1e-9),       # 22-wide boxes, odd overlap, 134 rows
+    (256, 100.0, (2, 16), 3, 10.0, True, 1e-4),
 ])
 def test_ras_exact_lu_2d(n, L, sub, ov, dt, fp32, tol):
     pfc = _pfc()

@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 # they were taken on: the sha256 prefix of the source file must match.
 MEASURED_TRAFFIC = {   # keyed by kernel and decomposition: (kernel, sub, overlap, sub_solver, fp32)
     ("ras_apply", (16, 64), 4, "lu", True): {"file": "paper_1703_01202_amd/csrc/ras_lu.hip",
-                                             "sha": "943eb6daba582fbb", "bytes": 1.2233e9},
+                                             "sha": "c903527f255c8ef2", "bytes": 1.2233e9},
 }
 
 
@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     ap.add_argument("--no-autotune", action="store_true", help="use the variant's fixed decomposition")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay run of the variant")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the short run that times every kernel kind (per-kernel breakdown)")
     ap.add_argument("--train-trajectories", type=int, default=LEARNED_TRAINING["trajectories"])
     ap.add_argument("--train-epochs", type=int, default=LEARNED_TRAINING["epochs"])
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
@@ -354,10 +356,11 @@ def main():
     main_res = run_variant(args.variant, args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)
     if tune_info is not None:
         main_res["autotune"] = tune_info
-    brk = run_variant(args.variant, min(args.steps, 50), args.warmup, timing=TIMING_ALL, net=net, net_meta=net_meta,
-                      tuned=tuned)
-    main_res["kernel_breakdown"] = {"steps": brk["steps"], "steps_per_s_all_kinds_timed": brk["steps_per_s"],
-                                    "kernels": brk["kernels"]}
+    if not args.no_breakdown:
+        brk = run_variant(args.variant, min(args.steps, 50), args.warmup, timing=TIMING_ALL, net=net,
+                          net_meta=net_meta, tuned=tuned)
+        main_res["kernel_breakdown"] = {"steps": brk["steps"], "steps_per_s_all_kinds_timed": brk["steps_per_s"],
+                                        "kernels": brk["kernels"]}
     graph_res = None
     if not args.no_graph and args.variant == "learned":
         graph_res = run_variant("learned_graph", args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)

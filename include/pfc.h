@@ -100,7 +100,8 @@ typedef struct {
                                          guess starts the iteration, so every guess meets the same
                                          target; 0: ||F|| at the guess actually used */
     int use_graph;                    /* 1: each Arnoldi step (preconditioner apply, J v, both Gram-Schmidt
-                                         passes, the copy of the Hessenberg column) is captured once per
+                                         passes, which write the Hessenberg column to mapped host
+                                         memory) is captured once per
                                          Krylov index and time step size as a HIP graph and replayed with
                                          one launch; needs a non-default stream (PFC_EINVAL otherwise) and
                                          is ignored while timing is on.  Results are bitwise those of the

@@ -117,7 +117,10 @@ struct pfc_ctx {
     // reductions
     double* d_part = nullptr;          // partials summed on the device (Gram-Schmidt, apply sums)
     double* d_scal = nullptr;          // device scalars, then partials summed on the host
-    double* h_pin = nullptr;           // pinned host mirror of d_scal
+    double* h_pin = nullptr;           // pinned host mirror of d_scal (mapped, coherent)
+    double* d_hpin = nullptr;          // h_pin as seen by kernels: values only the host reads
+                                       // (norm partials, Hessenberg column, apply means) are
+                                       // written here directly, with no copy
     double* h_y = nullptr;             // pinned staging of the FGMRES update coefficients
     int n_scal = 0;                    // doubles in d_scal / h_pin
 

@@ -147,9 +147,7 @@ pfc_status timer_drain(pfc_ctx* c) {
 
 // Euclidean norm of a device vector (synchronises).
 pfc_status norm2(pfc_ctx* c, const double* x, double* out) {
-    HIPCHK(launch_dot(c->stream, x, x, c->g.N, c->d_scal + SC_P));
-    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, c->d_scal + SC_P, sizeof(double) * kRedBlocks, hipMemcpyDeviceToHost,
-                          c->stream));
+    HIPCHK(launch_dot(c->stream, x, x, c->g.N, c->d_hpin + SC_P));   // partials straight to the host
     CHK(sync(c));
     *out = std::sqrt(host_sum(c, 0, kRedBlocks));
     if (!std::isfinite(*out)) return fail(c, PFC_ENAN, "non-finite norm");
@@ -168,11 +166,10 @@ pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, doubl
                          double* F, double* nrm) {
     int ts;
     timer_begin(c, 1, &ts, c->g.dim == 2);
-    HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_scal + SC_P : nullptr, nullptr));
+    HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_hpin + SC_P : nullptr, nullptr));
     timer_end(c, ts);
     if (!nrm) return PFC_OK;
     const int np = residual_partial_count(c);
-    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, c->d_scal + SC_P, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream));
     CHK(sync(c));
     *nrm = std::sqrt(host_sum(c, 0, np));
     if (!std::isfinite(*nrm)) return fail(c, PFC_ENAN, "non-finite residual norm");
@@ -246,8 +243,9 @@ pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
 }
 
 // One Arnoldi step j of FGMRES, enqueued: z_j = H^-1 v_j, w = J z_j, two classical
-// Gram-Schmidt passes against v_0..v_j (norm partials fused), then the copy of the
-// coefficients and partials to the host.
+// Gram-Schmidt passes against v_0..v_j (norm partials fused).  The values the host needs
+// (mean of z_j, both coefficient columns, norm partials) are written by the kernels straight
+// into the mapped host buffer, so the step has no copy.
 pfc_status enqueue_arnoldi_step(pfc_ctx* c, int j, double dt) {
     const long N = c->g.N;
     const bool proj = c->opts.mass_project;
@@ -258,15 +256,13 @@ pfc_status enqueue_arnoldi_step(pfc_ctx* c, int j, double dt) {
     // shift, and once from the update), which is the zero-mean projection of R12
     double* pj = proj ? part_apply(c, j) : nullptr;
     CHK(apply_raw(c, V + (long)j * N, zj, pj));
-    CHK(jv_impl(c, zj, dt, pj, c->d_scal + SC_M + j, w));
+    CHK(jv_impl(c, zj, dt, pj, c->d_hpin + SC_M + j, w));
     // CGS2: h = V^T w ; w -= V h ; h2 = V^T w ; w -= V h2 (norm fused)
     HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md1(c)));
-    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, nullptr, c->d_scal + SC_H));
+    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, nullptr, c->d_hpin + SC_H));
     HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md2(c)));
-    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_scal + SC_P,
-                        c->d_scal + SC_H2));
-    HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal, sizeof(double) * (SC_P + kRedBlocks), hipMemcpyDeviceToHost,
-                          c->stream));
+    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_hpin + SC_P,
+                        c->d_hpin + SC_H2));
     return PFC_OK;
 }
 
@@ -426,14 +422,12 @@ double residual_floor(const pfc_ctx* c, double dt, double xnorm) {
 pfc_status first_residual(pfc_ctx* c, const double* phi, double dt, bool want_ref, double* fn, double* xnorm,
                           double* fref) {
     const int np = residual_partial_count(c);
-    double* part = c->d_scal + SC_P;
+    double* part = c->d_hpin + SC_P;   // partials straight to the host
     int ts;
     timer_begin(c, 1, &ts);
     if (want_ref) HIPCHK(launch_residual(c, phi, phi, dt, nullptr, c->d_r, part + 2 * np, nullptr));
     HIPCHK(launch_residual(c, c->d_X, phi, dt, nullptr, c->d_F, part, part + np));
     timer_end(c, ts);
-    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, part, sizeof(double) * (want_ref ? 3 : 2) * np, hipMemcpyDeviceToHost,
-                          c->stream));
     CHK(sync(c));
     *fn = std::sqrt(host_sum(c, 0, np));
     *xnorm = std::sqrt(host_sum(c, np, np));
@@ -498,9 +492,7 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
 
 pfc_status energy_impl(pfc_ctx* c, const double* phi, double* e, double* m) {
     const int np = energy_partial_count(c);
-    HIPCHK(launch_energy(c, phi, c->d_scal + SC_P));
-    HIPCHK(hipMemcpyAsync(c->h_pin + SC_P, c->d_scal + SC_P, 2 * sizeof(double) * np, hipMemcpyDeviceToHost,
-                          c->stream));
+    HIPCHK(launch_energy(c, phi, c->d_hpin + SC_P));
     CHK(sync(c));
     *e = host_sum(c, 0, np) * c->g.cell_volume;
     *m = host_sum(c, np, np) * c->g.cell_volume;
@@ -728,7 +720,9 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (s == PFC_OK) {
         if (hipMalloc(&c->d_fac, esz * c->fac_elems) != hipSuccess) s = fail(c, PFC_ENOMEM, "factor allocation failed");
     }
-    if (s == PFC_OK && (hipHostMalloc((void**)&c->h_pin, sizeof(double) * c->n_scal) != hipSuccess ||
+    if (s == PFC_OK && (hipHostMalloc((void**)&c->h_pin, sizeof(double) * c->n_scal,
+                                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+                        hipHostGetDevicePointer((void**)&c->d_hpin, c->h_pin, 0) != hipSuccess ||
                         hipHostMalloc((void**)&c->h_y, sizeof(double) * (SC_SHIFT - SC_Y + 1)) != hipSuccess))
         s = fail(c, PFC_ENOMEM, "pinned allocation failed");
     if (s == PFC_OK && (set_ilu_lds_limits() != hipSuccess || set_lu_lds_limits() != hipSuccess))

@@ -64,26 +64,69 @@ __global__ __launch_bounds__(NT) void k_multidot(const double* __restrict__ V, l
 
 // w <- w + sign * sum_j c_j V_j with c_j = sum_b coef_part[j * coef_n + b], k <= 64 (summed by
 // every block in the same order; block 0 stores the c_j it used in coef_out).  With norm_part,
-// also this block's share of ||w_new||^2.
+// also this block's share of ||w_new||^2.  assign: w starts from zero (not read).  With shift,
+// sum(shift_part[0..shift_n)) * shift_scale is added to every w_i after the combination
+// (the same additions k_shift would make afterwards).
 __global__ __launch_bounds__(NT) void k_maxpy(const double* __restrict__ V, long ld, int k,
                                               const double* __restrict__ coef_part, int coef_n, double sign,
                                               double* __restrict__ w, long n, double* __restrict__ norm_part,
-                                              double* __restrict__ coef_out) {
+                                              double* __restrict__ coef_out, int assign,
+                                              const double* __restrict__ shift_part, int shift_n,
+                                              double shift_scale) {
     __shared__ double red[64 * (NT / 64)];
     __shared__ double cf[64];
     rows_sum_bcast(coef_part, k, coef_n, cf, red);
     if (coef_out && blockIdx.x == 0)
         for (int j = threadIdx.x; j < k; j += NT) coef_out[j] = cf[j];
+    const double sh = shift_part ? shift_scale * sum_partials_bcast(shift_part, shift_n, red) : 0.0;
     double acc = 0.0;
     for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
-        double s = w[i];
+        double s = assign ? 0.0 : w[i];
         for (int j = 0; j < k; ++j) s += sign * cf[j] * V[(long)j * ld + i];
+        if (shift_part) s += sh;
         w[i] = s;
         acc += s * s;
     }
     if (norm_part) {
         const double t = block_sum_det(acc, red);
         if (threadIdx.x == 0) norm_part[blockIdx.x] = t;
+    }
+}
+
+// One pass of Gram-Schmidt followed by the dots of the next one: w <- w + sign * sum_j c_j V_j
+// exactly as k_maxpy, and this block's share of V_q . w_new (q < k <= KG) into
+// dot_part[q * gridDim + b] exactly as k_multidot would compute it from the new w.
+__global__ __launch_bounds__(NT) void k_maxpy_dot(const double* __restrict__ V, long ld, int k,
+                                                  const double* __restrict__ coef_part, int coef_n, double sign,
+                                                  double* __restrict__ w, long n, double* __restrict__ dot_part,
+                                                  double* __restrict__ coef_out) {
+    __shared__ double red[64 * (NT / 64)];
+    __shared__ double cf[64];
+    rows_sum_bcast(coef_part, k, coef_n, cf, red);
+    if (coef_out && blockIdx.x == 0)
+        for (int j = threadIdx.x; j < k; j += NT) coef_out[j] = cf[j];
+    double acc[KG];
+#pragma unroll
+    for (int q = 0; q < KG; ++q) acc[q] = 0.0;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
+        double v[KG];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) v[q] = q < k ? V[(long)q * ld + i] : 0.0;
+        double s = w[i];
+#pragma unroll
+        for (int j = 0; j < KG; ++j)
+            if (j < k) s += sign * cf[j] * v[j];
+        w[i] = s;
+#pragma unroll
+        for (int q = 0; q < KG; ++q)
+            if (q < k) acc[q] += v[q] * s;
+    }
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+        if (q < k) {
+            const double t = block_sum_det(acc[q], red);
+            if (threadIdx.x == 0) dot_part[(long)q * gridDim.x + blockIdx.x] = t;
+        }
     }
 }
 
@@ -133,9 +176,21 @@ hipError_t launch_multidot(hipStream_t s, const double* V, long ld, int k, const
 }
 
 hipError_t launch_maxpy(hipStream_t s, const double* V, long ld, int k, const double* coef_part, int coef_n,
-                        double sign, double* w, long n, double* norm_part, double* coef_out) {
+                        double sign, double* w, long n, double* norm_part, double* coef_out, bool assign,
+                        const double* shift_part, int shift_n, double shift_scale) {
     hipLaunchKernelGGL(k_maxpy, dim3(kRedBlocks), dim3(NT), 0, s, V, ld, k, coef_part, coef_n, sign, w, n,
-                       norm_part, coef_out);
+                       norm_part, coef_out, assign ? 1 : 0, shift_part, shift_n, shift_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpy_dot(hipStream_t s, const double* V, long ld, int k, const double* coef_part, int coef_n,
+                            double sign, double* w, long n, double* dot_part, double* coef_out) {
+    if (k > KG) {   // beyond the fused pass: the two kernels
+        hipError_t e = launch_maxpy(s, V, ld, k, coef_part, coef_n, sign, w, n, nullptr, coef_out);
+        return e != hipSuccess ? e : launch_multidot(s, V, ld, k, w, n, dot_part);
+    }
+    hipLaunchKernelGGL(k_maxpy_dot, dim3(kRedBlocks), dim3(NT), 0, s, V, ld, k, coef_part, coef_n, sign, w, n,
+                       dot_part, coef_out);
     return hipGetLastError();
 }
 

@@ -539,25 +539,35 @@ __global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a3, c
 }
 
 // layer 4 of an inference pass from the per-tap sums: y(p) = b4 + sum_t s_t(p + off(t)),
-// off(t) = (t / 3 - 1, t % 3 - 1).  Writes y, or X = phi + s_o y when X is given.
+// off(t) = (t / 3 - 1, t % 3 - 1).  Writes y, or X = phi + s_o y when X is given, and then
+// with diff_part also this block's share of sum_p (phi - X)(p) (grid-stride over a fixed grid).
 __global__ __launch_bounds__(256) void k_out_sum(const float* __restrict__ s, const float* __restrict__ q, int ny,
                                                  int nx, float* __restrict__ yout, const double* __restrict__ phi,
-                                                 double s_o, double* __restrict__ X) {
+                                                 double s_o, double* __restrict__ X, double* __restrict__ diff_part) {
+    __shared__ double red[4];
     const long HW = (long)ny * nx;
-    const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;   // one cell per thread
-    if (p >= HW) return;
-    const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
-    float acc = q[OFF_B4];
+    double dsum = 0.0;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < HW; p += (long)gridDim.x * blockDim.x) {
+        const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
+        float acc = q[OFF_B4];
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
-        const long row = (long)wrap1(y + dy - 1, ny) * nx;
+        for (int dy = 0; dy < 3; ++dy) {
+            const long row = (long)wrap1(y + dy - 1, ny) * nx;
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) acc += s[(dy * 3 + dx) * HW + row + wrap1(xx + dx - 1, nx)];
+            for (int dx = 0; dx < 3; ++dx) acc += s[(dy * 3 + dx) * HW + row + wrap1(xx + dx - 1, nx)];
+        }
+        if (X) {
+            const double f = phi[p], xv = f + s_o * (double)acc;
+            X[p] = xv;
+            dsum += f - xv;
+        } else {
+            yout[p] = acc;
+        }
     }
-    if (X)
-        X[p] = phi[p] + s_o * (double)acc;
-    else
-        yout[p] = acc;
+    if (diff_part) {
+        const double t = block_sum_det(dsum, red);
+        if (threadIdx.x == 0) diff_part[blockIdx.x] = t;
+    }
 }
 
 // dy = scale * 2 (y - t) / HW and per-block partials of sum (y - t)^2
@@ -863,13 +873,14 @@ pfc_status forward_into(pfc_net* net, hipStream_t s, const float* x, int ny, int
 // floats), layer 3 with the output layer's per-tap sums into taps (9 HW floats; a3 is never
 // stored), and the output sum.  Output y_out, or X = phi + s_o y when X is given.
 pfc_status infer_into(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* a2, float* taps,
-                      float* y_out, const double* phi, double s_o, double* X) {
+                      float* y_out, const double* phi, double s_o, double* X, double* diff_part = nullptr) {
     const long HW = (long)ny * nx;
     hipLaunchKernelGGL(k_conv12_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, x, pack1_of(net),
                        net->d_q + OFF_B1, pack_of(net, 0), net->d_q + OFF_B2, a2, ny, nx);
     hipLaunchKernelGGL(k_conv32_taps, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
                        net->d_q + OFF_B3, nullptr, pack_of(net, 4), taps, ny, nx);
-    hipLaunchKernelGGL(k_out_sum, dim3(cell_grid(HW)), dim3(256), 0, s, taps, net->d_q, ny, nx, y_out, phi, s_o, X);
+    const dim3 sum_grid = diff_part ? dim3(kRedBlocks) : dim3(cell_grid(HW));
+    hipLaunchKernelGGL(k_out_sum, sum_grid, dim3(256), 0, s, taps, net->d_q, ny, nx, y_out, phi, s_o, X, diff_part);
     NETCHK(hipGetLastError());
     return PFC_OK;
 }
@@ -899,7 +910,7 @@ namespace pfc {
 // for the solver: learned initial guess X = phi + s_o * net(x(phi, prev)), before the mass shift
 pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
                      double ratio, const double* scales, const double* sum_part, int np, const NetWork& w,
-                     double* X) {
+                     double* X, double* diff_part) {
     const long n = (long)ny * nx;
     if (!net->prepared) {
         net->err = "network parameters changed since pfc_attach_net: attach it again";
@@ -908,7 +919,7 @@ pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const doubl
     hipLaunchKernelGGL(k_net_input, dim3(grid_for(n)), dim3(256), 0, s, phi, prev, n, ratio, 1.0 / scales[0],
                        1.0 / scales[1], sum_part, np, w.x);
     static_assert(kNetWorkFloats == WID + 9, "inference workspace: a2, then the tap sums");
-    return infer_into(net, s, w.x, ny, nx, w.a, w.a + (size_t)WID * n, nullptr, phi, scales[2], X);
+    return infer_into(net, s, w.x, ny, nx, w.a, w.a + (size_t)WID * n, nullptr, phi, scales[2], X, diff_part);
 }
 
 pfc_status net_prepare(pfc_net* net) {

@@ -194,7 +194,9 @@ hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, d
 // s is stored in *shift_out when given.
 hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt, const double* shift_part,
                      int shift_n, double shift_scale, double* shift_out, double* Jv);
-hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2);
+// energy and mass partials of phi; with acc_phi also acc_prev <- acc_phi, acc_phi <- phi
+hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2, double* acc_phi = nullptr,
+                         double* acc_prev = nullptr);
 
 // ---- BLAS-1 (blas.hip) ----
 hipError_t launch_dot(hipStream_t s, const double* x, const double* y, long n, double* partials);
@@ -203,7 +205,10 @@ hipError_t launch_reduce_rows_n(hipStream_t s, const double* partials, int rows,
 hipError_t launch_multidot(hipStream_t s, const double* V, long ld, int k, const double* w, long n,
                            double* partials);
 hipError_t launch_maxpy(hipStream_t s, const double* V, long ld, int k, const double* coef_part, int coef_n,
-                        double sign, double* w, long n, double* norm_part, double* coef_out);
+                        double sign, double* w, long n, double* norm_part, double* coef_out, bool assign = false,
+                        const double* shift_part = nullptr, int shift_n = 0, double shift_scale = 0.0);
+hipError_t launch_maxpy_dot(hipStream_t s, const double* V, long ld, int k, const double* coef_part, int coef_n,
+                            double sign, double* w, long n, double* dot_part, double* coef_out);
 hipError_t launch_axpby(hipStream_t s, double a, const double* x, double b, const double* y,
                         double* out, long n);
 hipError_t launch_scale(hipStream_t s, const double* x, double a, double* out, long n);
@@ -221,10 +226,11 @@ hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_p
 
 // ---- learned initial guess (net.hip) ----
 // X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)), using the buffers w;
-// before the mass shift.  The network must be prepared (net_prepare) and not trained meanwhile.
+// before the mass shift.  diff_part (nullable) receives kRedBlocks partial sums of phi - X for
+// that shift.  The network must be prepared (net_prepare) and not trained meanwhile.
 pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
                      double ratio, const double* scales, const double* sum_part, int np, const NetWork& w,
-                     double* X);
+                     double* X, double* diff_part);
 // Round and pack the current parameters for inference (synchronises the network's stream).
 pfc_status net_prepare(pfc_net* net);
 const char* net_error(const pfc_net* net);

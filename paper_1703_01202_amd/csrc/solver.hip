@@ -257,10 +257,10 @@ pfc_status enqueue_arnoldi_step(pfc_ctx* c, int j, double dt) {
     double* pj = proj ? part_apply(c, j) : nullptr;
     CHK(apply_raw(c, V + (long)j * N, zj, pj));
     CHK(jv_impl(c, zj, dt, pj, c->d_hpin + SC_M + j, w));
-    // CGS2: h = V^T w ; w -= V h ; h2 = V^T w ; w -= V h2 (norm fused)
+    // CGS2: h = V^T w ; w -= V h and h2 = V^T w in one pass ; w -= V h2 (norm fused)
     HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md1(c)));
-    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, nullptr, c->d_hpin + SC_H));
-    HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md2(c)));
+    HIPCHK(launch_maxpy_dot(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, part_md2(c),
+                            c->d_hpin + SC_H));
     HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_hpin + SC_P,
                         c->d_hpin + SC_H2));
     return PFC_OK;
@@ -312,10 +312,12 @@ pfc_status arnoldi_step(pfc_ctx* c, int j, double dt) {
 
 // Right-preconditioned flexible GMRES(m) from x = 0 on J x = b (Sec. 4, Eq. (21)).
 // Classical Gram-Schmidt with one re-orthogonalisation pass; Givens rotations on the host.
-// bnorm_in >= 0 is ||b|| when the caller knows it (saves one synchronisation).  Returns with
-// work still enqueued: the caller synchronises before reading x on the host.
+// bnorm_in >= 0 is ||b|| when the caller knows it (saves one synchronisation).  The right-hand
+// side is bsign * b (bsign = +-1), so a caller holding F solves J x = -F without forming -F.
+// x is only written (the first cycle's update assigns it).  Returns with work still
+// enqueued: the caller synchronises before reading x on the host.
 pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol, double atol, int* its,
-                  double* res_out, double bnorm_in = -1.0) {
+                  double* res_out, double bnorm_in = -1.0, double bsign = 1.0) {
     const long N = c->g.N;
     const int m = c->opts.gmres_restart;
     const int maxit = c->opts.gmres_maxit;
@@ -323,23 +325,25 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
     double bnorm = bnorm_in;
     if (bnorm < 0.0) CHK(norm2(c, b, &bnorm));
     const double target = std::max(rtol * bnorm, atol);
-    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
     *its = 0;
     *res_out = bnorm;
-    if (bnorm <= target) return PFC_OK;
+    if (bnorm <= target) {
+        HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
+        return PFC_OK;
+    }
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(SC_SHIFT - SC_Y + 1, 0.0);
     double* V = c->d_V;
     double* Z = c->d_Z;
     double beta = bnorm;
-    bool first = true;
+    bool first = true, x_zero = true;
     int total = 0;
     while (true) {
-        // r = b - J x  (x = 0 on the first cycle)
+        // r = bsign b - J x  (x = 0 on the first cycle)
         if (first) {
-            HIPCHK(launch_scale(c->stream, b, 1.0 / beta, V, N));
+            HIPCHK(launch_scale(c->stream, b, bsign / beta, V, N));
         } else {
             CHK(jv_impl(c, x, dt, nullptr, nullptr, c->d_r));
-            HIPCHK(launch_axpby(c->stream, 1.0, b, -1.0, c->d_r, c->d_r, N));
+            HIPCHK(launch_axpby(c->stream, bsign, b, -1.0, c->d_r, c->d_r, N));
             CHK(norm2(c, c->d_r, &beta));
             if (beta <= target) {
                 *res_out = beta;
@@ -398,8 +402,10 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
         std::copy(y.begin(), y.end(), c->h_y);
         HIPCHK(hipMemcpyAsync(c->d_scal + SC_Y, c->h_y, sizeof(double) * (SC_SHIFT - SC_Y + 1), hipMemcpyHostToDevice,
                               c->stream));
-        HIPCHK(launch_maxpy(c->stream, Z, N, jdone, c->d_scal + SC_Y, 1, 1.0, x, N, nullptr, nullptr));
-        if (proj) HIPCHK(launch_shift(c->stream, x, c->d_scal + SC_SHIFT, 1, -1.0, N));
+        // x (+)= Z y, minus the shift when projecting, in one pass
+        HIPCHK(launch_maxpy(c->stream, Z, N, jdone, c->d_scal + SC_Y, 1, 1.0, x, N, nullptr, nullptr, x_zero,
+                            proj ? c->d_scal + SC_SHIFT : nullptr, 1, -1.0));
+        x_zero = false;
         if (conv || total >= maxit) break;
     }
     *its = total;
@@ -459,10 +465,9 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
             HIPCHK(launch_coef(c, c->d_X, phi, c->d_c));
         }
         // J S = -F
-        HIPCHK(launch_scale(c->stream, c->d_F, -1.0, c->d_T, N));
         int its = 0;
         double lres = 0;
-        pfc_status s = fgmres(c, c->d_T, c->d_S, dt, c->opts.lin_rtol, c->opts.lin_atol, &its, &lres, fn);
+        pfc_status s = fgmres(c, c->d_F, c->d_S, dt, c->opts.lin_rtol, c->opts.lin_atol, &its, &lres, fn, -1.0);
         st->gmres_its += its;
         if (s != PFC_OK && s != PFC_EKRYLOV) return s;
         // backtracking line search on ||F||
@@ -490,9 +495,12 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
     return PFC_OK;
 }
 
-pfc_status energy_impl(pfc_ctx* c, const double* phi, double* e, double* m) {
+// energy and mass of phi; with acc_phi the step is accepted in the same pass
+// (acc_prev <- acc_phi, acc_phi <- phi)
+pfc_status energy_impl(pfc_ctx* c, const double* phi, double* e, double* m, double* acc_phi = nullptr,
+                       double* acc_prev = nullptr) {
     const int np = energy_partial_count(c);
-    HIPCHK(launch_energy(c, phi, c->d_hpin + SC_P));
+    HIPCHK(launch_energy(c, phi, c->d_hpin + SC_P, acc_phi, acc_prev));
     CHK(sync(c));
     *e = host_sum(c, 0, np) * c->g.cell_volume;
     *m = host_sum(c, np, np) * c->g.cell_volume;
@@ -546,9 +554,12 @@ pfc_status make_guess(pfc_ctx* c, const double* phi, double dt, int used) {
     } else {
         double* part = part_md1(c);
         HIPCHK(launch_dot(c->stream, phi, nullptr, N, part));
+        double* diff = c->opts.mass_project ? part_md2(c) : nullptr;   // partials of phi - X
         pfc_status s = net_guess(c->net, c->stream, phi, c->d_prev, c->g.ny, c->g.nx, dt / c->dt_nm1, c->net_scale,
-                                 part, kRedBlocks, c->netw, c->d_X);
+                                 part, kRedBlocks, c->netw, c->d_X, diff);
         if (s != PFC_OK) return fail(c, s, std::string("learned guess: ") + net_error(c->net));
+        if (diff) HIPCHK(launch_shift(c->stream, c->d_X, diff, kRedBlocks, 1.0 / (double)N, N));
+        return PFC_OK;
     }
     if (c->opts.mass_project) {   // restore the mass of phi^n exactly: X += mean(phi - X)
         HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
@@ -852,12 +863,10 @@ pfc_status pfc_step(pfc_ctx* c, double* phi, pfc_step_stats* st) {
         st->rejected++;
         dt = std::max(dt * 0.5, o.dt_min / 16);
     }
-    // accept: phi^(n-1) <- phi^n, phi^n <- X
-    HIPCHK(hipMemcpyAsync(c->d_prev, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(phi, c->d_X, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
-    c->have_prev = true;
+    // accept (phi^(n-1) <- phi^n, phi^n <- X) in the pass that forms the energy of X
     double e, m;
-    CHK(energy_impl(c, phi, &e, &m));
+    CHK(energy_impl(c, c->d_X, &e, &m, phi, c->d_prev));
+    c->have_prev = true;
     c->F_nm1 = c->F_n;
     c->F_n = e;
     c->dt_nm1 = dt;

@@ -208,8 +208,11 @@ __global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
 }
 
 // Partial sums of G_d (Eq. (7)) and of phi per block: part[b] and part[nblk + b].
+// With acc_phi (accepting a step): every cell also moves acc_phi -> acc_prev and phi -> acc_phi
+// (phi^(n-1) <- phi^n, phi^n <- phi), the copies done in the same pass.
 __global__ __launch_bounds__(NT) void k_energy2d(const double* __restrict__ phi,
-                                                 double* __restrict__ part, P p) {
+                                                 double* __restrict__ part, P p, double* __restrict__ acc_phi,
+                                                 double* __restrict__ acc_prev) {
     __shared__ double s[TY + 2][TX + 2];
     __shared__ double red[NT / 64];
     const int ntx = (p.nx + TX - 1) / TX;
@@ -231,6 +234,11 @@ __global__ __launch_bounds__(NT) void k_energy2d(const double* __restrict__ phi,
             eg += 0.5 * (1.0 - p.gamma) * f * f + 0.25 * f * f * f * f + 0.5 * lap * lap -
                   0.5 * ((xp * xp + xm * xm) * p.ihx2 + (yp * yp + ym * ym) * p.ihy2);
             em += f;
+            if (acc_phi) {
+                const long q = (long)(y0 + ly - 1) * p.nx + (x0 + lx - 1);
+                acc_prev[q] = acc_phi[q];
+                acc_phi[q] = f;
+            }
         }
     }
     const int nb = gridDim.x, b = blockIdx.x;
@@ -432,11 +440,17 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
     return hipGetLastError();
 }
 
-hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2) {
+hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2, double* acc_phi, double* acc_prev) {
     const P p = make_params(c, 0.0);
     if (c->g.dim == 2) {
-        hipLaunchKernelGGL(k_energy2d, tiles2d(c), dim3(NT), 0, c->stream, phi, part2, p);
+        hipLaunchKernelGGL(k_energy2d, tiles2d(c), dim3(NT), 0, c->stream, phi, part2, p, acc_phi, acc_prev);
     } else {
+        if (acc_phi) {
+            const size_t bytes = sizeof(double) * c->g.N;
+            hipError_t e = hipMemcpyAsync(acc_prev, acc_phi, bytes, hipMemcpyDeviceToDevice, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(acc_phi, phi, bytes, hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(k_mp_energy, dim3(kRedBlocks), dim3(NT), 0, c->stream, phi, part2, p);
     }
     return hipGetLastError();

@@ -19,11 +19,18 @@ def pfc():
     return m
 
 
-@pytest.mark.parametrize("sub_solver", ["ilu0", "lu"])
-def test_timing_mask_counts_and_leaves_results_unchanged(pfc, sub_solver):
-    w = I.crystal_growth(128, (2, 8), nsteps=4)
-    kw = dict(sub_solver=sub_solver, precond_fp32=True, dt_min=w.dt_min, dt_max=10.0, eta=5000.0,
-              newton_rtol=w.newton_rtol, newton_atol=w.newton_atol)
+CASES = {   # ILU(0) on the 64^2 noise workload, FP32 LU boxes on a 128^2 crystal grid (adaptive dt)
+    "ilu0": (I.small_noise_64(), dict(sub_solver="ilu0")),
+    "lu": (I.crystal_growth(128, (2, 8), nsteps=4), dict(sub_solver="lu", dt_max=10.0, eta=5000.0)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_timing_mask_counts_and_leaves_results_unchanged(pfc, case):
+    w, extra = CASES[case]
+    kw = dict(precond_fp32=True, dt_min=w.dt_min, dt_max=w.dt_max, newton_rtol=w.newton_rtol,
+              newton_atol=w.newton_atol)
+    kw.update(extra)
     phi0 = torch.from_numpy(w.initial()).cuda()
     runs = {}
     for name, timing in [("off", 0), ("apply", 1), ("all", True)]:

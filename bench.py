@@ -278,6 +278,31 @@ def run_3d(steps):
     return out
 
 
+def hbm_reference(gib=1):
+    """What this GPU's HBM sustains for plain streams, beside the roofline's nominal 8 TB/s: a
+    read-only reduction (torch sum) and a device copy of `gib` GiB, event-timed, 10 runs each."""
+    import torch
+    n = gib * (1 << 27)
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn, moved in (("read_sum", lambda: a.sum(), 8 * n), ("copy", lambda: b.copy_(a), 16 * n)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out[name] = {"us": ms * 1e3, "GB_per_s": moved / ms / 1e6}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_bench(steps, workers_list=(1, 16)):
     """64 independent instances of uneven size (sides 128..512, gamma 0.1..0.4, mean
     -0.35..-0.2, noise 0.05, h = pi/2), adaptive dt, extrapolated guess, exact subdomain LU
@@ -369,6 +394,7 @@ def main():
         cmp_res = run_variant(args.compare, args.steps, args.warmup, net=net, net_meta=net_meta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
     batch = None if args.no_batch else batch_bench(args.batch_steps)
+    hbm_ref = hbm_reference()
     three_d = None if args.no_3d else run_3d(args.steps_3d)
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
@@ -406,6 +432,7 @@ def main():
         out["detail"]["batch_64_ragged"] = batch
     if three_d is not None:
         out["detail"]["pfc3d_128_noise"] = three_d
+    out["detail"]["hbm_reference"] = hbm_ref
     print(json.dumps(out), flush=True)
 
 

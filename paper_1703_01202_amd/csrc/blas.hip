@@ -130,6 +130,18 @@ __global__ __launch_bounds__(NT) void k_maxpy_dot(const double* __restrict__ V, 
     }
 }
 
+// w <- w / h with h = sqrt(sum(part[0..np))) (the Arnoldi normalisation, summed on the
+// device); block 0 stores h in h_out.  w is left as it is when h is not positive.
+__global__ __launch_bounds__(NT) void k_normalize(double* __restrict__ w, const double* __restrict__ part, int np,
+                                                  long n, double* __restrict__ h_out) {
+    __shared__ double red[NT / 64];
+    const double h = sqrt(sum_partials_bcast(part, np, red));
+    if (h_out && blockIdx.x == 0 && threadIdx.x == 0) *h_out = h;
+    if (!(h > 0.0)) return;
+    const double s = 1.0 / h;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) w[i] = s * w[i];
+}
+
 __global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
                         double* __restrict__ out, long n) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -191,6 +203,11 @@ hipError_t launch_maxpy_dot(hipStream_t s, const double* V, long ld, int k, cons
     }
     hipLaunchKernelGGL(k_maxpy_dot, dim3(kRedBlocks), dim3(NT), 0, s, V, ld, k, coef_part, coef_n, sign, w, n,
                        dot_part, coef_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(hipStream_t s, double* w, const double* part, int np, long n, double* h_out) {
+    hipLaunchKernelGGL(k_normalize, dim3(kRedBlocks), dim3(NT), 0, s, w, part, np, n, h_out);
     return hipGetLastError();
 }
 

@@ -209,6 +209,7 @@ hipError_t launch_maxpy(hipStream_t s, const double* V, long ld, int k, const do
                         const double* shift_part = nullptr, int shift_n = 0, double shift_scale = 0.0);
 hipError_t launch_maxpy_dot(hipStream_t s, const double* V, long ld, int k, const double* coef_part, int coef_n,
                             double sign, double* w, long n, double* dot_part, double* coef_out);
+hipError_t launch_normalize(hipStream_t s, double* w, const double* part, int np, long n, double* h_out);
 hipError_t launch_axpby(hipStream_t s, double a, const double* x, double b, const double* y,
                         double* out, long n);
 hipError_t launch_scale(hipStream_t s, const double* x, double a, double* out, long n);

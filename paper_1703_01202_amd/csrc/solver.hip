@@ -29,13 +29,17 @@ using namespace pfc;
 namespace {
 
 // d_scal: scalar slots, then (from SC_P) partials that the host sums after one copy
-constexpr int kScal = 320;
-constexpr int SC_H = 8;         // first Gram-Schmidt coefficients (64)
-constexpr int SC_H2 = 80;       // second pass coefficients (64)
-constexpr int SC_Y = 160;       // update coefficients (64)
-constexpr int SC_SHIFT = 240;   // shift of the update
-constexpr int SC_M = 256;       // means of the preconditioned vectors z_j (64)
-constexpr int SC_P = kScal;     // host-summed partials (norms, residual, energy)
+// Layout of d_scal / h_pin in doubles.  The Gram-Schmidt coefficients of Arnoldi step j go to
+// half j % 2 of their region, so two steps can be in flight before the host reads them.
+constexpr int kScal = 464;
+constexpr int SC_H = 8;         // first Gram-Schmidt coefficients (2 x 64)
+constexpr int SC_H2 = 136;      // second pass coefficients (2 x 64)
+constexpr int SC_Y = 264;       // update coefficients (64)
+constexpr int SC_SHIFT = 328;   // shift of the update
+constexpr int SC_M = 336;       // means of the preconditioned vectors z_j (64)
+constexpr int SC_HN = 400;      // norms of the new basis vectors, h_(j+1,j) (64)
+constexpr int SC_P = kScal;     // partials: host-summed ones in h_pin, device-summed norms in d_scal
+inline int sc_half(int j) { return 64 * (j & 1); }
 
 // d_part: partials summed by the next kernel on the device
 //   [0, 64 R)        first Gram-Schmidt pass, row j = partials of v_j . w  (R = kRedBlocks)
@@ -243,9 +247,11 @@ pfc_status apply_impl(pfc_ctx* c, const double* r, double* z) {
 }
 
 // One Arnoldi step j of FGMRES, enqueued: z_j = H^-1 v_j, w = J z_j, two classical
-// Gram-Schmidt passes against v_0..v_j (norm partials fused).  The values the host needs
-// (mean of z_j, both coefficient columns, norm partials) are written by the kernels straight
-// into the mapped host buffer, so the step has no copy.
+// Gram-Schmidt passes against v_0..v_j (norm partials fused), and v_(j+1) = w / ||w|| with
+// the norm summed on the device.  The values the host needs (mean of z_j, both coefficient
+// columns, h_(j+1,j)) are written by the kernels straight into the mapped host buffer, so the
+// step has no copy and needs no host value: the next step can be enqueued before the host
+// has read this one.
 pfc_status enqueue_arnoldi_step(pfc_ctx* c, int j, double dt) {
     const long N = c->g.N;
     const bool proj = c->opts.mass_project;
@@ -257,12 +263,14 @@ pfc_status enqueue_arnoldi_step(pfc_ctx* c, int j, double dt) {
     double* pj = proj ? part_apply(c, j) : nullptr;
     CHK(apply_raw(c, V + (long)j * N, zj, pj));
     CHK(jv_impl(c, zj, dt, pj, c->d_hpin + SC_M + j, w));
-    // CGS2: h = V^T w ; w -= V h and h2 = V^T w in one pass ; w -= V h2 (norm fused)
+    // CGS2: h = V^T w ; w -= V h and h2 = V^T w in one pass ; w -= V h2 (norm partials fused)
     HIPCHK(launch_multidot(c->stream, V, N, j + 1, w, N, part_md1(c)));
     HIPCHK(launch_maxpy_dot(c->stream, V, N, j + 1, part_md1(c), kRedBlocks, -1.0, w, N, part_md2(c),
-                            c->d_hpin + SC_H));
-    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_hpin + SC_P,
-                        c->d_hpin + SC_H2));
+                            c->d_hpin + SC_H + sc_half(j)));
+    HIPCHK(launch_maxpy(c->stream, V, N, j + 1, part_md2(c), kRedBlocks, -1.0, w, N, c->d_scal + SC_P,
+                        c->d_hpin + SC_H2 + sc_half(j)));
+    // v_(j+1) = w / ||w|| on the device; ||w|| = h_(j+1,j) goes to the host
+    HIPCHK(launch_normalize(c->stream, w, c->d_scal + SC_P, kRedBlocks, N, c->d_hpin + SC_HN + j));
     return PFC_OK;
 }
 
@@ -322,6 +330,7 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
     const int m = c->opts.gmres_restart;
     const int maxit = c->opts.gmres_maxit;
     const bool proj = c->opts.mass_project;
+    const bool lookahead = c->last_gpn >= 1.5;
     double bnorm = bnorm_in;
     if (bnorm < 0.0) CHK(norm2(c, b, &bnorm));
     const double target = std::max(rtol * bnorm, atol);
@@ -356,35 +365,43 @@ pfc_status fgmres(pfc_ctx* c, const double* b, double* x, double dt, double rtol
         g[0] = beta;
         int jdone = 0;
         bool conv = false;
-        for (int j = 0; j < m; ++j) {
-            double* w = V + (long)(j + 1) * N;
+        // Arnoldi steps are enqueued one or two at a time (lookahead: the next step goes in
+        // before the host reads this one, one synchronisation for both; used when the last
+        // time step needed two or more iterations per linear solve, and wasted only when a
+        // solve converges at its first step of a pair)
+        for (int j = 0; j < m && !conv && total < maxit;) {
+            const bool ahead = lookahead && j + 1 < m && total + 1 < maxit;
             CHK(arnoldi_step(c, j, dt));
+            if (ahead) CHK(arnoldi_step(c, j + 1, dt));
             CHK(sync(c));
-            const double hn = std::sqrt(host_sum(c, 0, kRedBlocks));
-            if (!std::isfinite(hn)) return fail(c, PFC_ENAN, "non-finite Arnoldi norm");
-            for (int i = 0; i <= j; ++i) H[i * m + j] = c->h_pin[SC_H + i] + c->h_pin[SC_H2 + i];
-            H[(j + 1) * m + j] = hn;
-            if (hn > 0.0) HIPCHK(launch_scale(c->stream, w, 1.0 / hn, w, N));
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-                H[i * m + j] = t;
+            const int jend = ahead ? j + 2 : j + 1;
+            for (; j < jend; ++j) {
+                const double hn = c->h_pin[SC_HN + j];
+                if (!std::isfinite(hn)) return fail(c, PFC_ENAN, "non-finite Arnoldi norm");
+                for (int i = 0; i <= j; ++i)
+                    H[i * m + j] = c->h_pin[SC_H + sc_half(j) + i] + c->h_pin[SC_H2 + sc_half(j) + i];
+                H[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                    H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                    H[i * m + j] = t;
+                }
+                const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+                cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
+                sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
+                H[j * m + j] = den;
+                H[(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                ++total;
+                jdone = j + 1;
+                *res_out = std::fabs(g[j + 1]);
+                if (*res_out <= target || hn == 0.0) {
+                    conv = true;
+                    break;
+                }
+                if (total >= maxit) break;
             }
-            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-            cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
-            sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
-            H[j * m + j] = den;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++total;
-            jdone = j + 1;
-            *res_out = std::fabs(g[j + 1]);
-            if (*res_out <= target || hn == 0.0) {
-                conv = true;
-                break;
-            }
-            if (total >= maxit) break;
         }
         // y = R^{-1} g ; x += Z y
         for (int i = jdone - 1; i >= 0; --i) {

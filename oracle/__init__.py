@@ -14,8 +14,9 @@ Modules
              (Sec. 4, Eqs. (17)-(20)) and adaptive time stepping (Sec. 3, Eq. (16)).
 ``schwarz``  reference routines for the solver pieces that are approximations
              rather than definitions: the overlapping decomposition, the Schwarz
-             preconditioners (Sec. 4, Eqs. (22)-(26)), textbook ILU(0) and
-             right-preconditioned (F)GMRES (Sec. 4, Eq. (21)).
+             preconditioners (Sec. 4, Eqs. (22)-(26)), textbook ILU(0),
+             right-preconditioned (F)GMRES (Sec. 4, Eq. (21)) and the inexact
+             Newton-Krylov-Schwarz time step they make up (Eqs. (17)-(24)).
 ``cnn``      FP64 reference of the small convolutional network used as a learned
              Newton initial guess (forward, hand-written backward, Adam).
 

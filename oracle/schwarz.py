@@ -378,3 +378,60 @@ def arnoldi_mgs(matvec, precond, b, m):
         H[j + 1, j] = float(np.linalg.norm(w))
         V[j + 1] = w / H[j + 1, j]
     return V, Z, H
+
+
+# ---------------------------------------------------------------------------
+# The paper's inexact Newton-Krylov-Schwarz step (Sec. 4, Eqs. (17)-(24))
+# ---------------------------------------------------------------------------
+
+@dataclass
+class NksResult:
+    Phi: np.ndarray
+    newton: int            # Newton iterations taken
+    gmres: int             # FGMRES iterations over all of them
+    res_norms: list        # ||F|| at Phi_0, Phi_1, ...
+
+
+def nks_step(phi_n, dt, gamma, h, sub, overlap, kind="lu", variant="left", eps_r=1e-8, eps_a=1e-10,
+             xi_r=1e-3, xi_a=1e-11, restart=30, maxit=300, newton_maxit=30):
+    """One time step phi^n -> phi^(n+1) by the inexact Newton iteration of Sec. 4.
+
+    Phi_0 = phi^n (Eq. (17)).  While ||F(Phi_m)|| > max(eps_r ||F(Phi_0)||, eps_a)
+    (Eq. (20)), the correction solves J(Phi_m) S = -F(Phi_m) by right-preconditioned
+    FGMRES from S = 0, stopped at max(xi_r ||F(Phi_m)||, xi_a) (Eq. (21)), with the
+    Schwarz operator ``variant`` (classical AS 'as', left-RAS 'left', right-RAS 'right';
+    Eqs. (22)-(24)).  The subdomain solvers are built from the Jacobian at Phi_0 and kept
+    for the whole step (the reuse strategy of Table 1).  Phi_(m+1) = Phi_m + lam S with lam
+    halved from 1 until ||F|| falls by the Armijo factor (Eq. (18)).  The defaults are the
+    tolerances the paper lists for its experiments (Sec. 5).
+    """
+    from .scheme import ARMIJO, LAMBDA_MIN, jacobian_csr, residual
+
+    Phi = np.asarray(phi_n, dtype=np.float64).copy()
+    shape = Phi.shape
+    doms = decompose(shape, sub, overlap)
+    F = residual(Phi, phi_n, dt, gamma, h)
+    norms = [float(np.linalg.norm(F))]
+    target = max(eps_r * norms[0], eps_a)
+    solvers = schwarz_setup(jacobian_csr(Phi, phi_n, dt, gamma, h), doms, kind)
+    newton = gmres = 0
+    while norms[-1] > target and newton < newton_maxit:
+        J = jacobian_csr(Phi, phi_n, dt, gamma, h)
+        res = fgmres(lambda v: J @ v, lambda r: schwarz_apply(r, doms, solvers, variant), -F.ravel(),
+                     xi_r, xi_a, restart=restart, maxit=maxit)
+        gmres += res.iterations
+        S = res.x.reshape(shape)
+        fn, lam = norms[-1], 1.0
+        while True:
+            trial = Phi + lam * S
+            Ft = residual(trial, phi_n, dt, gamma, h)
+            ftn = float(np.linalg.norm(Ft))
+            if ftn <= (1.0 - ARMIJO * lam) * fn:
+                break
+            if lam <= LAMBDA_MIN:
+                raise RuntimeError("line search failed")
+            lam *= 0.5
+        Phi, F = trial, Ft
+        norms.append(ftn)
+        newton += 1
+    return NksResult(Phi=Phi, newton=newton, gmres=gmres, res_norms=norms)

@@ -426,3 +426,30 @@ def test_newton_count_matches_table1_test_b(sub, fp32):
     assert all(b <= a + 1e-12 * abs(a) for a, b in zip(energy, energy[1:]))
     if not fp32:
         assert abs(gmres / newton - ref["gmres_per_newton"]["LU"]) <= 0.2 * ref["gmres_per_newton"]["LU"]
+
+
+def test_newton_count_matches_tables_test_d_3d():
+    """The paper's printed Newton count for Test D (Sec. 5, Tables 1 and 2): 31 Newton
+    iterations over the first 10 fixed steps of dt = 0.1 on the 128^3 BCC-crystallite field
+    (domain scaled to [0, 40 pi]^3), tolerances of Sec. 5, left-RAS with delta = 1 (3 layers)
+    and ILU(0) subdomain solves; here 512 boxes.  Energy must not increase."""
+    import json
+    import os
+
+    pfc = _pfc()
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "test_d_newton_counts.json")))
+    st = g["setup"]
+    n = st["mesh"][0]
+    L = st["domain_scale_of_pi"] * math.pi
+    s = pfc.Solver(tuple(st["mesh"]), (L, L, L), st["gamma"], (8, 8, 8), 3, sub_solver="ilu0", precond_fp32=False,
+                   guess="previous", dt_min=st["dt"], dt_max=st["dt"], newton_rtol=st["eps_r"],
+                   newton_atol=st["eps_a"], lin_rtol=st["xi_r"], lin_atol=st["xi_a"], mass_project=False)
+    phi = T(I.bcc_spheres_ic(n=n, L=L))
+    newton, energy = 0, []
+    for _ in range(st["steps"]):
+        stt = s.step(phi)
+        newton += stt["newton_its"]
+        energy.append(stt["energy"])
+    s.close()
+    assert newton == g["table2_total_newton"]["left-RAS delta 1"]
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(energy, energy[1:]))

@@ -67,7 +67,11 @@ typedef struct {
     int mobility;
 } pfc_model;
 
-enum { PFC_RAS_LEFT = 0 };                         /* left-RAS, Eq. (23) */
+/* Schwarz preconditioners (Sec. 4): left-RAS (Eq. (23)): restrict with overlap, extend the owned
+ * cells only; classical AS (Eq. (22)): restrict and extend with overlap, the boxes' solutions
+ * added where they overlap; right-RAS (Eq. (24)): restrict the owned cells only, extend with
+ * overlap and add.  The sums over overlapping boxes are formed per cell in a fixed order. */
+enum { PFC_RAS_LEFT = 0, PFC_AS_CLASSICAL = 1, PFC_RAS_RIGHT = 2 };
 enum { PFC_SUB_ILU0 = 0, PFC_SUB_LU = 1 };         /* subdomain solvers (Sec. 4) */
 enum { PFC_GUESS_PREVIOUS = 0, PFC_GUESS_EXTRAP = 1, PFC_GUESS_LEARNED = 2 };
 
@@ -79,7 +83,7 @@ typedef struct {
     int gmres_maxit;                  /* per Newton step, default 300 */
     int sub[3];                       /* subdomains per axis (x, y, z) */
     int overlap;                      /* overlap in mesh layers (paper's delta = 3 layers) */
-    int ras_kind;                     /* PFC_RAS_LEFT */
+    int ras_kind;                     /* PFC_RAS_LEFT (default), PFC_AS_CLASSICAL or PFC_RAS_RIGHT */
     int sub_solver;                   /* PFC_SUB_ILU0 or PFC_SUB_LU (2-D only) */
     int precond_fp32;                 /* 1: factors stored and applied in FP32 */
     int mass_project;                 /* 1: zero-mean projection of guess and directions */

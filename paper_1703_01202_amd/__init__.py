@@ -25,7 +25,7 @@ def _ptr(t):
 def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precond_fp32=False, dt_min=0.1,
              dt_max=None, eta=0.0, newton_rtol=1e-8, newton_atol=1e-10, lin_rtol=1e-3, lin_atol=1e-11,
              gmres_restart=30, gmres_maxit=300, newton_maxit=50, guess="previous", mass_project=True,
-             max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True, use_graph=False):
+             max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True, use_graph=False, ras_kind="left"):
     """pfc_grid, pfc_model and pfc_opts for a grid given in array-axis order."""
     shape = tuple(int(s) for s in shape)
     dim = len(shape)
@@ -51,6 +51,7 @@ def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precon
         o.sub[a] = revS[a] if a < dim else 1
     o.overlap = int(overlap)
     o.sub_solver = _lib.SUB_SOLVERS[sub_solver]
+    o.ras_kind = _lib.RAS_KINDS[ras_kind]
     o.precond_fp32 = int(bool(precond_fp32))
     o.mass_project = int(bool(mass_project))
     o.guess = _lib.GUESS[guess]
@@ -78,7 +79,8 @@ class Solver:
         newton_atol, lin_rtol, lin_atol, gmres_restart, gmres_maxit, newton_maxit, guess
         ("previous" | "extrap" | "learned"), mass_project, max_retries, timing (True, or the
         bitmask of pfc_opts.timing), precond_lag,
-        newton_rel_ref, use_graph (needs ``stream``: a non-default stream handle)."""
+        newton_rel_ref, use_graph (needs ``stream``: a non-default stream handle), ras_kind
+        ("left" | "as" | "right": left-RAS, classical AS, right-RAS)."""
         import torch
         self._torch = torch
         self.lib = _lib.load()

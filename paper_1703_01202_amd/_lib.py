@@ -19,6 +19,7 @@ PFC_OK = 0
 STATUS = {0: "PFC_OK", -1: "PFC_EINVAL", -2: "PFC_ENOMEM", -3: "PFC_EHIP", -4: "PFC_ENAN",
           -5: "PFC_ENOTCONV", -6: "PFC_EKRYLOV", -7: "PFC_EPIVOT", -8: "PFC_EUNSUP"}
 SUB_SOLVERS = {"ilu0": 0, "lu": 1}
+RAS_KINDS = {"left": 0, "as": 1, "right": 2}
 GUESS = {"previous": 0, "extrap": 1, "learned": 2}
 
 

@@ -99,6 +99,7 @@ struct pfc_ctx {
     void* d_fac = nullptr;             // packed factors (double or float)
     size_t fac_elems = 0;
     int* d_flag = nullptr;             // pivot failure flag
+    double* d_zbox = nullptr;          // per-box extended solutions (classical AS, right-RAS)
     int lu_W = 0, lu_H = 0;            // exact LU: block size (box x-extent) and block rows
 
     // vectors (N doubles each)
@@ -224,6 +225,9 @@ hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
 hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
+// z = sum over the boxes covering each cell of their extended solutions in zbox (classical AS
+// and right-RAS), in a fixed order per cell
+hipError_t launch_schwarz_sum(const pfc_ctx* c, const double* zbox, double* z);
 
 // ---- learned initial guess (net.hip) ----
 // X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)), using the buffers w;

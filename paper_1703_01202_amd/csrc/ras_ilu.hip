@@ -191,7 +191,8 @@ template <typename T, int S>
 __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, double* __restrict__ z,
                                                   const T* __restrict__ fac, const int* __restrict__ lptr,
                                                   const int* __restrict__ lpts, Box b, StencilTable st,
-                                                  int nlev, double* __restrict__ sum_part) {
+                                                  int nlev, double* __restrict__ sum_part, int mode,
+                                                  double* __restrict__ zbox) {
     extern __shared__ unsigned char smem_raw[];
     T* yv = reinterpret_cast<T*>(smem_raw);
     constexpr int D = S / 2;                  // centre of the natural-order stencil
@@ -199,9 +200,13 @@ __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, 
     const int k = blockIdx.x;
     int ox, oy, oz;
     box_origin(b, k, &ox, &oy, &oz);
+    const int zoff = b.nz > 1 ? b.ov : 0, owz = b.nz > 1 ? b.ownz : 1;
     for (int i = tid; i < b.next; i += blockDim.x) {
         const int x = i % b.ex, y = (i / b.ex) % b.ey, zz = i / (b.ex * b.ey);
-        yv[i] = (T)r[gidx(b, ox, oy, oz, x, y, zz)];
+        // right-RAS restricts the owned cells only (Eq. (24)); the others restrict the whole box
+        const bool own = x >= b.ov && x < b.ov + b.ownx && y >= b.ov && y < b.ov + b.owny && zz >= zoff &&
+                         zz < zoff + owz;
+        yv[i] = (mode != 2 || own) ? (T)r[gidx(b, ox, oy, oz, x, y, zz)] : (T)0;
     }
     __syncthreads();
     const T* F = fac + (long)k * b.next * S;
@@ -294,20 +299,65 @@ __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, 
             for (int q = 0; q < D; ++q) f[q] = fn[q];
         }
     }
-    // restricted extension: write only the owned cells
-    const int owx = b.ownx, owy = b.owny, owz = b.nz > 1 ? b.ownz : 1;
-    const int zoff = b.nz > 1 ? b.ov : 0;
     double acc = 0.0;
-    for (int e = threadIdx.x; e < owx * owy * owz; e += blockDim.x) {
-        const int x = e % owx + b.ov, y = (e / owx) % owy + b.ov, zz = e / (owx * owy) + zoff;
-        const double v = (double)yv[(zz * b.ey + y) * b.ex + x];
-        z[gidx(b, ox, oy, oz, x, y, zz)] = v;
-        acc += v;
+    if (mode == 0) {   // left-RAS: restricted extension, the owned cells only (Eq. (23))
+        const int owx = b.ownx, owy = b.owny;
+        for (int e = threadIdx.x; e < owx * owy * owz; e += blockDim.x) {
+            const int x = e % owx + b.ov, y = (e / owx) % owy + b.ov, zz = e / (owx * owy) + zoff;
+            const double v = (double)yv[(zz * b.ey + y) * b.ex + x];
+            z[gidx(b, ox, oy, oz, x, y, zz)] = v;
+            acc += v;
+        }
+    } else {           // classical AS / right-RAS: the whole extended solution, added per cell later
+        for (int i = threadIdx.x; i < b.next; i += blockDim.x) {
+            const double v = (double)yv[i];
+            zbox[(long)k * b.next + i] = v;
+            acc += v;
+        }
     }
     if (sum_part) {
         __shared__ double red[16];
         const double sum = block_sum_det(acc, red);
         if (threadIdx.x == 0) sum_part[blockIdx.x] = sum;
+    }
+}
+
+// z(p) = sum of zbox over the boxes whose extended region covers cell p (classical AS and
+// right-RAS extension, Eqs. (22), (24)).  Along each axis the candidates are the owner box and
+// ceil(ov / own) boxes on either side (all boxes, in order, when that reaches round the
+// periodic axis), so each covering box is visited once, in the same order for every run.
+struct SumGeom {
+    int n[3], sub[3], own[3], ext[3], ovl[3], R[3];
+};
+
+__global__ __launch_bounds__(256) void k_schwarz_sum(const double* __restrict__ zbox, double* __restrict__ z,
+                                                     SumGeom g, long N, int next) {
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < N; p += (long)gridDim.x * blockDim.x) {
+        const int pos[3] = {(int)(p % g.n[0]), (int)((p / g.n[0]) % g.n[1]), (int)(p / ((long)g.n[0] * g.n[1]))};
+        int kb[3][16], lb[3][16], nc[3];
+        for (int a = 0; a < 3; ++a) {
+            const int k0 = pos[a] / g.own[a];
+            const bool all = 2 * g.R[a] + 1 >= g.sub[a];
+            const int cnt = all ? g.sub[a] : 2 * g.R[a] + 1;
+            nc[a] = 0;
+            for (int t = 0; t < cnt; ++t) {
+                const int kk = all ? t : wrapg(k0 - g.R[a] + t, g.sub[a]);
+                const int loc = wrapg(pos[a] - (kk * g.own[a] - g.ovl[a]), g.n[a]);
+                if (loc < g.ext[a]) {
+                    kb[a][nc[a]] = kk;
+                    lb[a][nc[a]] = loc;
+                    ++nc[a];
+                }
+            }
+        }
+        double acc = 0.0;
+        for (int iz = 0; iz < nc[2]; ++iz)
+            for (int iy = 0; iy < nc[1]; ++iy)
+                for (int ix = 0; ix < nc[0]; ++ix) {
+                    const long k = ((long)kb[2][iz] * g.sub[1] + kb[1][iy]) * g.sub[0] + kb[0][ix];
+                    acc += zbox[k * next + ((long)lb[2][iz] * g.ext[1] + lb[1][iy]) * g.ext[0] + lb[0][ix]];
+                }
+        z[p] = acc;
     }
 }
 
@@ -384,12 +434,31 @@ hipError_t launch_ilu_apply_s(pfc_ctx* c, const double* r, double* z, double* su
     if (c->opts.precond_fp32) {
         const size_t sh = sizeof(float) * b.next;
         return launch_k(c, k_ilu_apply<float, S>, dim3(c->dec.nsub), dim3(64), sh, r, z, (const float*)c->d_fac,
-                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
+                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part, c->opts.ras_kind, c->d_zbox);
     } else {
         const size_t sh = sizeof(double) * b.next;
         return launch_k(c, k_ilu_apply<double, S>, dim3(c->dec.nsub), dim3(64), sh, r, z, (const double*)c->d_fac,
-                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part);
+                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part, c->opts.ras_kind, c->d_zbox);
     }
+}
+
+hipError_t launch_schwarz_sum(const pfc_ctx* c, const double* zbox, double* z) {
+    SumGeom g;
+    const int gn[3] = {c->g.nx, c->g.ny, c->g.nz};
+    for (int a = 0; a < 3; ++a) {
+        const bool on = a < c->g.dim;
+        g.n[a] = on ? gn[a] : 1;
+        g.sub[a] = on ? c->dec.sub[a] : 1;
+        g.own[a] = on ? c->dec.own[a] : 1;
+        g.ext[a] = on ? c->dec.ext[a] : 1;
+        g.ovl[a] = on ? c->dec.ov : 0;
+        g.R[a] = (g.ovl[a] + g.own[a] - 1) / g.own[a];
+        if (std::min(2 * g.R[a] + 1, g.sub[a]) > 16) return hipErrorInvalidValue;   // checked by pfc_create
+    }
+    const long N = c->g.N;
+    const unsigned grid = (unsigned)std::min<long>((N + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_schwarz_sum, dim3(grid), dim3(256), 0, c->stream, zbox, z, g, N, c->dec.next);
+    return hipGetLastError();
 }
 
 hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {

@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
 //   backward (half 1): x_I = [S_II^-1 | -Uh(I,I+1..I+3)] y[IW : (I+4)W]    (4W columns)
 template <typename T, int NPL, int DEPTH>
 __global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z, const T* __restrict__ fac,
-                           LuBox b, double* __restrict__ sum_part) {
+                           LuBox b, double* __restrict__ sum_part, int mode, double* __restrict__ zbox) {
     extern __shared__ unsigned char smem_raw[];
     const int W = b.W, H = b.H, WW = W * W;
     T* y = reinterpret_cast<T*>(smem_raw);          // W*H box vector
@@ -478,7 +478,9 @@ __global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z,
 
     for (int e = tid; e < W * H; e += blockDim.x) {
         const int x = e % W, yy = e / W;
-        y[e] = (T)r[(long)wrapg(oy + yy, b.ny) * b.nx + wrapg(ox + x, b.nx)];
+        // right-RAS restricts the owned cells only (Eq. (24)); the others restrict the whole box
+        const bool own = x >= b.ov && x < b.ov + b.ownx && yy >= b.ov && yy < b.ov + b.owny;
+        y[e] = (mode != 2 || own) ? (T)r[(long)wrapg(oy + yy, b.ny) * b.nx + wrapg(ox + x, b.nx)] : (T)0;
     }
 
     T pl[DEPTH + 1][NPL];
@@ -550,13 +552,21 @@ __global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z,
         __syncthreads();
         rotate();
     }
-    // restricted extension: owned cells only (and their sum, for the zero-mean projection)
+    // extension, and the sum of what this box contributes (for the zero-mean projection)
     double acc = 0.0;
-    for (int e = tid; e < b.ownx * b.owny; e += blockDim.x) {
-        const int x = e % b.ownx + b.ov, yy = e / b.ownx + b.ov;
-        const double v = (double)y[yy * W + x];
-        z[(long)wrapg(oy + yy, b.ny) * b.nx + wrapg(ox + x, b.nx)] = v;
-        acc += v;
+    if (mode == 0) {   // left-RAS: owned cells only (Eq. (23))
+        for (int e = tid; e < b.ownx * b.owny; e += blockDim.x) {
+            const int x = e % b.ownx + b.ov, yy = e / b.ownx + b.ov;
+            const double v = (double)y[yy * W + x];
+            z[(long)wrapg(oy + yy, b.ny) * b.nx + wrapg(ox + x, b.nx)] = v;
+            acc += v;
+        }
+    } else {           // classical AS / right-RAS: the whole box, added per cell afterwards
+        for (int e = tid; e < W * H; e += blockDim.x) {
+            const double v = (double)y[e];
+            zbox[(long)k * W * H + e] = v;
+            acc += v;
+        }
     }
     if (sum_part) {
         __shared__ double red[16];
@@ -595,9 +605,13 @@ hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b
     const T* f = (const T*)c->d_fac;
     const dim3 grid(c->dec.nsub), blk(threads);
     if (b.W <= 24)
-        return launch_k(c, k_lu_apply<T, 10, f32 ? 3 : 1>, grid, blk, sh, r, z, f, b, sum_part);
-    if (b.W <= 32) return launch_k(c, k_lu_apply<T, 16, f32 ? 2 : 1>, grid, blk, sh, r, z, f, b, sum_part);
-    return launch_k(c, k_lu_apply<T, 21, f32 ? 1 : 0>, grid, blk, sh, r, z, f, b, sum_part);
+        return launch_k(c, k_lu_apply<T, 10, f32 ? 3 : 1>, grid, blk, sh, r, z, f, b, sum_part, c->opts.ras_kind,
+                        c->d_zbox);
+    if (b.W <= 32)
+        return launch_k(c, k_lu_apply<T, 16, f32 ? 2 : 1>, grid, blk, sh, r, z, f, b, sum_part, c->opts.ras_kind,
+                        c->d_zbox);
+    return launch_k(c, k_lu_apply<T, 21, f32 ? 1 : 0>, grid, blk, sh, r, z, f, b, sum_part, c->opts.ras_kind,
+                    c->d_zbox);
 }
 
 }  // namespace

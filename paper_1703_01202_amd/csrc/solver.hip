@@ -228,13 +228,17 @@ bool may_reuse_factors(const pfc_ctx* c, double dt) {
 }
 
 // z = H^-1 r; with sum_part the apply kernel also leaves one partial sum of z per subdomain.
+// Classical AS and right-RAS leave each box's extended solution in d_zbox, added per cell by
+// a second kernel.
 pfc_status apply_raw(pfc_ctx* c, const double* r, double* z, double* sum_part) {
+    const bool left = c->opts.ras_kind == PFC_RAS_LEFT;
     int ts;
-    timer_begin(c, 0, &ts, true);
+    timer_begin(c, 0, &ts, left);
     if (c->opts.sub_solver == PFC_SUB_LU)
         HIPCHK(launch_lu_apply(c, r, z, sum_part));
     else
         HIPCHK(launch_ilu_apply(c, r, z, sum_part));
+    if (!left) HIPCHK(launch_schwarz_sum(c, c->d_zbox, z));
     timer_end(c, ts);
     return PFC_OK;
 }
@@ -537,7 +541,7 @@ pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
 void free_all(pfc_ctx* c) {
     void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, c->d_fac, c->d_flag, c->d_c,
                     c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
-                    c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.a};
+                    c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.a, c->d_zbox};
     for (void* p : ptrs)
         if (p) hipFree(p);
     drop_graphs(c);
@@ -646,7 +650,12 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (s == PFC_OK && (op->gmres_maxit < 1 || op->newton_maxit < 1)) s = bad("iteration limits must be >= 1");
     if (s == PFC_OK && op->precond_lag < 0) s = bad("precond_lag must be >= 0");
     if (s == PFC_OK && op->use_graph && !stream) s = bad("use_graph needs a non-default stream (graph capture)");
-    if (s == PFC_OK && op->ras_kind != PFC_RAS_LEFT) s = bad("only left-RAS is built");
+    if (s == PFC_OK && (op->ras_kind < PFC_RAS_LEFT || op->ras_kind > PFC_RAS_RIGHT)) s = bad("unknown ras_kind");
+    if (s == PFC_OK && op->ras_kind != PFC_RAS_LEFT)   // boxes covering a cell, per axis, for the sum
+        for (int a = 0; a < dim; ++a) {
+            const int own = gr->n[a] / op->sub[a], R = (op->overlap + own - 1) / own;
+            if (std::min(2 * R + 1, op->sub[a]) > 16) s = bad("overlap too wide for the AS / right-RAS sum");
+        }
     if (s == PFC_OK && op->sub_solver != PFC_SUB_ILU0 && op->sub_solver != PFC_SUB_LU) s = bad("bad sub_solver");
     if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && dim != 2) {
         c->err = "exact subdomain LU is built for 2-D only";
@@ -723,6 +732,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     c->n_scal = SC_P + std::max({kRedBlocks, 3 * residual_partial_count(c), 2 * energy_partial_count(c)});
     A(dalloc(c, &c->d_scal, (size_t)c->n_scal));
     A(dalloc(c, &c->d_flag, 1));
+    if (op->ras_kind != PFC_RAS_LEFT) A(dalloc(c, &c->d_zbox, (size_t)c->dec.nsub * c->dec.next));
     if (op->sub_solver == PFC_SUB_ILU0) {
         std::vector<int> lptr, lpts;
         std::vector<int8_t> pair;

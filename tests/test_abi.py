@@ -79,7 +79,8 @@ def _create(lib, n=(64, 64, 1), sub=(4, 4, 1), overlap=2, dim=2, **kw):
     (dict(mobility=1), -1),                     # only M = 1 built
     (dict(dt_min=0.0), -1),
     (dict(sub_solver=1, dim=3, n=(32, 32, 32), sub=(4, 4, 4)), -8),   # exact LU is 2-D only
-    (dict(ras_kind=1), -1),
+    (dict(ras_kind=3), -1),                     # no such Schwarz variant
+    (dict(ras_kind=1, sub=(32, 32, 1), overlap=20), -1),   # AS sum over more than 16 boxes per axis
     (dict(guess=3), -1),                        # no such guess
     (dict(guess=2, dim=3, n=(32, 32, 32), sub=(4, 4, 4)), -8),       # learned guess is 2-D only
 ])

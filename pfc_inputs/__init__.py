@@ -9,7 +9,8 @@ Initial conditions follow the paper's experiments (Sec. 5):
                         small / 3-D / batched workloads);
 * ``hex_crystallites_ic``  hexagonal crystallites in a liquid (test B, Eqs. (29)-(30));
 * ``smooth_ic``         the smooth sine product used for the accuracy study (Eq. (28));
-* ``bcc_spheres_ic``    BCC crystallite spheres in 3-D (test D, Eqs. (32)-(34)).
+* ``bcc_spheres_ic``    BCC crystallite spheres in 3-D (test D, Eqs. (32)-(34));
+* ``crack_ic``          the notched, stretched hexagonal lattice of the crack test (test C).
 """
 from __future__ import annotations
 
@@ -26,6 +27,30 @@ def rng(seed):
 def cell_centres(n, L):
     """Cell-centred coordinates (i + 1/2) * L / n, i = 0..n-1 (Sec. 3)."""
     return (np.arange(n) + 0.5) * (L / n)
+
+
+def crack_ic(nx=4096, ny=1024, notch=(40, 20), liquid=0.79):
+    """Stretched hexagonal lattice with a liquid notch (test C, Sec. 5).
+
+    Domain 4096 pi/3 x 1024 pi/3 on an nx x ny mesh scaled with it (the paper's 4096 x 1024
+    gives dx = dy = pi/3); lattice 0.49 + cos(q_y y / sqrt 3) cos(q_x x) - 0.5 cos(2 q_y y / sqrt 3)
+    with q_x = sqrt(3)/2, q_y = 0.9 q_x, on the largest block of whole periods that fits the
+    domain (591 x 76 periods at the full size, scaled with nx, ny); the strips the block leaves
+    and a notch of notch[0] x notch[1] cells at the centre hold the coexisting liquid.
+    Array axes are (y, x)."""
+    Lx = 4096 * math.pi / 3 * nx / 4096
+    Ly = 1024 * math.pi / 3 * ny / 1024
+    qx = math.sqrt(3) / 2
+    qy = 0.9 * qx
+    px, py = 2 * math.pi / qx, 2 * math.pi * math.sqrt(3) / qy          # lattice periods
+    bx, by = math.floor(Lx / px) * px, math.floor(Ly / py) * py          # whole-period block
+    x, y = cell_centres(nx, Lx), cell_centres(ny, Ly)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    phi = 0.49 + np.cos(qy * Y / math.sqrt(3)) * np.cos(qx * X) - 0.5 * np.cos(2 * qy * Y / math.sqrt(3))
+    phi[(X >= bx) | (Y >= by)] = liquid
+    cx, cy = nx // 2, ny // 2
+    phi[cy - notch[1] // 2: cy + notch[1] // 2, cx - notch[0] // 2: cx + notch[0] // 2] = liquid
+    return phi
 
 
 def noise_ic(shape, mean, amp, seed):
@@ -145,6 +170,8 @@ class Workload:
             return bcc_spheres_ic(n=self.shape[-1], L=self.lengths[-1])
         if kind == "smooth":
             return smooth_ic(self.shape[-1], self.lengths[-1])
+        if kind == "crack":
+            return crack_ic(nx=self.shape[-1], ny=self.shape[-2])
         raise ValueError(kind)
 
 
@@ -167,6 +194,13 @@ def crystal_growth(n, sub, overlap=4, nsteps=200, seed=1):
     L = 400.0 * n / 1024.0
     return Workload(f"pfc2d_{n}_crystal", (n, n), (L, L), 0.25, 1e-2, 10.0, 5000.0, nsteps,
                     tuple(sub), overlap, ic=dict(kind="hex", mean=-0.285, seed=seed))
+
+
+def crack_4096x1024():
+    """Test C: 4096 x 1024 mesh on [0, 4096 pi/3] x [0, 1024 pi/3], gamma 1, the notched lattice,
+    adaptive dt 1..5 (eta 100), 16 x 64 boxes (64 x 64 owned), overlap 3 (delta = 1)."""
+    return Workload("pfc2d_crack_4096x1024", (1024, 4096), (1024 * math.pi / 3, 4096 * math.pi / 3), 1.0, 1.0, 5.0,
+                    100.0, 200, (16, 64), 3, ic=dict(kind="crack"))
 
 
 def noise_3d_128():

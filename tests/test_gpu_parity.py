@@ -558,3 +558,28 @@ def test_newton_count_matches_table2_test_d_other_preconditioners(variant, key):
         tab = g["table2_total_newton"]
         col = [tab[f"classical-AS delta {d}"] for d in (0, 1, 2)]
         assert min(col) <= newton <= max(col)
+
+
+def test_trajectory_crack_lattice_non_square():
+    """Test C's field (Sec. 5: notched, stretched hexagonal lattice, gamma = M = 1) scaled down to a
+    64 x 256 mesh at the paper's dx = dy = pi/3: a non-square periodic grid with 2 x 4 exact LU
+    boxes (overlap 3) and FP64 factors.  Three steps of dt = 1, Newton to 1e-10: the oracle
+    trajectory to 1e-10, mass to 1e-12, energy non-increasing."""
+    pfc = _pfc()
+    ny, nx = 64, 256
+    shape, lengths = (ny, nx), (ny * math.pi / 3, nx * math.pi / 3)
+    h = S.spacing(shape, lengths)
+    phi0 = I.crack_ic(nx=nx, ny=ny)
+    ref = S.run(phi0, 3, 1.0, h, 1.0, 1.0)
+    s = pfc.Solver(shape, lengths, 1.0, (2, 4), 3, sub_solver="lu", dt_min=1.0, dt_max=1.0, newton_rtol=0.0,
+                   newton_atol=1e-10)
+    phi = T(phi0)
+    m0 = S.mass(phi0, h)
+    energies = [S.free_energy(phi0, 1.0, h)]
+    for n in range(3):
+        st = s.step(phi)
+        assert rel(N(phi), ref.phis[n + 1]) < 1e-10, n
+        assert abs(st["mass"] - m0) <= 1e-12 * abs(m0)
+        assert st["energy"] <= energies[-1] + 1e-10 * abs(energies[-1])
+        energies.append(st["energy"])
+    s.close()

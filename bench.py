@@ -338,6 +338,17 @@ def batch_bench(steps, workers_list=(1, 16)):
     return out
 
 
+def run_table2():
+    """Table 2's Test A block (256^2, first 10 steps of dt = 0.01, ILU(0), 4 x 4 boxes): Newton and
+    GMRES counts and seconds for classical AS delta 0..2 and left/right-RAS delta 1..2."""
+    from paper_1703_01202_amd.autotune import table2_study
+
+    rows = table2_study()
+    for r in rows:
+        print(f"[bench] table2 {r}", file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +368,7 @@ def main():
     ap.add_argument("--train-trajectories", type=int, default=LEARNED_TRAINING["trajectories"])
     ap.add_argument("--train-epochs", type=int, default=LEARNED_TRAINING["epochs"])
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
+    ap.add_argument("--no-table2", action="store_true", help="skip the Test A preconditioner study (Table 2)")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -398,6 +410,7 @@ def main():
     batch = None if args.no_batch else batch_bench(args.batch_steps)
     hbm_ref = None if args.no_hbm_reference else hbm_reference()
     three_d = None if args.no_3d else run_3d(args.steps_3d)
+    table2 = None if args.no_table2 else run_table2()
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
@@ -436,6 +449,8 @@ def main():
         out["detail"]["pfc3d_128_noise"] = three_d
     if hbm_ref is not None:
         out["detail"]["hbm_reference"] = hbm_ref
+    if table2 is not None:
+        out["detail"]["table2_test_a"] = table2
     print(json.dumps(out), flush=True)
 
 

@@ -1,4 +1,5 @@
-"""Autotuner for the Schwarz decomposition and factor reuse of one workload.
+"""Autotuner for the Schwarz decomposition and factor reuse of one workload, and the paper's
+preconditioner study (Table 2) run on this library.
 
 Candidates are (subdomains per axis, overlap, precond_lag) triples.  Each candidate runs
 ``warmup`` untimed steps, is reset, and then times the first ``steps`` steps of the run
@@ -75,3 +76,48 @@ def autotune(shape, lengths, gamma, phi0, solver_kwargs, candidates, steps=30, w
         raise RuntimeError("no autotune candidate ran")
     best = max(ok, key=lambda r: r["steps_per_s"])
     return best, table
+
+
+def table2_study(shape=(256, 256), lengths=(128.0, 128.0), gamma=0.025, phi0=None, sub=(4, 4), steps=10, dt=0.01,
+                 deltas=(("as", 0), ("as", 1), ("as", 2), ("left", 1), ("left", 2), ("right", 1), ("right", 2)),
+                 sub_solver="ilu0", log=None):
+    """The preconditioner study of the paper's Table 2 on this library: for each (Schwarz variant,
+    delta) the first ``steps`` fixed steps of ``dt`` from ``phi0`` (default: test A's field) with
+    the tolerances of Sec. 5 and subdomain solves ``sub_solver`` (ILU(0), factored once per step).
+    delta counts 3 mesh layers.  Returns rows with the Newton iterations, GMRES iterations per
+    Newton step and seconds, for comparison with the printed table."""
+    import torch
+
+    if phi0 is None:
+        import pfc_inputs as I
+        phi0 = torch.from_numpy(I.noise_ic(shape, 0.07, 0.07, 0)).cuda()
+    rows = []
+    for kind, delta in deltas:
+        row = {"ras_kind": kind, "delta": delta, "overlap": 3 * delta}
+        try:
+            s = Solver(shape, lengths, gamma, sub, 3 * delta, sub_solver=sub_solver, precond_fp32=False,
+                       guess="previous", dt_min=dt, dt_max=dt, newton_rtol=1e-8, newton_atol=1e-10,
+                       lin_rtol=1e-3, lin_atol=1e-11, mass_project=False, ras_kind=kind)
+        except (PfcError, ValueError) as e:
+            row["error"] = str(e)
+            rows.append(row)
+            continue
+        try:
+            phi = phi0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            newton = gmres = 0
+            for _ in range(steps):
+                st = s.step(phi)
+                newton += st["newton_its"]
+                gmres += st["gmres_its"]
+            torch.cuda.synchronize()
+            row.update(newton=newton, gmres_per_newton=gmres / max(newton, 1), seconds=time.perf_counter() - t0)
+        except PfcError as e:
+            row["error"] = str(e)
+        finally:
+            s.close()
+        rows.append(row)
+        if log:
+            log(f"table2 {row}")
+    return rows

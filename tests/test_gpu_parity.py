@@ -583,3 +583,32 @@ def test_trajectory_crack_lattice_non_square():
         assert st["energy"] <= energies[-1] + 1e-10 * abs(energies[-1])
         energies.append(st["energy"])
     s.close()
+
+
+def test_table2_study_reproduces_every_test_a_newton_count():
+    """The whole Test A row block of Table 2 from the study helper: classical AS with delta = 0, 1,
+    2 and left-/right-RAS with delta = 1, 2 (3 layers per delta, ILU(0), 4 x 4 boxes) each take the
+    printed number of Newton iterations over the first 10 steps.  The GMRES iterations per Newton
+    step depend on the box layout (24 processors in the paper, 16 boxes here) and are checked for
+    the table's ordering only: no overlap is worst, and both RAS variants need fewer iterations
+    than classical AS at the same delta."""
+    import json
+    import os
+
+    from paper_1703_01202_amd.autotune import table2_study
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "test_a_newton_counts.json")))
+    st = g["setup"]
+    shape = tuple(st["mesh"])
+    rows = table2_study(shape, tuple(st["domain"]), st["gamma"], T(I.noise_ic(shape, st["phi_mean"], st["phi_noise"], 0)),
+                        steps=st["steps"], dt=st["dt"])
+    names = {"as": "classical-AS", "left": "left-RAS", "right": "right-RAS"}
+    its = {}
+    for r in rows:
+        assert "error" not in r, r
+        key = f"{names[r['ras_kind']]} delta {r['delta']}"
+        assert r["newton"] == g["table2_total_newton"][key], r
+        its[(r["ras_kind"], r["delta"])] = r["gmres_per_newton"]
+    assert its[("as", 0)] == max(its.values())
+    for d in (1, 2):
+        assert max(its[("left", d)], its[("right", d)]) < its[("as", d)]

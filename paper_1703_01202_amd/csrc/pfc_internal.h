@@ -90,6 +90,7 @@ struct pfc_ctx {
 
     // ILU(0) level schedule, shared by all boxes (same shape): points sorted by level
     int nlev = 0;
+    int ilu_cells_per_lane = 1;        // C of the ILU apply: cells of the widest level / 64, rounded up
     int* d_level_ptr = nullptr;        // [nlev + 1]
     int* d_level_pts = nullptr;        // [next], packed coords x | y << 8 | z << 16
     int8_t* d_pair = nullptr;          // [S*S] index of offset(t) - offset(s), or -1
@@ -223,6 +224,9 @@ hipError_t launch_extrap(hipStream_t s, const double* phi, const double* prev, d
 void build_stencil_table(const Geom& g, double gamma, double dt, StencilTable* t);
 hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
+// packed ILU(0) factor elements per cell for a stencil of S offsets
+int ilu_fac_elems_per_cell(int S);
+constexpr int kIluMaxCellsPerLane = 3;   // widest wavefront level an ILU(0) box may have: 64 * this
 hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
 // z = sum over the boxes covering each cell of their extended solutions in zbox (classical AS

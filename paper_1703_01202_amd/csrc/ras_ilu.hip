@@ -106,6 +106,20 @@ __device__ __forceinline__ bool inbox(const Box& b, int x, int y, int z) {
     return x >= 0 && x < b.ex && y >= 0 && y < b.ey && z >= 0 && z < b.ez;
 }
 
+// Packed ILU(0) factors of one box, level-major.  For the n_l cells of a level the D lower
+// factors come as QL groups of four ([group][cell][4]), then the reciprocal pivot and the D
+// upper factors as QU groups of four; unused slots are zero.  A lane reads its cell's factors
+// with 16-byte (FP32) or 32-byte (FP64) loads that are contiguous across the lanes.
+template <int S>
+struct IluPack {
+    static constexpr int D = S / 2;
+    static constexpr int QL = (D + 3) / 4;
+    static constexpr int QU = (D + 4) / 4;
+    static constexpr int kPerCell = 4 * (QL + QU);
+    template <typename T>
+    using Vec = T __attribute__((ext_vector_type(4)));
+};
+
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ cc,
                                                     const int* __restrict__ lptr,
@@ -166,36 +180,83 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ c
         }
         __syncthreads();
     }
-    // pack level-major: factor s of the p-th cell of level l at lptr[l]*S + s*n_l + p
-    T* out = fac + (long)k * b.next * S;
+    // pack level-major in groups of four factors (see IluPack): lower factors first, then the
+    // reciprocal pivot followed by the upper factors; the padding slots hold zero
+    using P = IluPack<S>;
+    T* out = fac + (long)k * b.next * P::kPerCell;
     for (int lev = 0; lev < nlev; ++lev) {
         const int p0 = lptr[lev], nl = lptr[lev + 1] - p0;
+        const long lb = (long)p0 * P::kPerCell, ub = lb + (long)P::QL * 4 * nl;
         for (int p = threadIdx.x; p < nl; p += blockDim.x) {
             const int pk = lpts[p0 + p];
             const int x = pk & 255, y = (pk >> 8) & 255, z = pk >> 16;
-            const long i = ((long)z * b.ey + y) * b.ex + x;
-            for (int s = 0; s < S; ++s) {
-                const double v = W[i * S + s];
-                out[(long)p0 * S + (long)s * nl + p] = (T)(s == D ? 1.0 / v : v);
-            }
+            const double* row = W + (((long)z * b.ey + y) * b.ex + x) * S;
+            for (int q = 0; q < P::QL; ++q)
+                for (int e = 0; e < 4; ++e) {
+                    const int t = 4 * q + e;
+                    out[lb + ((long)q * nl + p) * 4 + e] = (T)(t < D ? row[t] : 0.0);
+                }
+            for (int q = 0; q < P::QU; ++q)
+                for (int e = 0; e < 4; ++e) {
+                    const int u = 4 * q + e;
+                    out[ub + ((long)q * nl + p) * 4 + e] = (T)(u == 0 ? 1.0 / row[D] : (u <= D ? row[D + u] : 0.0));
+                }
         }
     }
 }
 
 // One wave per box: forward then backward substitution over the wavefront levels with the
-// box vector in LDS.  The stencil size is a template parameter so each row's factor loads
-// are unrolled, and the next level's row index and factors are fetched into registers
-// while the current level is computed (a level has at most 64 rows on the first pass;
-// larger levels take the remaining rows with direct loads).
-template <typename T, int S>
+// box vector in LDS.  Each lane takes C cells of a level (the host picks C from the widest
+// level).  The factors of the next PF levels are in flight in registers while a level is
+// computed: the loads are unconditional (clamped to the last cell and level), so the number of
+// loads issued after any level's factors is fixed and the wait before a level covers that
+// level only.  Neighbour indices are the cell index plus a per-box constant offset, clamped
+// into the box: a neighbour outside the box has a zero factor (the pattern of A_k stops at
+// the box), so whatever the clamped read returns adds nothing.
+// The apply runs one wave per box, and a wave's LDS operations take effect in program order,
+// so a level only has to keep the compiler from moving LDS accesses across the level boundary.
+// A workgroup barrier would also wait for every global load in flight, including the factors
+// fetched ahead for the next levels.  The scheduling barrier keeps each level's work (and the
+// fetch that follows it) in its place, so that the wait before a level is for that level's loads.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename T, int S, int C>
+struct IluApplyShape {
+    using P = IluPack<S>;
+    static constexpr int kLoadsPerLevel = C * (1 + P::QL * (int)(sizeof(T) / 4));   // vector memory ops
+    static constexpr int PF = 60 / kLoadsPerLevel < 1 ? 1 : (60 / kLoadsPerLevel > 4 ? 4 : 60 / kLoadsPerLevel);
+};
+
+template <typename V, int PF, int C, int Q>
+__device__ __forceinline__ void zero_slots(V (&f)[PF][C][Q], int (&pk)[PF][C], int (&nl)[PF]) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        nl[j] = 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            pk[j][c] = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) f[j][c][q] = V{};
+        }
+    }
+}
+
+template <typename T, int S, int C>
 __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, double* __restrict__ z,
                                                   const T* __restrict__ fac, const int* __restrict__ lptr,
                                                   const int* __restrict__ lpts, Box b, StencilTable st,
                                                   int nlev, double* __restrict__ sum_part, int mode,
                                                   double* __restrict__ zbox) {
+    using P = IluPack<S>;
+    using V = typename P::template Vec<T>;
+    constexpr int D = S / 2;                  // centre of the natural-order stencil
+    constexpr int QL = P::QL, QU = P::QU, PF = IluApplyShape<T, S, C>::PF;
     extern __shared__ unsigned char smem_raw[];
     T* yv = reinterpret_cast<T*>(smem_raw);
-    constexpr int D = S / 2;                  // centre of the natural-order stencil
     const int tid = threadIdx.x;
     const int k = blockIdx.x;
     int ox, oy, oz;
@@ -208,95 +269,90 @@ __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, 
                          zz < zoff + owz;
         yv[i] = (mode != 2 || own) ? (T)r[gidx(b, ox, oy, oz, x, y, zz)] : (T)0;
     }
-    __syncthreads();
-    const T* F = fac + (long)k * b.next * S;
-    // row update: acc = yv[i] - sum_s f[s] yv[i + off(s)] over s in [s0, s0 + D)
-    auto update = [&](int pk, const T* f, int s0, bool scale_diag, T dinv) {
-        const int x = pk & 255, y = (pk >> 8) & 255, zc = pk >> 16;
-        const int i = (zc * b.ey + y) * b.ex + x;
-        T acc = yv[i];
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            const int s = s0 + q;
-            const int xx = x + st.dx[s], yy = y + st.dy[s], zz = zc + st.dz[s];
-            const int j = inbox(b, xx, yy, zz) ? (zz * b.ey + yy) * b.ex + xx : i;
-            acc -= f[q] * yv[j];
-        }
-        yv[i] = scale_diag ? acc * dinv : acc;
-    };
-    // forward sweep (lower factors s < D)
+    if (tid == 0) yv[b.next] = (T)0;   // spare slot for lanes without a cell
+    const T* F = fac + (long)k * b.next * P::kPerCell;
+    const int last = b.next - 1;
+    auto cell = [&](int pk) { return ((pk >> 16) * b.ey + ((pk >> 8) & 255)) * b.ex + (pk & 255); };
+    auto noff = [&](int s) { return ((int)st.dz[s] * b.ey + st.dy[s]) * b.ex + st.dx[s]; };
+    wave_lds_order();
+    // forward sweep (unit lower factor)
     {
-        int p0 = lptr[0], nl = lptr[1] - p0, pk = 0;
-        T f[D];
-        if (tid < nl) {
-            pk = lpts[p0 + tid];
+        V f[PF][C][QL];
+        int pk[PF][C], nl[PF];
+        auto fetch = [&](int lev, V (&dst)[C][QL], int (&pkd)[C], int& nld) {
+            const int l = min(max(lev, 0), nlev - 1);
+            const int p0 = lptr[l];
+            nld = lptr[l + 1] - p0;
+            const V* base = reinterpret_cast<const V*>(F + (long)p0 * P::kPerCell);
 #pragma unroll
-            for (int q = 0; q < D; ++q) f[q] = F[(long)p0 * S + (long)q * nl + tid];
-        }
-        for (int lev = 0; lev < nlev; ++lev) {
-            int p0n = 0, nln = 0, pkn = 0;
-            T fn[D];
-            if (lev + 1 < nlev) {
-                p0n = lptr[lev + 1];
-                nln = lptr[lev + 2] - p0n;
-                if (tid < nln) {
-                    pkn = lpts[p0n + tid];
+            for (int c = 0; c < C; ++c) {
+                const int p = min(tid + 64 * c, nld - 1);
+                pkd[c] = lpts[p0 + p];
 #pragma unroll
-                    for (int q = 0; q < D; ++q) fn[q] = F[(long)p0n * S + (long)q * nln + tid];
+                for (int q = 0; q < QL; ++q) dst[c][q] = base[(long)q * nld + p];
+            }
+        };
+        zero_slots(f, pk, nl);
+        // the first pass computes nothing (levels -PF..-1) and only fetches; entering the loop
+        // with no loads in flight lets the wait before each level count just that level's loads
+        for (int l0 = -PF; l0 < nlev; l0 += PF) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    // a lane with no cell (or a level outside 0..nlev-1) works on the spare slot
+                    const bool ok = l0 + j >= 0 && l0 + j < nlev && tid + 64 * c < nl[j];
+                    const int i = ok ? cell(pk[j][c]) : b.next;
+                    T acc = yv[i];
+#pragma unroll
+                    for (int q = 0; q < D; ++q) acc -= f[j][c][q / 4][q % 4] * yv[min(max(i + noff(q), 0), last)];
+                    // adding the zero padding keeps every loaded register live until here, so
+                    // none is reused (and waited for) while its load is still in flight
+#pragma unroll
+                    for (int t = D; t < 4 * QL; ++t) acc += f[j][c][t / 4][t % 4];
+                    yv[i] = acc;
                 }
+                wave_lds_order();
+                fetch(l0 + j + PF, f[j], pk[j], nl[j]);
             }
-            if (tid < nl) update(pk, f, 0, false, T(0));
-            for (int p = tid + 64; p < nl; p += 64) {
-                T g[D];
-#pragma unroll
-                for (int q = 0; q < D; ++q) g[q] = F[(long)p0 * S + (long)q * nl + p];
-                update(lpts[p0 + p], g, 0, false, T(0));
-            }
-            __syncthreads();
-            p0 = p0n;
-            nl = nln;
-            pk = pkn;
-#pragma unroll
-            for (int q = 0; q < D; ++q) f[q] = fn[q];
         }
     }
-    // backward sweep (upper factors s > D, then the stored reciprocal diagonal)
+    // backward sweep (upper factors, then the stored reciprocal pivot)
     {
-        int p0 = lptr[nlev - 1], nl = lptr[nlev] - p0, pk = 0;
-        T f[D], dinv = T(0);
-        if (tid < nl) {
-            pk = lpts[p0 + tid];
+        V f[PF][C][QU];
+        int pk[PF][C], nl[PF];
+        auto fetch = [&](int lev, V (&dst)[C][QU], int (&pkd)[C], int& nld) {
+            const int l = min(max(lev, 0), nlev - 1);
+            const int p0 = lptr[l];
+            nld = lptr[l + 1] - p0;
+            const V* base = reinterpret_cast<const V*>(F + (long)p0 * P::kPerCell) + (long)QL * nld;
 #pragma unroll
-            for (int q = 0; q < D; ++q) f[q] = F[(long)p0 * S + (long)(D + 1 + q) * nl + tid];
-            dinv = F[(long)p0 * S + (long)D * nl + tid];
-        }
-        for (int lev = nlev - 1; lev >= 0; --lev) {
-            int p0n = 0, nln = 0, pkn = 0;
-            T fn[D], dn = T(0);
-            if (lev > 0) {
-                p0n = lptr[lev - 1];
-                nln = lptr[lev] - p0n;
-                if (tid < nln) {
-                    pkn = lpts[p0n + tid];
+            for (int c = 0; c < C; ++c) {
+                const int p = min(tid + 64 * c, nld - 1);
+                pkd[c] = lpts[p0 + p];
 #pragma unroll
-                    for (int q = 0; q < D; ++q) fn[q] = F[(long)p0n * S + (long)(D + 1 + q) * nln + tid];
-                    dn = F[(long)p0n * S + (long)D * nln + tid];
+                for (int q = 0; q < QU; ++q) dst[c][q] = base[(long)q * nld + p];
+            }
+        };
+        zero_slots(f, pk, nl);
+        for (int l0 = nlev - 1 + PF; l0 >= 0; l0 -= PF) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const bool ok = l0 - j >= 0 && l0 - j < nlev && tid + 64 * c < nl[j];
+                    const int i = ok ? cell(pk[j][c]) : b.next;
+                    T acc = yv[i];
+#pragma unroll
+                    for (int q = 1; q <= D; ++q)
+                        acc -= f[j][c][q / 4][q % 4] * yv[min(max(i + noff(D + q), 0), last)];
+#pragma unroll
+                    for (int t = D + 1; t < 4 * QU; ++t) acc += f[j][c][t / 4][t % 4];
+                    yv[i] = acc * f[j][c][0][0];
                 }
+                wave_lds_order();
+                fetch(l0 - j - PF, f[j], pk[j], nl[j]);
             }
-            if (tid < nl) update(pk, f, D + 1, true, dinv);
-            for (int p = tid + 64; p < nl; p += 64) {
-                T g[D];
-#pragma unroll
-                for (int q = 0; q < D; ++q) g[q] = F[(long)p0 * S + (long)(D + 1 + q) * nl + p];
-                update(lpts[p0 + p], g, D + 1, true, F[(long)p0 * S + (long)D * nl + p]);
-            }
-            __syncthreads();
-            p0 = p0n;
-            nl = nln;
-            pk = pkn;
-            dinv = dn;
-#pragma unroll
-            for (int q = 0; q < D; ++q) f[q] = fn[q];
         }
     }
     double acc = 0.0;
@@ -393,6 +449,7 @@ void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<in
     lptr->assign(1, 0);
     lpts->clear();
     for (auto& v : by) {
+        if (v.empty()) continue;   // a level value no cell of a thin box takes
         for (int p : v) lpts->push_back(p);
         lptr->push_back((int)lpts->size());
     }
@@ -428,20 +485,6 @@ hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& st) {
     return hipErrorInvalidValue;
 }
 
-template <int S>
-hipError_t launch_ilu_apply_s(pfc_ctx* c, const double* r, double* z, double* sum_part, const Box& b) {
-    const StencilTable& st = c->st;
-    if (c->opts.precond_fp32) {
-        const size_t sh = sizeof(float) * b.next;
-        return launch_k(c, k_ilu_apply<float, S>, dim3(c->dec.nsub), dim3(64), sh, r, z, (const float*)c->d_fac,
-                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part, c->opts.ras_kind, c->d_zbox);
-    } else {
-        const size_t sh = sizeof(double) * b.next;
-        return launch_k(c, k_ilu_apply<double, S>, dim3(c->dec.nsub), dim3(64), sh, r, z, (const double*)c->d_fac,
-                        c->d_level_ptr, c->d_level_pts, b, st, c->nlev, sum_part, c->opts.ras_kind, c->d_zbox);
-    }
-}
-
 hipError_t launch_schwarz_sum(const pfc_ctx* c, const double* zbox, double* z) {
     SumGeom g;
     const int gn[3] = {c->g.nx, c->g.ny, c->g.nz};
@@ -461,6 +504,29 @@ hipError_t launch_schwarz_sum(const pfc_ctx* c, const double* zbox, double* z) {
     return hipGetLastError();
 }
 
+template <typename T, int S, int C>
+hipError_t launch_ilu_apply_c(pfc_ctx* c, const double* r, double* z, double* sum_part, const Box& b) {
+    return launch_k(c, k_ilu_apply<T, S, C>, dim3(c->dec.nsub), dim3(64), sizeof(T) * (b.next + 1), r, z,
+                    (const T*)c->d_fac, c->d_level_ptr, c->d_level_pts, b, c->st, c->nlev, sum_part,
+                    c->opts.ras_kind, c->d_zbox);
+}
+
+template <typename T, int S>
+hipError_t launch_ilu_apply_t(pfc_ctx* c, const double* r, double* z, double* sum_part, const Box& b) {
+    switch (c->ilu_cells_per_lane) {
+        case 1: return launch_ilu_apply_c<T, S, 1>(c, r, z, sum_part, b);
+        case 2: return launch_ilu_apply_c<T, S, 2>(c, r, z, sum_part, b);
+        case 3: return launch_ilu_apply_c<T, S, 3>(c, r, z, sum_part, b);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+hipError_t launch_ilu_apply_s(pfc_ctx* c, const double* r, double* z, double* sum_part, const Box& b) {
+    return c->opts.precond_fp32 ? launch_ilu_apply_t<float, S>(c, r, z, sum_part, b)
+                                : launch_ilu_apply_t<double, S>(c, r, z, sum_part, b);
+}
+
 hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {
     const Box b = make_box(c);
     if (c->st.diag != c->st.S / 2) return hipErrorInvalidValue;
@@ -469,9 +535,20 @@ hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_
     return hipErrorInvalidValue;
 }
 
+int ilu_fac_elems_per_cell(int S) {
+    if (S == 25) return IluPack<25>::kPerCell;
+    if (S == 63) return IluPack<63>::kPerCell;
+    return 0;
+}
+
 hipError_t set_ilu_lds_limits() {
-    const void* fs[] = {(const void*)k_ilu_apply<double, 25>, (const void*)k_ilu_apply<float, 25>,
-                        (const void*)k_ilu_apply<double, 63>, (const void*)k_ilu_apply<float, 63>};
+    const void* fs[] = {
+        (const void*)k_ilu_apply<double, 25, 1>, (const void*)k_ilu_apply<float, 25, 1>,
+        (const void*)k_ilu_apply<double, 63, 1>, (const void*)k_ilu_apply<float, 63, 1>,
+        (const void*)k_ilu_apply<double, 25, 2>, (const void*)k_ilu_apply<float, 25, 2>,
+        (const void*)k_ilu_apply<double, 63, 2>, (const void*)k_ilu_apply<float, 63, 2>,
+        (const void*)k_ilu_apply<double, 25, 3>, (const void*)k_ilu_apply<float, 25, 3>,
+        (const void*)k_ilu_apply<double, 63, 3>, (const void*)k_ilu_apply<float, 63, 3>};
     for (const void* f : fs) {
         const hipError_t e = set_dynamic_lds_limit(f);
         if (e != hipSuccess) return e;

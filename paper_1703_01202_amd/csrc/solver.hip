@@ -701,7 +701,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (op->sub_solver == PFC_SUB_LU && d.ext[0] > 72) s = bad("exact LU needs a box x-extent of at most 72");
     if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && lu_factor_lds_bytes(d.ext[0]) > 159 * 1024)
         s = bad("exact LU block too large for LDS");
-    const size_t ilu_lds = (op->precond_fp32 ? 4 : 8) * (size_t)d.next;
+    const size_t ilu_lds = (op->precond_fp32 ? 4 : 8) * ((size_t)d.next + 1);
     if (s == PFC_OK && op->sub_solver == PFC_SUB_ILU0 && ilu_lds > 160 * 1024) s = bad("subdomain too large for LDS");
     if (s != PFC_OK) {
         std::string msg = c->err;
@@ -738,11 +738,16 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
         std::vector<int8_t> pair;
         build_ilu_schedule(c, c->st, &lptr, &lpts, &pair);
         c->nlev = (int)lptr.size() - 1;
+        int widest = 0;
+        for (int l = 0; l < c->nlev; ++l) widest = std::max(widest, lptr[l + 1] - lptr[l]);
+        c->ilu_cells_per_lane = (widest + 63) / 64;
+        if (c->ilu_cells_per_lane > kIluMaxCellsPerLane && s == PFC_OK)
+            s = fail(c, PFC_EINVAL, "ILU(0) box has a wavefront level wider than 192 cells");
         A(dalloc(c, &c->d_level_ptr, lptr.size()));
         A(dalloc(c, &c->d_level_pts, lpts.size()));
         A(dalloc(c, &c->d_pair, pair.size()));
-        c->fac_elems = (size_t)d.nsub * d.next * c->st.S;
-        A(dalloc(c, &c->d_work, c->fac_elems));
+        c->fac_elems = (size_t)d.nsub * d.next * ilu_fac_elems_per_cell(c->st.S);
+        A(dalloc(c, &c->d_work, (size_t)d.nsub * d.next * c->st.S));
         if (s == PFC_OK) {
             hipMemcpy(c->d_level_ptr, lptr.data(), sizeof(int) * lptr.size(), hipMemcpyHostToDevice);
             hipMemcpy(c->d_level_pts, lpts.data(), sizeof(int) * lpts.size(), hipMemcpyHostToDevice);

@@ -338,6 +338,32 @@ def batch_bench(steps, workers_list=(1, 16)):
     return out
 
 
+def run_3d_256(steps):
+    """Test D's full grid: 256^3 on [0, 80 pi]^3, three BCC spheres, gamma 0.35, dt 0.1 (see the
+    workload's note on ILU(0) above that), FP32 ILU(0) on 16^3 boxes with overlap 3."""
+    import torch
+    import paper_1703_01202_amd as pfc
+    import pfc_inputs as I
+    w = I.bcc_growth_3d_256()
+    phi = torch.from_numpy(w.initial()).cuda()
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, precond_fp32=True, guess="extrap",
+                   dt_min=w.dt_min, dt_max=w.dt_max, eta=w.eta, precond_lag=10, timing=True)
+    s.step(phi)   # untimed: first factorisation and warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [s.step(phi) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {k: s.kernel_time(k) for k in range(4)}
+    s.close()
+    N = w.shape[0] * w.shape[1] * w.shape[2]
+    out = {"workload": "pfc3d_bcc_256", "steps": steps, "seconds": el, "steps_per_s": steps / el,
+           "dof_steps_per_s": N * steps / el, "newton_its": sum(st["newton_its"] for st in stats),
+           "gmres_its": sum(st["gmres_its"] for st in stats), "dt": w.dt_min, "kernels": kt}
+    print(f"[bench] 3-D 256^3: {steps / el:.2f} steps/s", file=sys.stderr, flush=True)
+    return out
+
+
 def run_table2():
     """Table 2's Test A block (256^2, first 10 steps of dt = 0.01, ILU(0), 4 x 4 boxes): Newton and
     GMRES counts and seconds for classical AS delta 0..2 and left/right-RAS delta 1..2."""
@@ -369,6 +395,7 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=LEARNED_TRAINING["epochs"])
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     ap.add_argument("--no-table2", action="store_true", help="skip the Test A preconditioner study (Table 2)")
+    ap.add_argument("--steps-3d-256", type=int, default=6, help="steps of the 256^3 test-D grid (0 skips it)")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -411,6 +438,7 @@ def main():
     hbm_ref = None if args.no_hbm_reference else hbm_reference()
     three_d = None if args.no_3d else run_3d(args.steps_3d)
     table2 = None if args.no_table2 else run_table2()
+    three_d_256 = run_3d_256(args.steps_3d_256) if args.steps_3d_256 > 0 else None
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
@@ -451,6 +479,8 @@ def main():
         out["detail"]["hbm_reference"] = hbm_ref
     if table2 is not None:
         out["detail"]["table2_test_a"] = table2
+    if three_d_256 is not None:
+        out["detail"]["pfc3d_bcc_256"] = three_d_256
     print(json.dumps(out), flush=True)
 
 

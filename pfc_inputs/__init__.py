@@ -210,6 +210,16 @@ def noise_3d_128():
                     (8, 8, 8), 2, ic=dict(kind="noise", mean=-0.2, amp=0.1, seed=2))
 
 
+def bcc_growth_3d_256(dt_min=0.1, dt_max=0.1):
+    """Test D's grid: 256^3 on [0, 80 pi]^3, gamma 0.35, three BCC crystallite spheres (mean -0.35,
+    radius 5 pi), 16^3 subdomains (16^3 owned cells), overlap 3 (delta = 1), eta 500.  The paper
+    runs dt 0.5..10 here; the default is the dt = 0.1 of its test-D tuning runs, the range where
+    natural-order ILU(0) on this mesh size stays stable (it breaks down from dt ~ 0.3 on)."""
+    L = 80 * math.pi
+    return Workload("pfc3d_bcc_256", (256, 256, 256), (L, L, L), 0.35, dt_min, dt_max, 500.0, 50,
+                    (16, 16, 16), 3, ic=dict(kind="bcc"))
+
+
 def batch_instances(count=64, seed=3):
     """Ragged batch: side ~ U{128,192,256,384,512}, gamma ~ U[0.1,0.4], mean ~ U[-0.35,-0.2]."""
     g = rng(seed)

@@ -612,3 +612,35 @@ def test_table2_study_reproduces_every_test_a_newton_count():
     assert its[("as", 0)] == max(its.values())
     for d in (1, 2):
         assert max(its[("left", d)], its[("right", d)]) < its[("as", d)]
+
+
+def test_test_d_full_grid_256():
+    """Test D's full grid, 256^3 on [0, 80 pi]^3 (16.8 M cells, 4096 boxes of 22^3, FP32 ILU(0)):
+    residual and Jacobian action against the oracle at full size; then two time steps, each
+    accepted state checked with the oracle's residual against Newton's stop test, energy not
+    increasing and the mass kept."""
+    pfc = _pfc()
+    w = I.bcc_growth_3d_256()
+    h = S.spacing(w.shape, w.lengths)
+    phi0 = w.initial()
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, precond_fp32=True, guess="extrap",
+                   dt_min=w.dt_min, dt_max=w.dt_max, eta=w.eta, precond_lag=10)
+    Phi = phi0 + 0.01 * np.random.default_rng(8).standard_normal(w.shape)
+    F, _ = s.residual(T(Phi), T(phi0), 0.1)
+    assert rel(N(F), S.residual(Phi, phi0, 0.1, w.gamma, h)) < 1e-12
+    del F
+    v = np.random.default_rng(9).standard_normal(w.shape)
+    assert rel(N(s.jv(T(Phi), T(phi0), 0.1, T(v))), S.jv(Phi, phi0, 0.1, w.gamma, h, v)) < 1e-12
+    del Phi, v
+    phi = T(phi0)
+    prev = phi0
+    e_prev, m0 = S.free_energy(phi0, w.gamma, h), S.mass(phi0, h)
+    for _ in range(2):
+        st = s.step(phi)
+        cur = N(phi)
+        res = np.linalg.norm(S.residual(cur, prev, st["dt"], w.gamma, h))
+        assert res <= 1.01 * max(1e-8 * st["res_ref"], 1e-10) + 1e-9, (res, st)
+        assert st["energy"] <= e_prev + 1e-12 * abs(e_prev)
+        assert abs(st["mass"] - m0) <= 1e-12 * abs(m0)
+        e_prev, prev = st["energy"], cur
+    s.close()

@@ -215,3 +215,31 @@ def test_nks_step_stops_where_eq20_says():
     assert loose.newton <= tight.newton
     F = S.residual(tight.Phi, phi, 0.1, 0.25, h)
     assert np.linalg.norm(F) == pytest.approx(tight.res_norms[-1], rel=1e-12)
+
+
+@pytest.mark.parametrize("dt,stable", [(0.1, True), (0.5, False)])
+def test_natural_order_ilu0_on_test_d_mesh_size(dt, stable):
+    """Why test D's 256^3 grid runs at dt = 0.1: on its mesh size (h = 80 pi / 256) the
+    natural-order ILU(0) of a 3-D subdomain matrix (Eqs. (25)-(26), liquid phi = -0.35,
+    gamma = 0.35, box of 4^3 cells extended by 3 layers) keeps every pivot positive at the
+    dt = 0.1 of the paper's test-D tuning runs, and loses that at its production dt_min = 0.5:
+    negative pivots, and a preconditioned operator whose spectrum leaves any bounded region."""
+    import math
+
+    n_own, ov = 4, 3
+    hv = 80 * math.pi / 256
+    shape = (4 * n_own,) * 3
+    h = S.spacing(shape, (hv * shape[0],) * 3)
+    phi = np.full(shape, -0.35)
+    dom = W.decompose(shape, (4, 4, 4), ov)[0]
+    A = W.subdomain_matrix_zero_ring(phi, phi, dt, 0.35, h, dom)
+    rows = W.ilu0(A, W.subdomain_pattern(dom.ext_n))
+    piv = np.array([r[i] for i, r in enumerate(rows)])
+    L, U = W.ilu0_dense_factors(rows)
+    ev = np.linalg.eigvals(np.linalg.solve(U, np.linalg.solve(L, A)))
+    if stable:
+        assert piv.min() > 0
+        assert 0 < ev.real.min() and abs(ev).max() < 10
+    else:
+        assert piv.min() < 0
+        assert abs(ev).max() > 1e6

@@ -93,7 +93,6 @@ struct pfc_ctx {
     int ilu_cells_per_lane = 1;        // C of the ILU apply: cells of the widest level / 64, rounded up
     int* d_level_ptr = nullptr;        // [nlev + 1]
     int* d_level_pts = nullptr;        // [next], packed coords x | y << 8 | z << 16
-    int8_t* d_pair = nullptr;          // [S*S] index of offset(t) - offset(s), or -1
 
     // factors
     double* d_work = nullptr;          // ILU natural-layout workspace / LU window (FP64)

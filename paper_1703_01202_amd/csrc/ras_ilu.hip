@@ -13,7 +13,7 @@
 // keeps the box vector in LDS and streams the factors, packed level by level with the
 // stencil index outermost so that the lanes of a level read consecutive addresses.
 #include <algorithm>
-#include <map>
+#include <vector>
 
 #include "device_reduce.h"
 #include "pfc_internal.h"
@@ -120,25 +120,57 @@ struct IluPack {
     using Vec = T __attribute__((ext_vector_type(4)));
 };
 
+// The composite stencil's offsets in natural order (z, then y, then x; |dx| + |dy| + |dz| <= 3,
+// the order build_stencil_table uses), and for each pair (s, t) the index of offset(t) -
+// offset(s), or -1.  Known at compile time, so the elimination reads each pivot row at fixed
+// offsets and skips the pairs outside the pattern without a test.
+template <int S>
+struct IluPairs {
+    int8_t dx[S], dy[S], dz[S];
+    int8_t u[S][S];
+    constexpr IluPairs() : dx(), dy(), dz(), u() {
+        int idx[7][7][7] = {};
+        for (int z = 0; z < 7; ++z)
+            for (int y = 0; y < 7; ++y)
+                for (int x = 0; x < 7; ++x) idx[z][y][x] = -1;
+        const int zr = S == 63 ? 3 : 0;
+        int n = 0;
+        for (int z = -zr; z <= zr; ++z)
+            for (int y = -3; y <= 3; ++y)
+                for (int x = -3; x <= 3; ++x) {
+                    if ((x < 0 ? -x : x) + (y < 0 ? -y : y) + (z < 0 ? -z : z) > 3) continue;
+                    dx[n] = (int8_t)x;
+                    dy[n] = (int8_t)y;
+                    dz[n] = (int8_t)z;
+                    idx[z + 3][y + 3][x + 3] = n++;
+                }
+        for (int s = 0; s < S; ++s)
+            for (int t = 0; t < S; ++t) {
+                const int x = dx[t] - dx[s] + 3, y = dy[t] - dy[s] + 3, z = dz[t] - dz[s] + 3;
+                const bool inside = x >= 0 && x < 7 && y >= 0 && y < 7 && z >= 0 && z < 7;
+                u[s][t] = (int8_t)(inside ? idx[z][y][x] : -1);
+            }
+    }
+};
+template <int S>
+inline constexpr IluPairs<S> kIluPairs{};
+
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ cc,
                                                     const int* __restrict__ lptr,
-                                                    const int* __restrict__ lpts,
-                                                    const int8_t* __restrict__ pair, double* __restrict__ work,
+                                                    const int* __restrict__ lpts, double* __restrict__ work,
                                                     T* __restrict__ fac, int* __restrict__ flag, Box b,
                                                     StencilTable st, int nlev) {
-    __shared__ int8_t spair[S * S];
     constexpr int D = S / 2;                  // the zero offset sits in the middle (natural order)
     const int k = blockIdx.x;
     int ox, oy, oz;
     box_origin(b, k, &ox, &oy, &oz);
     double* W = work + (long)k * b.next * S;
-    for (int e = threadIdx.x; e < S * S; e += blockDim.x) spair[e] = pair[e];
     // assemble A_k row by row
     for (int i = threadIdx.x; i < b.next; i += blockDim.x) {
         const int x = i % b.ex, y = (i / b.ex) % b.ey, z = i / (b.ex * b.ey);
         for (int s = 0; s < S; ++s) {
-            const int xx = x + st.dx[s], yy = y + st.dy[s], zz = z + st.dz[s];
+            const int xx = x + kIluPairs<S>.dx[s], yy = y + kIluPairs<S>.dy[s], zz = z + kIluPairs<S>.dz[s];
             double v = 0.0;
             if (inbox(b, xx, yy, zz)) v = st.kconst[s] - st.d1[s] * cc[gidx(b, ox, oy, oz, xx, yy, zz)];
             W[(long)i * S + s] = v;
@@ -158,18 +190,18 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ c
 #pragma unroll
             for (int t = 0; t < S; ++t) {
                 r[t] = row[t];
-                in[t] = inbox(b, x + st.dx[t], y + st.dy[t], z + st.dz[t]);
+                in[t] = inbox(b, x + kIluPairs<S>.dx[t], y + kIluPairs<S>.dy[t], z + kIluPairs<S>.dz[t]);
             }
 #pragma unroll
             for (int s = 0; s < D; ++s) {
                 if (!in[s]) continue;
-                const long kk = i + ((long)st.dz[s] * b.ey + st.dy[s]) * b.ex + st.dx[s];
+                const long kk = i + ((long)kIluPairs<S>.dz[s] * b.ey + kIluPairs<S>.dy[s]) * b.ex + kIluPairs<S>.dx[s];
                 const double* rk = W + kk * S;
                 const double aik = r[s] / rk[D];
                 r[s] = aik;
 #pragma unroll
                 for (int t = s + 1; t < S; ++t) {
-                    const int u = spair[s * S + t];
+                    const int u = kIluPairs<S>.u[s][t];   // resolved at compile time
                     if (u >= 0 && in[t]) r[t] -= aik * rk[u];
                 }
             }
@@ -437,9 +469,8 @@ Box make_box(const pfc_ctx* c) {
 
 }  // namespace
 
-// Host-side level schedule and offset-pair table for the box shape of the context.
-void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<int>* lptr,
-                        std::vector<int>* lpts, std::vector<int8_t>* pair) {
+// Host-side level schedule for the box shape of the context.
+void build_ilu_schedule(const pfc_ctx* c, std::vector<int>* lptr, std::vector<int>* lpts) {
     const int ex = c->dec.ext[0], ey = c->dec.ext[1], ez = c->g.dim == 3 ? c->dec.ext[2] : 1;
     const int maxlev = (ex - 1) + 3 * (ey - 1) + 7 * (ez - 1) + 1;
     std::vector<std::vector<int>> by(maxlev);
@@ -453,27 +484,19 @@ void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<in
         for (int p : v) lpts->push_back(p);
         lptr->push_back((int)lpts->size());
     }
-    const int S = st.S;
-    pair->assign(S * S, -1);
-    std::map<std::tuple<int, int, int>, int> idx;
-    for (int s = 0; s < S; ++s) idx[{st.dx[s], st.dy[s], st.dz[s]}] = s;
-    for (int s = 0; s < S; ++s)
-        for (int t = 0; t < S; ++t) {
-            auto it = idx.find({st.dx[t] - st.dx[s], st.dy[t] - st.dy[s], st.dz[t] - st.dz[s]});
-            if (it != idx.end()) (*pair)[s * S + t] = (int8_t)it->second;
-        }
 }
 
 template <int S>
 hipError_t launch_ilu_factor_s(pfc_ctx* c, const StencilTable& st, const Box& b) {
+    for (int s = 0; s < S; ++s)   // the kernel's pair table assumes this offset order
+        if (st.dx[s] != kIluPairs<S>.dx[s] || st.dy[s] != kIluPairs<S>.dy[s] || st.dz[s] != kIluPairs<S>.dz[s])
+            return hipErrorInvalidValue;
     if (c->opts.precond_fp32)
         hipLaunchKernelGGL((k_ilu_factor<float, S>), dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c,
-                           c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, (float*)c->d_fac, c->d_flag, b, st,
-                           c->nlev);
+                           c->d_level_ptr, c->d_level_pts, c->d_work, (float*)c->d_fac, c->d_flag, b, st, c->nlev);
     else
         hipLaunchKernelGGL((k_ilu_factor<double, S>), dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c,
-                           c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, (double*)c->d_fac, c->d_flag, b,
-                           st, c->nlev);
+                           c->d_level_ptr, c->d_level_pts, c->d_work, (double*)c->d_fac, c->d_flag, b, st, c->nlev);
     return hipGetLastError();
 }
 

@@ -15,8 +15,7 @@
 namespace pfc {
 int residual_partial_count(const pfc_ctx* c);
 int energy_partial_count(const pfc_ctx* c);
-void build_ilu_schedule(const pfc_ctx* c, const StencilTable& st, std::vector<int>* lptr,
-                        std::vector<int>* lpts, std::vector<int8_t>* pair);
+void build_ilu_schedule(const pfc_ctx* c, std::vector<int>* lptr, std::vector<int>* lpts);
 hipError_t set_ilu_lds_limits();
 hipError_t set_lu_lds_limits();
 size_t lu_factor_lds_bytes(int W);
@@ -539,7 +538,7 @@ pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
 }
 
 void free_all(pfc_ctx* c) {
-    void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_pair, c->d_work, c->d_fac, c->d_flag, c->d_c,
+    void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_work, c->d_fac, c->d_flag, c->d_c,
                     c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
                     c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.a, c->d_zbox};
     for (void* p : ptrs)
@@ -735,8 +734,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (op->ras_kind != PFC_RAS_LEFT) A(dalloc(c, &c->d_zbox, (size_t)c->dec.nsub * c->dec.next));
     if (op->sub_solver == PFC_SUB_ILU0) {
         std::vector<int> lptr, lpts;
-        std::vector<int8_t> pair;
-        build_ilu_schedule(c, c->st, &lptr, &lpts, &pair);
+        build_ilu_schedule(c, &lptr, &lpts);
         c->nlev = (int)lptr.size() - 1;
         int widest = 0;
         for (int l = 0; l < c->nlev; ++l) widest = std::max(widest, lptr[l + 1] - lptr[l]);
@@ -745,13 +743,11 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
             s = fail(c, PFC_EINVAL, "ILU(0) box has a wavefront level wider than 192 cells");
         A(dalloc(c, &c->d_level_ptr, lptr.size()));
         A(dalloc(c, &c->d_level_pts, lpts.size()));
-        A(dalloc(c, &c->d_pair, pair.size()));
         c->fac_elems = (size_t)d.nsub * d.next * ilu_fac_elems_per_cell(c->st.S);
         A(dalloc(c, &c->d_work, (size_t)d.nsub * d.next * c->st.S));
         if (s == PFC_OK) {
             hipMemcpy(c->d_level_ptr, lptr.data(), sizeof(int) * lptr.size(), hipMemcpyHostToDevice);
             hipMemcpy(c->d_level_pts, lpts.data(), sizeof(int) * lpts.size(), hipMemcpyHostToDevice);
-            hipMemcpy(c->d_pair, pair.data(), pair.size(), hipMemcpyHostToDevice);
         }
     } else {
         c->lu_W = d.ext[0];

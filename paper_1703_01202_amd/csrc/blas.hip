@@ -36,29 +36,73 @@ __global__ __launch_bounds__(NT) void k_reduce_rows(const double* __restrict__ p
     if (threadIdx.x == 0) out[blockIdx.x] = s * scale;
 }
 
+// part[j * gridDim + b] = block b's share of V_j . w for j0 <= j < j0 + KK.  The vector count
+// is a template parameter so that the KK loads of an element are unconditional and in flight
+// together (a runtime count made each load a branch with its own wait).
+template <int KK>
+__device__ __forceinline__ void multidot_pass(const double* __restrict__ V, long ld, int j0,
+                                              const double* __restrict__ w, long n, double* __restrict__ part,
+                                              double* red) {
+    double acc[KK];
+#pragma unroll
+    for (int q = 0; q < KK; ++q) acc[q] = 0.0;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
+        const double wi = w[i];
+#pragma unroll
+        for (int q = 0; q < KK; ++q) acc[q] += V[(long)(j0 + q) * ld + i] * wi;
+    }
+#pragma unroll
+    for (int q = 0; q < KK; ++q) {
+        const double t = block_sum_det(acc[q], red);
+        if (threadIdx.x == 0) part[(long)(j0 + q) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
 // part[j * gridDim + b] = block b's share of V_j . w, j < k
 __global__ __launch_bounds__(NT) void k_multidot(const double* __restrict__ V, long ld, int k,
                                                  const double* __restrict__ w, long n,
                                                  double* __restrict__ part) {
     __shared__ double red[NT / 64];
     for (int j0 = 0; j0 < k; j0 += KG) {
-        double acc[KG];
-#pragma unroll
-        for (int q = 0; q < KG; ++q) acc[q] = 0.0;
-        const int kk = min(KG, k - j0);
-        for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
-            const double wi = w[i];
-#pragma unroll
-            for (int q = 0; q < KG; ++q)
-                if (q < kk) acc[q] += V[(long)(j0 + q) * ld + i] * wi;
+        switch (min(KG, k - j0)) {
+            case 1: multidot_pass<1>(V, ld, j0, w, n, part, red); break;
+            case 2: multidot_pass<2>(V, ld, j0, w, n, part, red); break;
+            case 3: multidot_pass<3>(V, ld, j0, w, n, part, red); break;
+            case 4: multidot_pass<4>(V, ld, j0, w, n, part, red); break;
+            case 5: multidot_pass<5>(V, ld, j0, w, n, part, red); break;
+            case 6: multidot_pass<6>(V, ld, j0, w, n, part, red); break;
+            case 7: multidot_pass<7>(V, ld, j0, w, n, part, red); break;
+            default: multidot_pass<8>(V, ld, j0, w, n, part, red); break;
         }
+    }
+}
+
+// s + sum_{q < KK} sign * cf[j0 + q] * V_{j0+q}[i], added in order of q (loads unconditional)
+template <int KK>
+__device__ __forceinline__ double axpy_chunk(const double* __restrict__ V, long ld, int j0, long i,
+                                             const double* cf, double sign, double s) {
+    double v[KK];
 #pragma unroll
-        for (int q = 0; q < KG; ++q) {
-            if (q < kk) {
-                const double s = block_sum_det(acc[q], red);
-                if (threadIdx.x == 0) part[(long)(j0 + q) * gridDim.x + blockIdx.x] = s;
-            }
-        }
+    for (int q = 0; q < KK; ++q) v[q] = V[(long)(j0 + q) * ld + i];
+#pragma unroll
+    for (int q = 0; q < KK; ++q) s += sign * cf[j0 + q] * v[q];
+    return s;
+}
+
+// s + sum_{j < k} sign * cf[j] * V_j[i], in order of j
+__device__ __forceinline__ double axpy_all(const double* __restrict__ V, long ld, int k, long i, const double* cf,
+                                           double sign, double s) {
+    int j = 0;
+    for (; j + KG <= k; j += KG) s = axpy_chunk<KG>(V, ld, j, i, cf, sign, s);
+    switch (k - j) {
+        case 1: return axpy_chunk<1>(V, ld, j, i, cf, sign, s);
+        case 2: return axpy_chunk<2>(V, ld, j, i, cf, sign, s);
+        case 3: return axpy_chunk<3>(V, ld, j, i, cf, sign, s);
+        case 4: return axpy_chunk<4>(V, ld, j, i, cf, sign, s);
+        case 5: return axpy_chunk<5>(V, ld, j, i, cf, sign, s);
+        case 6: return axpy_chunk<6>(V, ld, j, i, cf, sign, s);
+        case 7: return axpy_chunk<7>(V, ld, j, i, cf, sign, s);
+        default: return s;
     }
 }
 
@@ -81,8 +125,7 @@ __global__ __launch_bounds__(NT) void k_maxpy(const double* __restrict__ V, long
     const double sh = shift_part ? shift_scale * sum_partials_bcast(shift_part, shift_n, red) : 0.0;
     double acc = 0.0;
     for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
-        double s = assign ? 0.0 : w[i];
-        for (int j = 0; j < k; ++j) s += sign * cf[j] * V[(long)j * ld + i];
+        double s = axpy_all(V, ld, k, i, cf, sign, assign ? 0.0 : w[i]);
         if (shift_part) s += sh;
         w[i] = s;
         acc += s * s;
@@ -96,6 +139,31 @@ __global__ __launch_bounds__(NT) void k_maxpy(const double* __restrict__ V, long
 // One pass of Gram-Schmidt followed by the dots of the next one: w <- w + sign * sum_j c_j V_j
 // exactly as k_maxpy, and this block's share of V_q . w_new (q < k <= KG) into
 // dot_part[q * gridDim + b] exactly as k_multidot would compute it from the new w.
+template <int KK>
+__device__ __forceinline__ void maxpy_dot_body(const double* __restrict__ V, long ld, const double* cf, double sign,
+                                               double* __restrict__ w, long n, double* __restrict__ dot_part,
+                                               double* red) {
+    double acc[KK];
+#pragma unroll
+    for (int q = 0; q < KK; ++q) acc[q] = 0.0;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
+        double v[KK];
+#pragma unroll
+        for (int q = 0; q < KK; ++q) v[q] = V[(long)q * ld + i];
+        double s = w[i];
+#pragma unroll
+        for (int j = 0; j < KK; ++j) s += sign * cf[j] * v[j];
+        w[i] = s;
+#pragma unroll
+        for (int q = 0; q < KK; ++q) acc[q] += v[q] * s;
+    }
+#pragma unroll
+    for (int q = 0; q < KK; ++q) {
+        const double t = block_sum_det(acc[q], red);
+        if (threadIdx.x == 0) dot_part[(long)q * gridDim.x + blockIdx.x] = t;
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_maxpy_dot(const double* __restrict__ V, long ld, int k,
                                                   const double* __restrict__ coef_part, int coef_n, double sign,
                                                   double* __restrict__ w, long n, double* __restrict__ dot_part,
@@ -105,28 +173,16 @@ __global__ __launch_bounds__(NT) void k_maxpy_dot(const double* __restrict__ V, 
     rows_sum_bcast(coef_part, k, coef_n, cf, red);
     if (coef_out && blockIdx.x == 0)
         for (int j = threadIdx.x; j < k; j += NT) coef_out[j] = cf[j];
-    double acc[KG];
-#pragma unroll
-    for (int q = 0; q < KG; ++q) acc[q] = 0.0;
-    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
-        double v[KG];
-#pragma unroll
-        for (int q = 0; q < KG; ++q) v[q] = q < k ? V[(long)q * ld + i] : 0.0;
-        double s = w[i];
-#pragma unroll
-        for (int j = 0; j < KG; ++j)
-            if (j < k) s += sign * cf[j] * v[j];
-        w[i] = s;
-#pragma unroll
-        for (int q = 0; q < KG; ++q)
-            if (q < k) acc[q] += v[q] * s;
-    }
-#pragma unroll
-    for (int q = 0; q < KG; ++q) {
-        if (q < k) {
-            const double t = block_sum_det(acc[q], red);
-            if (threadIdx.x == 0) dot_part[(long)q * gridDim.x + blockIdx.x] = t;
-        }
+    switch (k) {
+        case 1: maxpy_dot_body<1>(V, ld, cf, sign, w, n, dot_part, red); break;
+        case 2: maxpy_dot_body<2>(V, ld, cf, sign, w, n, dot_part, red); break;
+        case 3: maxpy_dot_body<3>(V, ld, cf, sign, w, n, dot_part, red); break;
+        case 4: maxpy_dot_body<4>(V, ld, cf, sign, w, n, dot_part, red); break;
+        case 5: maxpy_dot_body<5>(V, ld, cf, sign, w, n, dot_part, red); break;
+        case 6: maxpy_dot_body<6>(V, ld, cf, sign, w, n, dot_part, red); break;
+        case 7: maxpy_dot_body<7>(V, ld, cf, sign, w, n, dot_part, red); break;
+        case 8: maxpy_dot_body<8>(V, ld, cf, sign, w, n, dot_part, red); break;
+        default: break;   // k is 1..KG (the launcher takes larger k apart)
     }
 }
 

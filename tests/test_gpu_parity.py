@@ -176,6 +176,30 @@ def test_ras_ilu0_3d_sampled_subdomains():
     s.close()
 
 
+@pytest.mark.parametrize("shape,ext", [((10, 24, 72), (7, 14, 38)), ((14, 34, 116), (9, 19, 60))])
+def test_ras_ilu0_3d_levels_wider_than_a_wave(shape, ext):
+    """Boxes of 38 x 14 x 7 and 60 x 19 x 9 cells: the widest wavefront level has 65 and 129
+    cells, so the apply gives each lane two and three cells of a level.  One box checked
+    against the oracle's ILU(0), with FP64 and FP32 factors."""
+    pfc = _pfc()
+    L = tuple(float(n) for n in shape)
+    h = S.spacing(shape, L)
+    Phi, phi = _pair(shape, 17, amp=0.05, mean=-0.2)
+    r = np.random.default_rng(18).standard_normal(shape)
+    J = S.jacobian_csr(Phi, phi, 0.1, 0.56, h)
+    d = W.decompose(shape, (2, 2, 2), 1)[3]
+    assert d.ext_n == ext
+    idx = d.ext_global_indices()
+    own = d.owned_mask_local()
+    y = W.ilu0_solve(W.ilu0(W.subdomain_matrix(J, d), W.subdomain_pattern(d.ext_n)), r.ravel()[idx])
+    for fp32, tol in ((False, 1e-11), (True, 1e-4)):
+        s = pfc.Solver(shape, L, 0.56, (2, 2, 2), 1, mass_project=False, precond_fp32=fp32)
+        s.ras_setup(T(Phi), T(phi), 0.1)
+        z = N(s.ras_apply(T(r))).ravel()
+        assert rel(z[idx[own]], y[own]) < tol
+        s.close()
+
+
 @pytest.mark.parametrize("n,L,sub,ov,dt,fp32,tol", [
     (64, 32 * math.pi, (4, 4), 2, 0.1, False, 1e-10),
     (256, 100.0, (4, 4), 4, 10.0, False, 1e-9),        # 72 x 72 boxes at the 1024^2 mesh size

@@ -418,33 +418,39 @@ struct SumGeom {
     int n[3], sub[3], own[3], ext[3], ovl[3], R[3];
 };
 
+// Candidate t (0 <= t < count) of one axis: its box index and the cell's position in that box's
+// extension (>= ext when the box does not cover the cell).
+struct AxisCover {
+    int k0, R, sub, own, ovl, n, all, count;
+    __device__ AxisCover(int pos, int R_, int sub_, int own_, int ovl_, int n_)
+        : k0(pos / own_), R(R_), sub(sub_), own(own_), ovl(ovl_), n(n_),
+          all(2 * R_ + 1 >= sub_), count(2 * R_ + 1 >= sub_ ? sub_ : 2 * R_ + 1) {}
+    __device__ int box(int t) const { return all ? t : wrapg(k0 - R + t, sub); }
+    __device__ int local(int pos, int kk) const { return wrapg(pos - (kk * own - ovl), n); }
+};
+
 __global__ __launch_bounds__(256) void k_schwarz_sum(const double* __restrict__ zbox, double* __restrict__ z,
                                                      SumGeom g, long N, int next) {
     for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < N; p += (long)gridDim.x * blockDim.x) {
-        const int pos[3] = {(int)(p % g.n[0]), (int)((p / g.n[0]) % g.n[1]), (int)(p / ((long)g.n[0] * g.n[1]))};
-        int kb[3][16], lb[3][16], nc[3];
-        for (int a = 0; a < 3; ++a) {
-            const int k0 = pos[a] / g.own[a];
-            const bool all = 2 * g.R[a] + 1 >= g.sub[a];
-            const int cnt = all ? g.sub[a] : 2 * g.R[a] + 1;
-            nc[a] = 0;
-            for (int t = 0; t < cnt; ++t) {
-                const int kk = all ? t : wrapg(k0 - g.R[a] + t, g.sub[a]);
-                const int loc = wrapg(pos[a] - (kk * g.own[a] - g.ovl[a]), g.n[a]);
-                if (loc < g.ext[a]) {
-                    kb[a][nc[a]] = kk;
-                    lb[a][nc[a]] = loc;
-                    ++nc[a];
+        const int px = (int)(p % g.n[0]), py = (int)((p / g.n[0]) % g.n[1]), pz = (int)(p / ((long)g.n[0] * g.n[1]));
+        const AxisCover ax(px, g.R[0], g.sub[0], g.own[0], g.ovl[0], g.n[0]);
+        const AxisCover ay(py, g.R[1], g.sub[1], g.own[1], g.ovl[1], g.n[1]);
+        const AxisCover az(pz, g.R[2], g.sub[2], g.own[2], g.ovl[2], g.n[2]);
+        double acc = 0.0;
+        for (int tz = 0; tz < az.count; ++tz) {
+            const int kz = az.box(tz), lz = az.local(pz, kz);
+            if (lz >= g.ext[2]) continue;
+            for (int ty = 0; ty < ay.count; ++ty) {
+                const int ky = ay.box(ty), ly = ay.local(py, ky);
+                if (ly >= g.ext[1]) continue;
+                for (int tx = 0; tx < ax.count; ++tx) {
+                    const int kx = ax.box(tx), lx = ax.local(px, kx);
+                    if (lx >= g.ext[0]) continue;
+                    const long k = ((long)kz * g.sub[1] + ky) * g.sub[0] + kx;
+                    acc += zbox[k * next + ((long)lz * g.ext[1] + ly) * g.ext[0] + lx];
                 }
             }
         }
-        double acc = 0.0;
-        for (int iz = 0; iz < nc[2]; ++iz)
-            for (int iy = 0; iy < nc[1]; ++iy)
-                for (int ix = 0; ix < nc[0]; ++ix) {
-                    const long k = ((long)kb[2][iz] * g.sub[1] + kb[1][iy]) * g.sub[0] + kb[0][ix];
-                    acc += zbox[k * next + ((long)lb[2][iz] * g.ext[1] + lb[1][iy]) * g.ext[0] + lb[0][ix]];
-                }
         z[p] = acc;
     }
 }

@@ -276,11 +276,11 @@ __device__ __forceinline__ double lap7(const double* __restrict__ a, int x, int 
     const long i = ((long)z * p.ny + y) * p.nx + x;
 
 // out = (a + b)/2 (mode 0) or a - s (mode 1), s = shift_scale * sum(shift_part[0..shift_n))
-// (s = 0 without shift_part; block 0 stores s in *shift_out)
-__global__ __launch_bounds__(256) void k_mp_combine(const double* __restrict__ a, const double* __restrict__ b,
+// (s = 0 without shift_part; block 0 stores s in *shift_out).  Elementwise: out may be a.
+__global__ __launch_bounds__(256) void k_mp_combine(const double* a, const double* __restrict__ b,
                                                     const double* __restrict__ shift_part, int shift_n,
                                                     double shift_scale, double* __restrict__ shift_out, int mode,
-                                                    double* __restrict__ out, long n) {
+                                                    double* out, long n) {
     __shared__ double red[4];
     double sh = 0.0;
     if (shift_part) {
@@ -296,10 +296,11 @@ __global__ void k_mp_lap(const double* __restrict__ u, double* __restrict__ out,
     out[i] = lap7(u, x, y, z, p);
 }
 
-// mu = (1-gamma) u + 2 Lu + Delta Lu + q (residual) or inner Jacobian operator (jv)
+// mu = (1-gamma) u + 2 Lu + Delta Lu + q (residual) or inner Jacobian operator (jv).  u is read
+// at the cell itself only, so out may be u (updated in place).
 __global__ void k_mp_inner(const double* __restrict__ Phi, const double* __restrict__ phi,
-                           const double* __restrict__ u, const double* __restrict__ Lu,
-                           const double* __restrict__ cc, int jv, double* __restrict__ out, P p) {
+                           const double* u, const double* __restrict__ Lu,
+                           const double* __restrict__ cc, int jv, double* out, P p) {
     MP_INDEX
     const double l = Lu[i];
     const double ll = lap7(Lu, x, y, z, p);
@@ -312,10 +313,11 @@ __global__ void k_mp_inner(const double* __restrict__ Phi, const double* __restr
     }
 }
 
-// residual (jv = 0): F = (Phi - phi)/dt - Delta mu - src ; jv: out = v/dt - Delta inner
-__global__ void k_mp_final(const double* __restrict__ a, const double* __restrict__ b,
+// residual (jv = 0): F = (Phi - phi)/dt - Delta mu - src ; jv: out = v/dt - Delta inner.  a is
+// read at the cell itself only, so out may be a (updated in place).
+__global__ void k_mp_final(const double* a, const double* __restrict__ b,
                            const double* __restrict__ m, const double* __restrict__ src, int jv,
-                           double* __restrict__ out, P p) {
+                           double* out, P p) {
     MP_INDEX
     const double lm = lap7(m, x, y, z, p);
     double f = (jv ? a[i] : a[i] - b[i]) * p.inv_dt - lm;
@@ -409,10 +411,9 @@ hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* ph
     hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, Phi, phi, nullptr, 0, 0.0, nullptr, 0, u,
                        c->g.N);
     hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, u, Lu, p);
-    // mu overwrites u only after every Lu neighbour is read: use F as the mu buffer
-    hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, Lu, nullptr, 0, F, p);
-    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, F, src, 0, u, p);
-    hipMemcpyAsync(F, u, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream);
+    // mu replaces u in place (u is read at the cell only); F is then written directly
+    hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, Lu, nullptr, 0, u, p);
+    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, src, 0, F, p);
     if (norm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, F, c->g.N, norm_part);
     return hipGetLastError();
 }
@@ -429,14 +430,15 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
         return launch_k(c, k_jv2d, tiles2d(c), dim3(NT), 0, v, cbuf, shift_part, shift_n, shift_scale, shift_out,
                         Jv, p);
     }
-    double* u = c->d_tmp3;
+    // the shifted v lives in the output buffer, the inner operator in the scratch vector, and the
+    // last pass updates the output in place (it reads the shifted v at the cell only)
+    double* w = c->d_tmp3;
     double* Lu = c->d_tmp3 + c->g.N;
     hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, v, nullptr, shift_part, shift_n,
-                       shift_scale, shift_out, 1, u, c->g.N);
-    hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, u, Lu, p);
-    hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, nullptr, nullptr, u, Lu, cbuf, 1, Jv, p);
-    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, u, nullptr, Jv, nullptr, 1, Lu, p);
-    hipMemcpyAsync(Jv, Lu, sizeof(double) * c->g.N, hipMemcpyDeviceToDevice, c->stream);
+                       shift_scale, shift_out, 1, Jv, c->g.N);
+    hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, Jv, Lu, p);
+    hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, nullptr, nullptr, Jv, Lu, cbuf, 1, w, p);
+    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Jv, nullptr, w, nullptr, 1, Jv, p);
     return hipGetLastError();
 }
 

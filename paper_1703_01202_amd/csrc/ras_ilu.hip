@@ -9,9 +9,11 @@
 // ILU(0) keeps exactly that pattern, natural (z, y, x) order, IKJ elimination.  Rows
 // are scheduled by the wavefront level x + 3y (2-D) / x + 3y + 7z (3-D): every
 // lower-triangular neighbour of a cell has a strictly smaller level, so all cells of
-// one level factor and solve independently.  One workgroup per subdomain; the solve
-// keeps the box vector in LDS and streams the factors, packed level by level with the
-// stencil index outermost so that the lanes of a level read consecutive addresses.
+// one level factor and solve independently.  One workgroup per subdomain; the solve (one
+// wave) keeps the box vector in LDS and streams the factors, packed level by level in
+// groups of four so that a lane's loads are 16 or 32 bytes wide and the lanes of a level
+// read consecutive addresses.  Classical AS and right-RAS (Eqs. (22), (24)) keep each box's
+// extended solution and add them per cell in a second kernel.
 #include <algorithm>
 #include <vector>
 

@@ -60,3 +60,24 @@ def test_batch_rejects_a_bad_instance_and_bad_fields(pfc):
     with pytest.raises(ValueError):
         batch.step([torch.zeros((8, 8), dtype=torch.float64, device="cuda")])
     batch.close()
+
+
+def test_autotune_times_candidates_and_skips_rejected_ones():
+    """The autotuner runs every candidate on the library, reports the ones the library rejects
+    (an overlap wider than the grid allows) with their error, leaves phi0 untouched, and returns
+    the fastest of the candidates that ran."""
+    from paper_1703_01202_amd.autotune import autotune
+    import pfc_inputs as I
+
+    w = I.small_noise_64()
+    phi0 = torch.from_numpy(w.initial()).cuda()
+    keep = phi0.clone()
+    kw = dict(sub_solver="ilu0", precond_fp32=False, dt_min=w.dt_min, dt_max=w.dt_max, guess="previous")
+    cands = [((4, 4), 2, 0), ((4, 4), 40, 0), ((2, 2), 2, 5)]
+    best, table = autotune(w.shape, w.lengths, w.gamma, phi0, kw, cands, steps=3, warmup=1)
+    assert torch.equal(phi0, keep)
+    assert len(table) == 3 and "error" in table[1] and "steps_per_s" not in table[1]
+    ran = [r for r in table if "steps_per_s" in r]
+    assert len(ran) == 2 and best is max(ran, key=lambda r: r["steps_per_s"])
+    assert all(r["newton_its"] > 0 for r in ran)
+    assert np.isfinite(best["steps_per_s"])

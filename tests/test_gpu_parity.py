@@ -142,6 +142,22 @@ def test_ras_ilu0_2d(project):
     s.close()
 
 
+@pytest.mark.parametrize("shape,sub,ov", [((16, 16), (2, 8), 0), ((16, 24), (2, 12), 0), ((12, 8, 8), (2, 4, 4), 0)])
+def test_ras_ilu0_thin_boxes(shape, sub, ov):
+    """Boxes two cells wide: some wavefront level values (x + 3y, + 7z) hold no cell and the
+    schedule skips them; the apply must still match the oracle's ILU(0)."""
+    pfc = _pfc()
+    L = tuple(float(n) for n in shape)
+    h = S.spacing(shape, L)
+    Phi, phi = _pair(shape, 21, amp=0.05, mean=-0.2)
+    s = pfc.Solver(shape, L, 0.56, sub, ov, mass_project=False)
+    s.ras_setup(T(Phi), T(phi), 0.1)
+    apply, _ = _oracle_ras(Phi, phi, 0.1, 0.56, h, sub, ov, "ilu0", False)
+    r = np.random.default_rng(22).standard_normal(shape)
+    assert rel(N(s.ras_apply(T(r))), apply(r)) < 1e-11
+    s.close()
+
+
 def test_ras_ilu0_fp32_2d():
     pfc = _pfc()
     w = I.small_noise_64()

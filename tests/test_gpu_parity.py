@@ -158,6 +158,15 @@ def test_ras_ilu0_thin_boxes(shape, sub, ov):
     s.close()
 
 
+def test_ilu0_box_with_a_level_wider_than_three_cells_per_lane_is_rejected():
+    """The apply gives a lane at most three cells of a wavefront level; a box of 72 x 24 x 11
+    cells has a level of 194 cells, and the library refuses it at creation."""
+    pfc = _pfc()
+    shape = (18, 44, 140)
+    with pytest.raises(pfc.PfcError):
+        pfc.Solver(shape, tuple(float(n) for n in shape), 0.56, (2, 2, 2), 1, precond_fp32=True)
+
+
 def test_ras_ilu0_fp32_2d():
     pfc = _pfc()
     w = I.small_noise_64()

@@ -127,7 +127,11 @@ void pfc_default_opts(pfc_opts* o);
 
 /* Create a solver context for one grid.  stream is a hipStream_t (NULL: default
  * stream).  Allocates all device workspace (Krylov basis, factors); PFC_ENOMEM if the
- * device is out of memory, PFC_EINVAL for bad sizes or options. */
+ * device is out of memory, PFC_EINVAL for bad sizes or options.  Limits of the subdomain
+ * solvers (PFC_EINVAL beyond them): an ILU(0) box's vector must fit in 160 KiB of LDS
+ * (one spare element included) and its widest wavefront level (cells with equal
+ * x + 3y + 7z) must hold at most 192 cells; exact LU is 2-D and bounds the box width by
+ * the LDS its factorisation needs. */
 pfc_status pfc_create(const pfc_grid* g, const pfc_model* m, const pfc_opts* o,
                       void* stream, pfc_ctx** out);
 void pfc_destroy(pfc_ctx* ctx);

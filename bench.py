@@ -366,6 +366,35 @@ def run_3d_256(steps):
     return out
 
 
+def run_crack(steps):
+    """Test C's grid: 4096 x 1024 on [0, 4096 pi/3] x [0, 1024 pi/3], the notched lattice, gamma 1,
+    adaptive dt 1..5 (eta 100); FP32 exact-LU subdomain solves on 16 x 64 boxes of 64 x 64 owned
+    cells, overlap 3; extrapolated guess, factors lagged up to 20 steps."""
+    import torch
+    import paper_1703_01202_amd as pfc
+    import pfc_inputs as I
+    w = I.crack_4096x1024()
+    phi = torch.from_numpy(w.initial()).cuda()
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, sub_solver="lu", precond_fp32=True,
+                   guess="extrap", dt_min=w.dt_min, dt_max=w.dt_max, eta=w.eta, precond_lag=20, timing=True)
+    s.step(phi)   # untimed: first factorisation and warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [s.step(phi) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {k: s.kernel_time(k) for k in range(4)}
+    s.close()
+    N = w.shape[0] * w.shape[1]
+    e = [st["energy"] for st in stats]
+    out = {"workload": "pfc2d_crack_4096x1024", "steps": steps, "seconds": el, "steps_per_s": steps / el,
+           "dof_steps_per_s": N * steps / el, "newton_its": sum(st["newton_its"] for st in stats),
+           "gmres_its": sum(st["gmres_its"] for st in stats), "dt_last": stats[-1]["dt"],
+           "energy_monotone": all(b <= a for a, b in zip(e, e[1:])), "kernels": kt}
+    print(f"[bench] test C 4096x1024: {steps / el:.1f} steps/s", file=sys.stderr, flush=True)
+    return out
+
+
 def run_table2():
     """Table 2's Test A block (256^2, first 10 steps of dt = 0.01, ILU(0), 4 x 4 boxes): Newton and
     GMRES counts and seconds for classical AS delta 0..2 and left/right-RAS delta 1..2."""
@@ -398,6 +427,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     ap.add_argument("--no-table2", action="store_true", help="skip the Test A preconditioner study (Table 2)")
     ap.add_argument("--steps-3d-256", type=int, default=6, help="steps of the 256^3 test-D grid (0 skips it)")
+    ap.add_argument("--steps-crack", type=int, default=20, help="steps of the 4096x1024 test-C grid (0 skips it)")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -441,6 +471,7 @@ def main():
     three_d = None if args.no_3d else run_3d(args.steps_3d)
     table2 = None if args.no_table2 else run_table2()
     three_d_256 = run_3d_256(args.steps_3d_256) if args.steps_3d_256 > 0 else None
+    crack = run_crack(args.steps_crack) if args.steps_crack > 0 else None
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
@@ -483,6 +514,8 @@ def main():
         out["detail"]["table2_test_a"] = table2
     if three_d_256 is not None:
         out["detail"]["pfc3d_bcc_256"] = three_d_256
+    if crack is not None:
+        out["detail"]["pfc2d_crack_4096x1024"] = crack
     print(json.dumps(out), flush=True)
 
 

@@ -249,9 +249,8 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ c
 // the box), so whatever the clamped read returns adds nothing.
 // The apply runs one wave per box, and a wave's LDS operations take effect in program order,
 // so a level only has to keep the compiler from moving LDS accesses across the level boundary.
-// A workgroup barrier would also wait for every global load in flight, including the factors
-// fetched ahead for the next levels.  The scheduling barrier keeps each level's work (and the
-// fetch that follows it) in its place, so that the wait before a level is for that level's loads.
+// The scheduling barrier keeps each level's work (and the fetch that follows it) in its place,
+// so that the wait before a level is for that level's loads.
 __device__ __forceinline__ void wave_lds_order() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, 
                 const int p = min(tid + 64 * c, nld - 1);
                 pkd[c] = lpts[p0 + p];
 #pragma unroll
-                for (int q = 0; q < QL; ++q) dst[c][q] = base[(long)q * nld + p];
+                for (int q = 0; q < QL; ++q) dst[c][q] = __builtin_nontemporal_load(&base[(long)q * nld + p]);
             }
         };
         zero_slots(f, pk, nl);
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64) void k_ilu_apply(const double* __restrict__ r, 
                 const int p = min(tid + 64 * c, nld - 1);
                 pkd[c] = lpts[p0 + p];
 #pragma unroll
-                for (int q = 0; q < QU; ++q) dst[c][q] = base[(long)q * nld + p];
+                for (int q = 0; q < QU; ++q) dst[c][q] = __builtin_nontemporal_load(&base[(long)q * nld + p]);
             }
         };
         zero_slots(f, pk, nl);

@@ -458,7 +458,9 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
 
 // Block solve.  Thread (p, g), g < G = blockDim / W, handles row p of a block row and the
 // columns q = g + G*i of its dense product; it holds the factors of DEPTH block rows ahead
-// in registers so that their loads overlap the barriers of the current row.
+// in registers so that their loads overlap the barriers of the current row.  The factors are
+// read once per apply and far exceed the caches, so they are loaded non-temporally: they
+// stream past the caches instead of evicting the box vectors' gather lines.
 //   forward  (half 0): z_I = y_I - [Lh(I,I-3..I-1)] y[(I-3)W : IW]        (3W columns)
 //   backward (half 1): x_I = [S_II^-1 | -Uh(I,I+1..I+3)] y[IW : (I+4)W]    (4W columns)
 template <typename T, int NPL, int DEPTH>
@@ -490,7 +492,7 @@ __global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z,
 #pragma unroll
         for (int i = 0; i < NPL; ++i) {
             const int q = g + G * i;
-            l[i] = (act && q < ncol) ? base[q * W + p] : (T)0;
+            l[i] = (act && q < ncol) ? __builtin_nontemporal_load(&base[q * W + p]) : (T)0;
         }
     };
     auto rotate = [&]() {

@@ -459,8 +459,9 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
 // Block solve.  Thread (p, g), g < G = blockDim / W, handles row p of a block row and the
 // columns q = g + G*i of its dense product; it holds the factors of DEPTH block rows ahead
 // in registers so that their loads overlap the barriers of the current row.  The factors are
-// read once per apply and far exceed the caches, so they are loaded non-temporally: they
-// stream past the caches instead of evicting the box vectors' gather lines.
+// read once per apply and far exceed the caches; with three rows in flight they are loaded
+// non-temporally, streaming past the caches instead of evicting the box vectors' gather
+// lines (measured faster there; with one row in flight, on 70-wide boxes, it was slower).
 //   forward  (half 0): z_I = y_I - [Lh(I,I-3..I-1)] y[(I-3)W : IW]        (3W columns)
 //   backward (half 1): x_I = [S_II^-1 | -Uh(I,I+1..I+3)] y[IW : (I+4)W]    (4W columns)
 template <typename T, int NPL, int DEPTH>
@@ -486,13 +487,17 @@ __global__ void k_lu_apply(const double* __restrict__ r, double* __restrict__ z,
     }
 
     T pl[DEPTH + 1][NPL];
+    constexpr bool kNonTemporal = DEPTH >= 3;
     auto load = [&](int I, int half, T* l) {
         const T* base = F + (long)I * 7 * WW + half * 3 * WW;
         const int ncol = half ? 4 * W : 3 * W;
 #pragma unroll
         for (int i = 0; i < NPL; ++i) {
             const int q = g + G * i;
-            l[i] = (act && q < ncol) ? __builtin_nontemporal_load(&base[q * W + p]) : (T)0;
+            if constexpr (kNonTemporal)
+                l[i] = (act && q < ncol) ? __builtin_nontemporal_load(&base[q * W + p]) : (T)0;
+            else
+                l[i] = (act && q < ncol) ? base[q * W + p] : (T)0;
         }
     };
     auto rotate = [&]() {

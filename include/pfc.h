@@ -180,6 +180,21 @@ pfc_status pfc_newton(pfc_ctx* ctx, const double* phi, double dt, double* Phi,
  * and the step retried from phi^n.  The first call after pfc_reset uses dt_min. */
 pfc_status pfc_step(pfc_ctx* ctx, double* phi, pfc_step_stats* st);
 
+/* The Newton initial guess Phi_0 of one step phi^n -> phi^(n+1) of size dt (Sec. 4: the
+ * paper starts from the previous solution), from explicit history instead of the context's:
+ *   kind PFC_GUESS_PREVIOUS: X = phi (phi_prev, dt, dt_prev ignored; may be NULL / 0);
+ *   kind PFC_GUESS_EXTRAP:   X = phi + (dt/dt_prev) (phi - phi_prev);
+ *   kind PFC_GUESS_LEARNED:  X = phi + s_o y, y = the attached network (include/pfc_net.h) at
+ *                            x[0] = (phi - mean phi)/s_a, x[1] = (dt/dt_prev)(phi - phi_prev)/s_b.
+ * When mass_project is set, the extrapolated and learned guesses are then shifted by a
+ * constant to the mass of phi.  This is the computation pfc_step makes with its stored history
+ * (there with the fallbacks described at pfc_step); it serves callers that run their own time
+ * loop and tests.  phi, phi_prev, X: device FP64 fields of the context's grid; X aliases neither
+ * input.  PFC_EINVAL for a bad kind, missing phi_prev or non-positive dt/dt_prev (kinds 1, 2),
+ * or the learned kind without an attached network.  Enqueues only. */
+pfc_status pfc_guess(pfc_ctx* ctx, int kind, const double* phi, const double* phi_prev, double dt,
+                     double dt_prev, double* X);
+
 /* Forget the time history (step counter, energies, previous solution). */
 pfc_status pfc_reset(pfc_ctx* ctx);
 

@@ -252,6 +252,17 @@ def _solve_fft_gmres(J, rhs, shape, h, dt, gamma, cbar, workers=-1):
     A = spla.LinearOperator((n, n), matvec=lambda x: J @ x, dtype=np.float64)
     M = spla.LinearOperator((n, n), matvec=prec, dtype=np.float64)
     x, info = spla.gmres(A, rhs, M=M, rtol=1e-14, atol=0.0, restart=60, maxiter=40)
+    # the direction must be the exact one to rounding: the true residual must reach 1e-12 of
+    # the right-hand side, or the rounding level of the product J x itself (eps || |J| |x| ||,
+    # which binds at large dt) when that level is below 1e-8 of the right-hand side, whatever
+    # GMRES reports; an unconverged solve is never returned
+    bn = float(np.linalg.norm(rhs))
+    res = float(np.linalg.norm(rhs - J @ x))
+    floor = np.finfo(np.float64).eps * float(np.linalg.norm(abs(J) @ np.abs(x)))
+    floor = floor if floor <= 1e-8 * bn else 0.0
+    if info < 0 or not np.isfinite(res) or res > max(1e-12 * bn, floor):
+        raise RuntimeError(f"FFT-preconditioned GMRES did not converge (info {info}, residual {res:.3e} "
+                           f"of {bn:.3e}, rounding level {floor:.3e})")
     return x
 
 

@@ -199,6 +199,52 @@ def ilu0(A, pattern):
     return rows
 
 
+# ---------------------------------------------------------------------------
+# ILU(k): level-of-fill pattern (Saad, Iterative Methods for Sparse Linear Systems,
+# Sec. 10.3.3), numeric factorisation by the same IKJ loop on that pattern
+# ---------------------------------------------------------------------------
+
+def iluk_levels(pattern, k):
+    """Level of fill of every kept entry of ILU(k) for a matrix with structural ``pattern``.
+
+    Entries of the matrix have level 0.  Eliminating row i in the IKJ order, each
+    k' < i of row i whose level is at most k updates every j > k' of row k' and gives
+    (i, j) the level min(lev(i, j), lev(i, k') + lev(k', j) + 1); entries whose level
+    exceeds k are dropped when row i is done.  Returns one dict {col: level} per row.
+    """
+    n = len(pattern)
+    rows = [dict.fromkeys(p, 0) for p in pattern]
+    for i in range(n):
+        rows[i][i] = 0
+    for i in range(1, n):
+        ri = rows[i]
+        done = set()
+        while True:                  # lower entries in increasing column order, fill included
+            cand = [c for c in ri if c < i and c not in done and ri[c] <= k]
+            if not cand:
+                break
+            kk = min(cand)
+            done.add(kk)
+            lik = ri[kk]
+            for j, lkj in rows[kk].items():
+                if j > kk:
+                    lev = lik + lkj + 1
+                    if lev <= k and lev < ri.get(j, k + 1):
+                        ri[j] = lev
+        rows[i] = {c: v for c, v in ri.items() if v <= k}
+    return rows
+
+
+def iluk_pattern(pattern, k):
+    """Sorted column lists of the ILU(k) pattern (ILU(0): the matrix's own pattern)."""
+    return [sorted(r) for r in iluk_levels(pattern, k)]
+
+
+def iluk(A, pattern, k):
+    """ILU(k) of A: the IKJ loop of ``ilu0`` on the level-k pattern."""
+    return ilu0(A, iluk_pattern(pattern, k))
+
+
 def ilu0_solve(rows, b):
     """Solve (L U) x = b with the factors of ``ilu0`` (forward, then backward)."""
     n = len(rows)
@@ -238,7 +284,7 @@ def ilu0_dense_factors(rows):
 # ---------------------------------------------------------------------------
 
 class SubdomainSolver:
-    """inv(A_k) by sparse LU ('lu') or ILU(0) ('ilu0')."""
+    """inv(A_k) by sparse LU ('lu'), ILU(0) ('ilu0') or ILU(k) ('ilu1', 'ilu2', ...)."""
 
     def __init__(self, A, kind, ext_n):
         self.kind = kind
@@ -246,6 +292,8 @@ class SubdomainSolver:
             self.lu = spla.splu(sp.csc_matrix(A))
         elif kind == "ilu0":
             self.rows = ilu0(A, subdomain_pattern(ext_n))
+        elif kind.startswith("ilu") and kind[3:].isdigit():
+            self.rows = iluk(A, subdomain_pattern(ext_n), int(kind[3:]))
         else:
             raise ValueError(kind)
 

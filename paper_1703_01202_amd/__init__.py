@@ -171,6 +171,15 @@ class Solver:
         self._check(self.lib.pfc_step(self.ctx, self._field(phi, "phi"), ctypes.byref(st)))
         return st.as_dict()
 
+    def guess(self, kind, phi, phi_prev=None, dt=0.0, dt_prev=0.0, out=None):
+        """Newton initial guess of ``kind`` ("previous" | "extrap" | "learned") from explicit
+        history (pfc_guess)."""
+        X = out if out is not None else self._empty()
+        self._check(self.lib.pfc_guess(self.ctx, _lib.GUESS[kind], self._field(phi, "phi"),
+                                       self._field(phi_prev, "phi_prev") if phi_prev is not None else None,
+                                       float(dt), float(dt_prev), self._field(X, "X")))
+        return X
+
     def reset(self):
         self._check(self.lib.pfc_reset(self.ctx))
 

@@ -94,6 +94,8 @@ SIGNATURES = {
     "pfc_net_get_gradient": (ctypes.c_int, [ctypes.c_void_p, c_float_p]),
     "pfc_net_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double]),
+    "pfc_guess": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_void_p]),
     "pfc_attach_net": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, ctypes.c_double]),
     # batched instances (include/pfc_batch.h)
     "pfc_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(PfcGrid), ctypes.POINTER(PfcModel),

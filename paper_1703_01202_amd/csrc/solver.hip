@@ -561,31 +561,37 @@ int guess_kind(const pfc_ctx* c, double dt) {
     return PFC_GUESS_PREVIOUS;
 }
 
-// d_X = initial guess of kind `used` for the step phi^n -> phi^(n+1) of size dt; the
-// extrapolated and learned guesses are shifted to the mass of phi^n when mass_project is set.
-pfc_status make_guess(pfc_ctx* c, const double* phi, double dt, int used) {
+// X = initial guess of kind `used` for the step phi^n -> phi^(n+1), from phi = phi^n,
+// prev = phi^(n-1) and ratio = dt_n / dt_(n-1); the extrapolated and learned guesses are
+// shifted to the mass of phi^n when mass_project is set.
+pfc_status guess_into(pfc_ctx* c, const double* phi, const double* prev, double ratio, int used, double* X) {
     const long N = c->g.N;
     if (used == PFC_GUESS_PREVIOUS) {
-        HIPCHK(hipMemcpyAsync(c->d_X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
         return PFC_OK;
     }
     if (used == PFC_GUESS_EXTRAP) {
-        HIPCHK(launch_extrap(c->stream, phi, c->d_prev, dt / c->dt_nm1, c->d_X, N));
+        HIPCHK(launch_extrap(c->stream, phi, prev, ratio, X, N));
     } else {
         double* part = part_md1(c);
         HIPCHK(launch_dot(c->stream, phi, nullptr, N, part));
         double* diff = c->opts.mass_project ? part_md2(c) : nullptr;   // partials of phi - X
-        pfc_status s = net_guess(c->net, c->stream, phi, c->d_prev, c->g.ny, c->g.nx, dt / c->dt_nm1, c->net_scale,
-                                 part, kRedBlocks, c->netw, c->d_X, diff);
+        pfc_status s = net_guess(c->net, c->stream, phi, prev, c->g.ny, c->g.nx, ratio, c->net_scale,
+                                 part, kRedBlocks, c->netw, X, diff);
         if (s != PFC_OK) return fail(c, s, std::string("learned guess: ") + net_error(c->net));
-        if (diff) HIPCHK(launch_shift(c->stream, c->d_X, diff, kRedBlocks, 1.0 / (double)N, N));
+        if (diff) HIPCHK(launch_shift(c->stream, X, diff, kRedBlocks, 1.0 / (double)N, N));
         return PFC_OK;
     }
     if (c->opts.mass_project) {   // restore the mass of phi^n exactly: X += mean(phi - X)
-        HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, c->d_X, c->d_w, N));
-        CHK(shift_by_sum(c, c->d_X, c->d_w, 1.0 / (double)N));
+        HIPCHK(launch_axpby(c->stream, 1.0, phi, -1.0, X, c->d_w, N));
+        CHK(shift_by_sum(c, X, c->d_w, 1.0 / (double)N));
     }
     return PFC_OK;
+}
+
+// d_X = the guess of kind `used` for the step of size dt from the stored history.
+pfc_status make_guess(pfc_ctx* c, const double* phi, double dt, int used) {
+    return guess_into(c, phi, c->d_prev, used == PFC_GUESS_PREVIOUS ? 1.0 : dt / c->dt_nm1, used, c->d_X);
 }
 
 }  // namespace
@@ -1012,6 +1018,17 @@ pfc_status pfc_kernel_time(pfc_ctx* c, int which, long* count, double* total_ms)
     *count = c->timer.count[which];
     *total_ms = c->timer.total_ms[which];
     return PFC_OK;
+}
+
+pfc_status pfc_guess(pfc_ctx* c, int kind, const double* phi, const double* phi_prev, double dt, double dt_prev,
+                     double* X) {
+    if (!c) return PFC_EINVAL;
+    if (!phi || !X || X == phi || X == phi_prev) return fail(c, PFC_EINVAL, "bad argument");
+    if (kind < PFC_GUESS_PREVIOUS || kind > PFC_GUESS_LEARNED) return fail(c, PFC_EINVAL, "bad guess kind");
+    if (kind != PFC_GUESS_PREVIOUS && (!phi_prev || !(dt > 0) || !(dt_prev > 0)))
+        return fail(c, PFC_EINVAL, "the extrapolated and learned guesses need phi_prev and positive dt, dt_prev");
+    if (kind == PFC_GUESS_LEARNED && !c->net) return fail(c, PFC_EINVAL, "no network attached");
+    return guess_into(c, phi, phi_prev, kind == PFC_GUESS_PREVIOUS ? 1.0 : dt / dt_prev, kind, X);
 }
 
 pfc_status pfc_attach_net(pfc_ctx* c, pfc_net* net, const double* scales, double dt_train) {

@@ -1,0 +1,102 @@
+"""Failure handling of the solve, driven from the host so that every kernel exits normally:
+a non-finite field, a Newton solve that misses its tolerance (the dt-halving retry of
+pfc_step), GMRES that misses its tolerance, and lagged factors that no longer precondition
+(the refresh with fresh factors).  Status codes are those of include/pfc.h."""
+import numpy as np
+import pytest
+
+import pfc_inputs as I
+from oracle import scheme as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ENAN, ENOTCONV, EKRYLOV = -4, -5, -6
+
+
+@pytest.fixture(scope="module")
+def pfc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1703_01202_amd as m
+    return m
+
+
+def _solver(pfc, w, **kw):
+    return pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, **kw)
+
+
+def test_non_finite_field_is_reported(pfc):
+    w = I.small_noise_64()
+    phi0 = w.initial()
+    phi0[5, 7] = np.nan
+    s = _solver(pfc, w, dt_min=0.1)
+    phi = torch.from_numpy(phi0).cuda()
+    with pytest.raises(pfc.PfcError) as e:
+        s.step(phi)
+    assert e.value.status == ENAN
+    with pytest.raises(pfc.PfcError) as e:
+        s.residual(phi, phi, 0.1)
+    assert e.value.status == ENAN
+    s.close()
+
+
+def test_failed_newton_solve_halves_dt_and_retries(pfc):
+    """Exact linear solves (GMRES to 1e-12) and two Newton iterations: on the 64^2 noise state
+    the oracle's residual after two exact Newton steps is 2.1e-7, 1.6e-8 and 8.0e-10 at
+    dt = 0.4, 0.2 and 0.1.  With eps_a = 4e-9 the step at dt = 0.4 and its first retry fail
+    and the second retry, at dt = 0.1, is accepted; with one retry allowed the step fails."""
+    w = I.small_noise_64()
+    h = S.spacing(w.shape, w.lengths)
+    phi0 = w.initial()
+    kw = dict(dt_min=0.4, dt_max=0.4, newton_rtol=0.0, newton_atol=4e-9, newton_maxit=2, lin_rtol=1e-12,
+              lin_atol=0.0)
+    s = _solver(pfc, w, max_retries=4, **kw)
+    phi = torch.from_numpy(phi0).cuda()
+    st = s.step(phi)
+    assert st["rejected"] == 2 and st["dt"] == 0.1, st
+    res = np.linalg.norm(S.residual(phi.cpu().numpy(), phi0, 0.1, w.gamma, h))
+    assert res <= 4e-9 * 1.01, res
+    s.close()
+    s = _solver(pfc, w, max_retries=1, **kw)
+    phi = torch.from_numpy(phi0).cuda()
+    with pytest.raises(pfc.PfcError) as e:
+        s.step(phi)
+    assert e.value.status == ENOTCONV
+    s.close()
+
+
+def test_gmres_that_misses_its_tolerance_is_reported(pfc):
+    w = I.small_noise_64()
+    phi = torch.from_numpy(w.initial()).cuda()
+    s = _solver(pfc, w, gmres_maxit=2)
+    s.ras_setup(phi, phi, 0.1)
+    b = torch.from_numpy(np.random.default_rng(3).standard_normal(w.shape)).cuda()
+    with pytest.raises(pfc.PfcError) as e:
+        s.gmres(phi, phi, 0.1, b, 1e-12, 0.0)
+    assert e.value.status == EKRYLOV
+    s.close()
+
+
+def test_stale_lagged_factors_are_refreshed(pfc):
+    """Factors kept across steps (precond_lag) are replaced, between two steps, by factors of
+    a far-away state (phi = 5 everywhere); the next step first tries them, fails within its
+    GMRES and Newton budgets, and then solves with fresh factors: one factorisation more,
+    and the accepted state passes the oracle's residual test."""
+    w = I.small_noise_64()
+    h = S.spacing(w.shape, w.lengths)
+    s = _solver(pfc, w, dt_min=0.1, newton_rtol=0.0, newton_atol=1e-10, precond_lag=50, gmres_maxit=8,
+                newton_maxit=4, timing=8)
+    phi = torch.from_numpy(w.initial()).cuda()
+    s.step(phi)
+    before = phi.cpu().numpy()
+    far = torch.full(w.shape, 5.0, dtype=torch.float64, device="cuda")
+    s.ras_setup(far, far, 0.1)
+    nfac = s.kernel_time(3)[0]
+    st = s.step(phi)
+    assert s.kernel_time(3)[0] == nfac + 1, st
+    assert st["rejected"] == 0
+    res = np.linalg.norm(S.residual(phi.cpu().numpy(), before, 0.1, w.gamma, h))
+    assert res <= 1.01e-10, res
+    s.close()

@@ -211,3 +211,42 @@ def test_trained_network_gains_over_the_method_without_it(pfc):
         assert np.linalg.norm(out[g]["phi"] - ref["phi"]) <= 1e-8 * np.linalg.norm(ref["phi"])
         assert max(abs(m - ref["mass"][0]) for m in out[g]["mass"]) <= 1e-12 * abs(ref["mass"][0])
         assert all(b <= a + 1e-9 * abs(a) for a, b in zip(out[g]["energy"], out[g]["energy"][1:]))
+
+
+@pytest.mark.parametrize("shape,L,sub,ov", [((1024, 1024), (400.0, 400.0), (16, 64), 4),
+                                           ((40, 70), (25.0, 44.0), (2, 2), 3)])
+def test_solver_learned_guess_matches_oracle(pfc, shape, L, sub, ov):
+    """The solver's learned initial guess (pfc_guess, the computation pfc_step makes): the
+    input planes (mean removal, step ratio, scales), the network and the epilogue
+    X = phi + s_o y with its shift to the mass of phi, against the oracle's guess on the
+    same weights, at the 1024^2 crystal mesh with the benchmark's boxes and on a grid that
+    is ragged against the 32 x 8 network tiles.  y agrees to ~1e-4 of its scale (module
+    header), so X to a few 1e-4 of s_o max|y|; the mass of phi is kept to rounding."""
+    import pfc_inputs as I
+    theta = _params(15, out_scale=0.5)
+    n = shape[0]
+    phi = I.hex_crystallites_ic(n=n, L=L[0], seed=1) if shape[0] == shape[1] else \
+        I.noise_ic(shape, -0.285, 0.3, 16)
+    prev = phi + 0.02 * np.random.default_rng(17).standard_normal(shape)
+    scales = (0.3, 0.02, 0.01)
+    dt, dt_prev = 0.012, 0.01
+    net = pfc.GuessNet(theta)
+    s = pfc.Solver(shape, L, 0.25, sub, ov, sub_solver="lu", precond_fp32=True, guess="learned")
+    s.attach_net(net, scales, dt)
+    P = torch.from_numpy(phi).cuda()
+    X = s.guess("learned", P, torch.from_numpy(prev).cuda(), dt, dt_prev).cpu().numpy()
+    ref = cnn.guess(theta, phi, prev, dt / dt_prev, scales)
+    y_ref, _ = cnn.forward(theta, cnn.make_input(phi, prev, dt / dt_prev, scales[0], scales[1]))
+    bound = 4e-4 * scales[2] * np.abs(y_ref).max()
+    assert np.abs(X - ref).max() <= bound, (np.abs(X - ref).max(), bound)
+    assert abs(X.sum() - phi.sum()) <= 1e-12 * np.abs(phi).sum()
+    # the previous-step and extrapolated kinds are their closed forms
+    Xp = s.guess("previous", P).cpu().numpy()
+    assert np.array_equal(Xp, phi)
+    Xe = s.guess("extrap", P, torch.from_numpy(prev).cuda(), dt, dt_prev).cpu().numpy()
+    e = phi + (dt / dt_prev) * (phi - prev)
+    e += np.mean(phi) - np.mean(e)
+    assert np.abs(Xe - e).max() <= 1e-13 * np.abs(e).max()
+    with pytest.raises(pfc.PfcError):
+        s.guess("extrap", P, None, dt, dt_prev)
+    s.close()

@@ -291,3 +291,64 @@ def test_solution_self_convergence_second_order_in_time():
     errs = [S.rel_l2(_mms_solve(L, n, g, T, m)[0], ref) for m in (8, 16, 32)]
     rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
     assert all(1.8 < r < 2.3 for r in rates), (errs, rates)
+
+
+def test_fft_gmres_newton_matches_direct_128():
+    """The oracle's solver above 256^2 (FFT-preconditioned GMRES to 1e-14) gives the root of
+    the exact sparse direct Newton at 128^2 on the crystal mesh size, small and large dt."""
+    w = I.crystal_growth(128, (2, 2))
+    phi = w.initial()
+    h = S.spacing(w.shape, w.lengths)
+    for dt in (0.01, 10.0):
+        a = S.newton_solve(phi, dt, w.gamma, h, linear="direct")
+        b = S.newton_solve(phi, dt, w.gamma, h, linear="fftgmres")
+        assert a.converged and b.converged
+        assert S.rel_l2(b.Phi, a.Phi) < 1e-12
+
+
+@pytest.mark.slow
+def test_fft_gmres_newton_matches_direct_256():
+    w = I.crystal_growth(256, (2, 2))
+    phi = w.initial()
+    h = S.spacing(w.shape, w.lengths)
+    a = S.newton_solve(phi, 1.0, w.gamma, h, linear="direct")
+    b = S.newton_solve(phi, 1.0, w.gamma, h, linear="fftgmres")
+    assert S.rel_l2(b.Phi, a.Phi) < 1e-12
+
+
+def test_fft_gmres_refuses_an_unconverged_solve():
+    """A system with no solution (the Jacobian with its first row zeroed, a right-hand side
+    that is not zero there) raises instead of returning an inexact direction."""
+    w = I.crystal_growth(64, (2, 2))
+    phi = w.initial()
+    h = S.spacing(w.shape, w.lengths)
+    J = S.jacobian_csr(phi, phi, 10.0, w.gamma, h)
+    rhs = np.random.default_rng(0).standard_normal(phi.size)
+    bad = J.tolil()
+    bad[0, :] = 0.0
+    with pytest.raises(RuntimeError):
+        S._solve_fft_gmres(bad.tocsr(), rhs, w.shape, h, 10.0, w.gamma, float(np.mean(S.jacobian_coef(phi, phi))))
+    x = S._solve_fft_gmres(J, rhs, w.shape, h, 10.0, w.gamma, float(np.mean(S.jacobian_coef(phi, phi))))
+    floor = np.finfo(np.float64).eps * np.linalg.norm(abs(J) @ np.abs(x))     # rounding level of J x
+    assert np.linalg.norm(J @ x - rhs) <= max(1e-12 * np.linalg.norm(rhs), floor)
+
+
+def test_run_dt_history_three_steps():
+    """Eq. (16) in the time loop: dt_0 = dt_min; dt_1 from F^1, F^0 and dt_0; dt_2 from F^2, F^1
+    and dt_1 (the energies of the states the loop accepted).  A constant state keeps its
+    energy, so every later step takes dt_max; eta = 0 does the same for any state."""
+    w = I.small_noise_64()
+    h = S.spacing(w.shape, w.lengths)
+    phi0 = w.initial()
+    tr = S.run(phi0, 3, w.gamma, h, 0.05, 2.0, eta=0.01)
+    E, d = tr.energies, tr.dts
+    assert d[0] == 0.05
+    fp1 = abs(E[1] - E[0]) / d[0]
+    fp2 = abs(E[2] - E[1]) / d[1]
+    assert d[1] == pytest.approx(max(0.05, 2.0 / math.sqrt(1.0 + 0.01 * fp1 * fp1)), rel=1e-15)
+    assert d[2] == pytest.approx(max(0.05, 2.0 / math.sqrt(1.0 + 0.01 * fp2 * fp2)), rel=1e-15)
+    assert 0.05 < d[1] < 2.0 and 0.05 < d[2] < 2.0          # the formula's interior branch ran
+    flat = S.run(np.full(w.shape, -0.285), 3, w.gamma, h, 0.05, 2.0, eta=40.0)
+    assert flat.dts == [0.05, 2.0, 2.0]
+    free = S.run(phi0, 2, w.gamma, h, 0.05, 2.0, eta=0.0)
+    assert free.dts == [0.05, 2.0]

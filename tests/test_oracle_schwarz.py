@@ -243,3 +243,126 @@ def test_natural_order_ilu0_on_test_d_mesh_size(dt, stable):
     else:
         assert piv.min() < 0
         assert abs(ev).max() > 1e6
+
+
+# ---------------------------------------------------------------------------
+# ILU(k) (Sec. 4 subdomain solvers; Table 1's ILU(1) and ILU(2) columns)
+# ---------------------------------------------------------------------------
+
+def _fill_path_levels(pattern):
+    """Level of every entry by the fill-path theorem (Hysom and Pothen): (i, j) has level L
+    when the shortest path from i to j in the graph of A whose inner vertices are all numbered
+    below min(i, j) has L + 1 edges.  Brute force, one search per pair."""
+    n = len(pattern)
+    adj = [set(p) - {i} for i, p in enumerate(pattern)]
+    lev = {}
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                lev[(i, j)] = 0
+                continue
+            m = min(i, j)
+            dist = {i: 0}
+            frontier = [i]
+            found = None
+            while frontier and found is None:
+                nxt = []
+                for u in frontier:
+                    for v in adj[u]:
+                        if v == j:
+                            found = dist[u] + 1
+                            break
+                        if v < m and v not in dist:
+                            dist[v] = dist[u] + 1
+                            nxt.append(v)
+                    if found is not None:
+                        break
+                frontier = nxt
+            if found is not None:
+                lev[(i, j)] = found - 1
+    return lev
+
+
+@pytest.mark.parametrize("ext", [(8, 8), (9, 7)])
+def test_iluk_levels_follow_the_fill_path_theorem(ext):
+    pat = W.subdomain_pattern(ext)
+    ref = _fill_path_levels(pat)
+    for k in (0, 1, 2, 3):
+        rows = W.iluk_levels(pat, k)
+        got = {(i, j): v for i, r in enumerate(rows) for j, v in r.items()}
+        want = {key: v for key, v in ref.items() if v <= k}
+        assert got == want, k
+
+
+def test_iluk_defining_property_and_nesting():
+    shape, h = (20, 20), (0.5, 0.5)
+    Phi, phi = _state(shape, 4)
+    J = S.jacobian_csr(Phi, phi, 0.01, 0.25, h)
+    d = W.decompose(shape, (2, 2), 2)[1]
+    A = W.subdomain_matrix(J, d).toarray()
+    pat = W.subdomain_pattern(d.ext_n)
+    prev = None
+    for k in (0, 1, 2):
+        pk = W.iluk_pattern(pat, k)
+        if prev is not None:
+            assert all(set(a) < set(b) or set(a) == set(b) for a, b in zip(prev, pk))
+            assert sum(map(len, pk)) > sum(map(len, prev))
+        prev = pk
+        L, U = W.ilu0_dense_factors(W.iluk(A, pat, k))
+        LU = L @ U
+        mask = np.zeros_like(A, dtype=bool)
+        for i, cols in enumerate(pk):
+            mask[i, cols] = True
+        np.testing.assert_allclose(LU[mask], A[mask], atol=1e-11 * np.abs(A).max())
+        if k == 0:
+            assert W.iluk(A, pat, 0) == W.ilu0(A, pat)
+
+
+def test_iluk_with_enough_levels_is_the_exact_lu():
+    """With enough levels the pattern is the whole band profile of the box matrix (no entry
+    of the exact LU factors is dropped) and ILU(k) is the exact factorisation."""
+    shape, h = (16, 16), (0.5, 0.5)
+    Phi, phi = _state(shape, 5)
+    J = S.jacobian_csr(Phi, phi, 0.1, 0.25, h)
+    d = W.decompose(shape, (2, 2), 1)[0]
+    A = W.subdomain_matrix(J, d).toarray()
+    pat = W.subdomain_pattern(d.ext_n)
+    n = A.shape[0]
+    k = 0
+    while sum(map(len, W.iluk_pattern(pat, k))) != sum(map(len, W.iluk_pattern(pat, k + 1))):
+        k += 1
+    rows = W.iluk(A, pat, k)
+    L, U = W.ilu0_dense_factors(rows)
+    np.testing.assert_allclose(L @ U, A, atol=1e-12 * np.abs(A).max())
+    b = np.random.default_rng(6).standard_normal(n)
+    np.testing.assert_allclose(W.ilu0_solve(rows, b), np.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("dt,own,ov,stable_levels", [(0.01, 16, 4, (1, 2)), (1.0, 32, 3, ())])
+def test_natural_order_iluk_on_test_b_mesh_size(dt, own, ov, stable_levels):
+    """Why the 1024^2 crystal workload (test B's mesh, h = 400/1024) uses exact subdomain LU:
+    natural-order ILU(k) of its subdomain matrices (Eqs. (25)-(26), at the benchmark's crystal
+    state) is stable only at the benchmark's dt_min = 0.01 on boxes 24 cells wide, and only
+    with fill (k = 1, 2: positive pivots, preconditioned spectrum near 1); ILU(0) has negative
+    pivots there.  At test B's dt = 1 on a box 38 cells wide, ILU(0), ILU(1) and ILU(2) all
+    have negative pivots and preconditioned spectra beyond 1e4 in modulus."""
+    import pfc_inputs as I
+    n = 8 * own
+    L = 400.0 * n / 1024
+    phi = I.hex_crystallites_ic(n=n, L=L, seed=1)
+    h = S.spacing((n, n), (L, L))
+    doms = W.decompose((n, n), (8, 8), ov)
+    dom = max(doms, key=lambda d: np.var(phi.ravel()[d.ext_global_indices()]))   # a box on a crystallite
+    A = W.subdomain_matrix_zero_ring(phi, phi, dt, 0.25, h, dom)
+    pat = W.subdomain_pattern(dom.ext_n)
+    for k in (0, 1, 2):
+        rows = W.iluk(A, pat, k)
+        piv = np.array([r[i] for i, r in enumerate(rows)])
+        Lf, Uf = W.ilu0_dense_factors(rows)
+        ev = np.linalg.eigvals(np.linalg.solve(Uf, np.linalg.solve(Lf, A)))
+        if k in stable_levels:
+            assert piv.min() > 0, k
+            assert 0.5 < ev.real.min() and abs(ev).max() < 2, (k, ev.real.min(), abs(ev).max())
+        else:
+            assert piv.min() < 0, k
+            assert abs(ev).max() > 1e4, (k, abs(ev).max())

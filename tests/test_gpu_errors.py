@@ -81,22 +81,25 @@ def test_gmres_that_misses_its_tolerance_is_reported(pfc):
 
 def test_stale_lagged_factors_are_refreshed(pfc):
     """Factors kept across steps (precond_lag) are replaced, between two steps, by factors of
-    a far-away state (phi = 5 everywhere); the next step first tries them, fails within its
-    GMRES and Newton budgets, and then solves with fresh factors: one factorisation more,
-    and the accepted state passes the oracle's residual test."""
+    a far-away state (phi = 50 everywhere, a Jacobian coefficient 3750 instead of ~0.12); the
+    next step first tries them, fails within its budgets (two Newton steps of at most eight
+    GMRES iterations; fresh factors need two Newton steps of two or three to reach 1e-7 on
+    this state: the oracle's inexact Newton gives 1.9e-3 and 1.6e-8), and then solves with
+    fresh factors: one factorisation more, and the accepted state passes the oracle's
+    residual test."""
     w = I.small_noise_64()
     h = S.spacing(w.shape, w.lengths)
-    s = _solver(pfc, w, dt_min=0.1, newton_rtol=0.0, newton_atol=1e-10, precond_lag=50, gmres_maxit=8,
-                newton_maxit=4, timing=8)
+    s = _solver(pfc, w, dt_min=0.1, newton_rtol=0.0, newton_atol=1e-7, precond_lag=50, gmres_maxit=8,
+                newton_maxit=2, timing=8)
     phi = torch.from_numpy(w.initial()).cuda()
     s.step(phi)
     before = phi.cpu().numpy()
-    far = torch.full(w.shape, 5.0, dtype=torch.float64, device="cuda")
+    far = torch.full(w.shape, 50.0, dtype=torch.float64, device="cuda")
     s.ras_setup(far, far, 0.1)
     nfac = s.kernel_time(3)[0]
     st = s.step(phi)
     assert s.kernel_time(3)[0] == nfac + 1, st
     assert st["rejected"] == 0
     res = np.linalg.norm(S.residual(phi.cpu().numpy(), before, 0.1, w.gamma, h))
-    assert res <= 1.01e-10, res
+    assert res <= 1.01e-7, res
     s.close()

@@ -209,6 +209,19 @@ pfc_status pfc_reset(pfc_ctx* ctx);
 pfc_status pfc_checkpoint_save(pfc_ctx* ctx, const double* phi, const char* path);
 pfc_status pfc_checkpoint_load(pfc_ctx* ctx, double* phi, const char* path);
 
+/* The residual of pfc_residual (same kernel, bitwise the same F and norm) without a context
+ * and without allocating: for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc).  2-D grids only (PFC_EUNSUP for
+ * dim 3, whose residual needs two grid-sized work vectors); mobility must be 0; n >= 8 per
+ * axis, dt > 0, F aliasing neither input (PFC_EINVAL otherwise).  Phi, phi, src (nullable), F:
+ * device FP64 [ny][nx]; stream: hipStream_t (NULL = default).  The kernel's per-block partial
+ * sums of ||F||^2 (at most 1024) go to a fixed 8 KiB device array of the library, one per GPU,
+ * kept until the process ends; calls that overlap on one GPU race on it.  With norm2 (host)
+ * the call synchronises the stream and returns ||F||_2 (PFC_ENAN if not finite); without it,
+ * it only enqueues.  PFC_EHIP on a HIP error. */
+pfc_status pfc_residual_noalloc(const pfc_grid* g, const pfc_model* m, const double* Phi, const double* phi,
+                                double dt, const double* src, double* F, double* norm2, void* stream);
+
 /* Per-kernel timing (bit which of opts.timing): which = 0 preconditioner apply, 1 residual,
  * 2 Jacobian action, 3 factorisation.  Returns the launch count and the summed
  * event-measured duration in milliseconds since the last pfc_reset.  Single-kernel regions

@@ -81,6 +81,9 @@ SIGNATURES = {
     "pfc_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "pfc_checkpoint_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_char_p]),
     "pfc_checkpoint_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_char_p]),
+    "pfc_residual_noalloc": (ctypes.c_int, [ctypes.POINTER(PfcGrid), ctypes.POINTER(PfcModel), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                            c_double_p, ctypes.c_void_p]),
     "pfc_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_long), c_double_p]),
     # learned initial guess (include/pfc_net.h)
     "pfc_net_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),

@@ -186,6 +186,12 @@ inline hipError_t set_dynamic_lds_limit(const void* f) {
 // ---- stencil kernels (stencil.hip) ----
 // Reductions leave per-block partials (device_reduce.h); partial_count gives their number.
 int residual_partial_count(const pfc_ctx* c);   // blocks of the residual kernel
+// The 2-D residual kernel outside a context: grid nx x ny with 1/h^2 per axis, on stream s;
+// writes residual2d_blocks(nx, ny) (at most 1024) partial sums of F^2 to norm_part.
+int residual2d_blocks(int nx, int ny);
+hipError_t launch_residual2d_plain(hipStream_t s, int nx, int ny, double ihx2, double ihy2, double gamma,
+                                   double dt, const double* Phi, const double* phi, const double* src, double* F,
+                                   double* norm_part);
 int energy_partial_count(const pfc_ctx* c);     // blocks of the energy kernel (two partials each)
 // F and per-block partials of ||F||^2 (norm_part) and of ||Phi||^2 (xnorm_part); both nullable
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,

@@ -442,6 +442,28 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
     return hipGetLastError();
 }
 
+int residual2d_blocks(int nx, int ny) {
+    const unsigned t = (unsigned)(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY));
+    return (int)(t < 1024u ? t : 1024u);
+}
+
+hipError_t launch_residual2d_plain(hipStream_t s, int nx, int ny, double ihx2, double ihy2, double gamma,
+                                   double dt, const double* Phi, const double* phi, const double* src, double* F,
+                                   double* norm_part) {
+    P p;
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = 1;
+    p.ihx2 = ihx2;
+    p.ihy2 = ihy2;
+    p.ihz2 = 0.0;
+    p.gamma = gamma;
+    p.inv_dt = dt > 0 ? 1.0 / dt : 0.0;
+    hipLaunchKernelGGL(k_residual2d, dim3(residual2d_blocks(nx, ny)), dim3(NT), 0, s, Phi, phi, src, F, norm_part,
+                       (double*)nullptr, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2, double* acc_phi, double* acc_prev) {
     const P p = make_params(c, 0.0);
     if (c->g.dim == 2) {

@@ -72,7 +72,10 @@ typedef struct {
  * added where they overlap; right-RAS (Eq. (24)): restrict the owned cells only, extend with
  * overlap and add.  The sums over overlapping boxes are formed per cell in a fixed order. */
 enum { PFC_RAS_LEFT = 0, PFC_AS_CLASSICAL = 1, PFC_RAS_RIGHT = 2 };
-enum { PFC_SUB_ILU0 = 0, PFC_SUB_LU = 1 };         /* subdomain solvers (Sec. 4) */
+/* Subdomain solvers (Sec. 4; Table 1): ILU(0) on the stencil pattern, exact LU (2-D), and
+ * ILU(k) with k = pfc_opts.ilu_level levels of fill (k = 0 gives the ILU(0) factors through the
+ * general-pattern kernels). */
+enum { PFC_SUB_ILU0 = 0, PFC_SUB_LU = 1, PFC_SUB_ILUK = 2 };
 enum { PFC_GUESS_PREVIOUS = 0, PFC_GUESS_EXTRAP = 1, PFC_GUESS_LEARNED = 2 };
 
 typedef struct {
@@ -84,7 +87,7 @@ typedef struct {
     int sub[3];                       /* subdomains per axis (x, y, z) */
     int overlap;                      /* overlap in mesh layers (paper's delta = 3 layers) */
     int ras_kind;                     /* PFC_RAS_LEFT (default), PFC_AS_CLASSICAL or PFC_RAS_RIGHT */
-    int sub_solver;                   /* PFC_SUB_ILU0 or PFC_SUB_LU (2-D only) */
+    int sub_solver;                   /* PFC_SUB_ILU0, PFC_SUB_LU (2-D only) or PFC_SUB_ILUK */
     int precond_fp32;                 /* 1: factors stored and applied in FP32 */
     int mass_project;                 /* 1: zero-mean projection of guess and directions */
     int guess;                        /* PFC_GUESS_* */
@@ -110,6 +113,7 @@ typedef struct {
                                          one launch; needs a non-default stream (PFC_EINVAL otherwise) and
                                          is ignored while timing is on.  Results are bitwise those of the
                                          launches made one by one. */
+    int ilu_level;                    /* levels of fill k of PFC_SUB_ILUK, 0..4 (default 2) */
 } pfc_opts;
 
 /* Per-step statistics.  res0 = ||F|| at the initial guess, res_final at the accepted
@@ -131,7 +135,8 @@ void pfc_default_opts(pfc_opts* o);
  * solvers (PFC_EINVAL beyond them): an ILU(0) box's vector must fit in 160 KiB of LDS
  * (one spare element included) and its widest wavefront level (cells with equal
  * x + 3y + 7z) must hold at most 192 cells; exact LU is 2-D and bounds the box width by
- * the LDS its factorisation needs. */
+ * the LDS its factorisation needs; ILU(k) needs a box of at most 65534 cells whose vector fits
+ * in LDS and rows of at most 256 entries. */
 pfc_status pfc_create(const pfc_grid* g, const pfc_model* m, const pfc_opts* o,
                       void* stream, pfc_ctx** out);
 void pfc_destroy(pfc_ctx* ctx);

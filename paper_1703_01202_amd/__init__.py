@@ -50,7 +50,9 @@ def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precon
     for a in range(3):
         o.sub[a] = revS[a] if a < dim else 1
     o.overlap = int(overlap)
-    o.sub_solver = _lib.SUB_SOLVERS[sub_solver]
+    o.sub_solver, level = _lib.sub_solver_code(sub_solver)
+    if o.sub_solver == _lib.SUB_SOLVERS["iluk"]:
+        o.ilu_level = level
     o.ras_kind = _lib.RAS_KINDS[ras_kind]
     o.precond_fp32 = int(bool(precond_fp32))
     o.mass_project = int(bool(mass_project))
@@ -75,7 +77,7 @@ class Solver:
 
     def __init__(self, shape, lengths, gamma, sub, overlap, stream=None, **options):
         """Options (keywords, defaults as in pfc_default_opts unless given): sub_solver
-        ("ilu0" | "lu"), precond_fp32, dt_min (0.1), dt_max (= dt_min), eta, newton_rtol,
+        ("ilu0" | "lu" | "ilu1" .. "ilu4" | "iluk0"), precond_fp32, dt_min (0.1), dt_max (= dt_min), eta, newton_rtol,
         newton_atol, lin_rtol, lin_atol, gmres_restart, gmres_maxit, newton_maxit, guess
         ("previous" | "extrap" | "learned"), mass_project, max_retries, timing (True, or the
         bitmask of pfc_opts.timing), precond_lag,

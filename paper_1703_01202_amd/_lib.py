@@ -18,7 +18,19 @@ c_float_p = ctypes.POINTER(ctypes.c_float)
 PFC_OK = 0
 STATUS = {0: "PFC_OK", -1: "PFC_EINVAL", -2: "PFC_ENOMEM", -3: "PFC_EHIP", -4: "PFC_ENAN",
           -5: "PFC_ENOTCONV", -6: "PFC_EKRYLOV", -7: "PFC_EPIVOT", -8: "PFC_EUNSUP"}
-SUB_SOLVERS = {"ilu0": 0, "lu": 1}
+SUB_SOLVERS = {"ilu0": 0, "lu": 1, "iluk": 2}
+
+
+def sub_solver_code(name):
+    """(pfc_opts.sub_solver, pfc_opts.ilu_level) of "ilu0", "lu", or "iluK" (K = 1..4: ILU(K)
+    through the general-pattern kernels; "iluk0" is ILU(0) through those same kernels)."""
+    if name in ("ilu0", "lu"):
+        return SUB_SOLVERS[name], 0
+    if name == "iluk0":
+        return SUB_SOLVERS["iluk"], 0
+    if name.startswith("ilu") and name[3:].isdigit() and 1 <= int(name[3:]) <= 4:
+        return SUB_SOLVERS["iluk"], int(name[3:])
+    raise ValueError(f"unknown subdomain solver {name!r}")
 RAS_KINDS = {"left": 0, "as": 1, "right": 2}
 GUESS = {"previous": 0, "extrap": 1, "learned": 2}
 
@@ -41,7 +53,7 @@ class PfcOpts(ctypes.Structure):
         ("guess", ctypes.c_int),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double), ("eta", ctypes.c_double),
         ("max_retries", ctypes.c_int), ("timing", ctypes.c_int), ("precond_lag", ctypes.c_int),
-        ("newton_rel_ref", ctypes.c_int), ("use_graph", ctypes.c_int),
+        ("newton_rel_ref", ctypes.c_int), ("use_graph", ctypes.c_int), ("ilu_level", ctypes.c_int),
     ]
 
 

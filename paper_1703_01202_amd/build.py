@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["stencil.hip", "blas.hip", "ras_ilu.hip", "ras_lu.hip", "net.hip", "solver.hip", "batch.hip", "noalloc.hip"]
+SOURCES = ["stencil.hip", "blas.hip", "ras_ilu.hip", "ras_iluk.hip", "ras_lu.hip", "net.hip", "solver.hip", "batch.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "libpfc.so")
 
 FLAGS = [

@@ -76,6 +76,8 @@ struct NetWork {
 };
 constexpr int kNetWorkFloats = 32 + 9;   // floats of NetWork::a per cell
 
+struct IlukPlan;   // ILU(k) pattern, schedules and working factors (ras_iluk.hip)
+
 }  // namespace pfc
 
 struct pfc_ctx {
@@ -101,6 +103,7 @@ struct pfc_ctx {
     int* d_flag = nullptr;             // pivot failure flag
     double* d_zbox = nullptr;          // per-box extended solutions (classical AS, right-RAS)
     int lu_W = 0, lu_H = 0;            // exact LU: block size (box x-extent) and block rows
+    pfc::IlukPlan* iluk = nullptr;     // ILU(k): pattern and schedules shared by the boxes
 
     // vectors (N doubles each)
     double* d_c = nullptr;             // Jacobian coefficient at the current iterate
@@ -231,6 +234,13 @@ hipError_t launch_ilu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_ilu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
 // packed ILU(0) factor elements per cell for a stencil of S offsets
 int ilu_fac_elems_per_cell(int S);
+// ---- ILU(k) (ras_iluk.hip) ----
+pfc_status iluk_plan_create(pfc_ctx* c, int level, std::string* err);   // sets c->iluk, c->fac_elems
+void iluk_plan_free(IlukPlan* p);
+void iluk_plan_stats(const IlukPlan* p, long* nnz, int* fac_levels, int* passes_f, int* passes_b, long* slots);
+hipError_t launch_iluk_factor(pfc_ctx* c, const StencilTable& st);
+hipError_t launch_iluk_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);
+hipError_t set_iluk_lds_limits();
 constexpr int kIluMaxCellsPerLane = 3;   // widest wavefront level an ILU(0) box may have: 64 * this
 hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& t);
 hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_part);

@@ -200,6 +200,8 @@ pfc_status setup_impl(pfc_ctx* c, const double* Phi, const double* phi, double d
     timer_begin(c, 3, &ts);
     if (c->opts.sub_solver == PFC_SUB_LU)
         HIPCHK(launch_lu_factor(c, st));
+    else if (c->opts.sub_solver == PFC_SUB_ILUK)
+        HIPCHK(launch_iluk_factor(c, st));
     else
         HIPCHK(launch_ilu_factor(c, st));
     timer_end(c, ts);
@@ -235,6 +237,8 @@ pfc_status apply_raw(pfc_ctx* c, const double* r, double* z, double* sum_part) {
     timer_begin(c, 0, &ts, left);
     if (c->opts.sub_solver == PFC_SUB_LU)
         HIPCHK(launch_lu_apply(c, r, z, sum_part));
+    else if (c->opts.sub_solver == PFC_SUB_ILUK)
+        HIPCHK(launch_iluk_apply(c, r, z, sum_part));
     else
         HIPCHK(launch_ilu_apply(c, r, z, sum_part));
     if (!left) HIPCHK(launch_schwarz_sum(c, c->d_zbox, z));
@@ -544,6 +548,8 @@ void free_all(pfc_ctx* c) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     drop_graphs(c);
+    iluk_plan_free(c->iluk);
+    c->iluk = nullptr;
     if (c->h_pin) hipHostFree(c->h_pin);
     if (c->h_y) hipHostFree(c->h_y);
     for (auto e : c->timer.pool) hipEventDestroy(e);
@@ -622,6 +628,7 @@ void pfc_default_opts(pfc_opts* o) {
     o->precond_lag = 0;
     o->newton_rel_ref = 1;
     o->use_graph = 0;
+    o->ilu_level = 2;
 }
 
 pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* op, void* stream,
@@ -661,7 +668,10 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
             const int own = gr->n[a] / op->sub[a], R = (op->overlap + own - 1) / own;
             if (std::min(2 * R + 1, op->sub[a]) > 16) s = bad("overlap too wide for the AS / right-RAS sum");
         }
-    if (s == PFC_OK && op->sub_solver != PFC_SUB_ILU0 && op->sub_solver != PFC_SUB_LU) s = bad("bad sub_solver");
+    if (s == PFC_OK && op->sub_solver != PFC_SUB_ILU0 && op->sub_solver != PFC_SUB_LU && op->sub_solver != PFC_SUB_ILUK)
+        s = bad("bad sub_solver");
+    if (s == PFC_OK && op->sub_solver == PFC_SUB_ILUK && (op->ilu_level < 0 || op->ilu_level > 4))
+        s = bad("ilu_level must be 0..4");
     if (s == PFC_OK && op->sub_solver == PFC_SUB_LU && dim != 2) {
         c->err = "exact subdomain LU is built for 2-D only";
         s = PFC_EUNSUP;
@@ -755,6 +765,10 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
             hipMemcpy(c->d_level_ptr, lptr.data(), sizeof(int) * lptr.size(), hipMemcpyHostToDevice);
             hipMemcpy(c->d_level_pts, lpts.data(), sizeof(int) * lpts.size(), hipMemcpyHostToDevice);
         }
+    } else if (op->sub_solver == PFC_SUB_ILUK) {
+        std::string e;
+        const pfc_status r = iluk_plan_create(c, op->ilu_level, &e);
+        if (r != PFC_OK && s == PFC_OK) s = fail(c, r, e);
     } else {
         c->lu_W = d.ext[0];
         c->lu_H = d.ext[1];
@@ -770,7 +784,8 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
                         hipHostGetDevicePointer((void**)&c->d_hpin, c->h_pin, 0) != hipSuccess ||
                         hipHostMalloc((void**)&c->h_y, sizeof(double) * (SC_SHIFT - SC_Y + 1)) != hipSuccess))
         s = fail(c, PFC_ENOMEM, "pinned allocation failed");
-    if (s == PFC_OK && (set_ilu_lds_limits() != hipSuccess || set_lu_lds_limits() != hipSuccess))
+    if (s == PFC_OK && (set_ilu_lds_limits() != hipSuccess || set_lu_lds_limits() != hipSuccess ||
+                        set_iluk_lds_limits() != hipSuccess))
         s = fail(c, PFC_EHIP, "cannot raise the LDS limit");
     if (s == PFC_OK && hipMemset(c->d_scal, 0, sizeof(double) * c->n_scal) != hipSuccess)
         s = fail(c, PFC_EHIP, "memset");

@@ -1,0 +1,150 @@
+"""ILU(k) subdomain solves (Sec. 4; Table 1's ILU(1) and ILU(2) columns) against the oracle's
+ILU(k): the Schwarz applies on 2-D and 3-D grids, FP64 and FP32 factors, the three Schwarz
+forms, and a Newton solve.  Tolerances as for ILU(0): the applies agree to rounding in FP64
+(rel 1e-11) and to the FP32 factors' precision (rel 1e-4)."""
+import math
+
+import numpy as np
+import pytest
+
+import pfc_inputs as I
+from oracle import scheme as S
+from oracle import schwarz as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _pfc():
+    import paper_1703_01202_amd as pfc
+    return pfc
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _oracle_apply(Phi, phi, dt, gamma, h, sub, ov, kind, variant="left"):
+    J = S.jacobian_csr(Phi, phi, dt, gamma, h)
+    doms = W.decompose(Phi.shape, sub, ov)
+    sol = W.schwarz_setup(J, doms, kind)
+    return lambda r: W.schwarz_apply(r, doms, sol, variant)
+
+
+@pytest.mark.parametrize("name,kind", [("iluk0", "ilu0"), ("ilu1", "ilu1"), ("ilu2", "ilu2")])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_ras_iluk_2d_matches_oracle(name, kind, fp32):
+    pfc = _pfc()
+    w = I.small_noise_64()
+    h = S.spacing(w.shape, w.lengths)
+    phi = w.initial()
+    Phi = phi + 0.01 * np.random.default_rng(31).standard_normal(w.shape)
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, sub_solver=name, precond_fp32=fp32,
+                   mass_project=False)
+    s.ras_setup(T(Phi), T(phi), 0.1)
+    apply = _oracle_apply(Phi, phi, 0.1, w.gamma, h, w.sub, w.overlap, kind)
+    for seed in (32, 33):
+        r = np.random.default_rng(seed).standard_normal(w.shape)
+        assert rel(N(s.ras_apply(T(r))), apply(r)) < (1e-4 if fp32 else 1e-11)
+    s.close()
+
+
+@pytest.mark.parametrize("variant", ["as", "right"])
+def test_schwarz_variants_iluk_2d(variant):
+    pfc = _pfc()
+    # boxes of 20 x 35 owned cells and overlap 3 at the 64^2 workload's mesh size (h = pi/2),
+    # where ILU(1) keeps positive pivots
+    shape = (40, 70)
+    L = (40 * math.pi / 2, 70 * math.pi / 2)
+    h = S.spacing(shape, L)
+    g = np.random.default_rng(34)
+    phi = -0.285 + 0.05 * g.uniform(-1, 1, shape)
+    Phi = phi + 0.01 * g.standard_normal(shape)
+    s = pfc.Solver(shape, L, 0.25, (2, 2), 3, sub_solver="ilu1", mass_project=False, ras_kind=variant)
+    s.ras_setup(T(Phi), T(phi), 0.1)
+    apply = _oracle_apply(Phi, phi, 0.1, 0.25, h, (2, 2), 3, "ilu1", variant)
+    r = g.standard_normal(shape)
+    assert rel(N(s.ras_apply(T(r))), apply(r)) < 1e-11
+    s.close()
+
+
+@pytest.mark.parametrize("fp32,tol", [(False, 1e-11), (True, 1e-4)])
+def test_ras_iluk_3d_sampled_boxes(fp32, tol):
+    """3-D ILU(1) on 8^3 boxes (4^3 owned, overlap 2): two boxes checked against the oracle."""
+    pfc = _pfc()
+    shape, L = (16, 16, 16), (16.0, 16.0, 16.0)
+    h = S.spacing(shape, L)
+    g = np.random.default_rng(35)
+    phi = -0.2 + 0.05 * g.uniform(-1, 1, shape)
+    Phi = phi + 0.01 * g.standard_normal(shape)
+    r = g.standard_normal(shape)
+    s = pfc.Solver(shape, L, 0.56, (4, 4, 4), 2, sub_solver="ilu1", mass_project=False, precond_fp32=fp32)
+    s.ras_setup(T(Phi), T(phi), 0.1)
+    z = N(s.ras_apply(T(r))).ravel()
+    J = S.jacobian_csr(Phi, phi, 0.1, 0.56, h)
+    doms = W.decompose(shape, (4, 4, 4), 2)
+    pat = W.subdomain_pattern(doms[0].ext_n)
+    for d in (doms[0], doms[37]):
+        rows = W.ilu0(W.subdomain_matrix(J, d), W.iluk_pattern(pat, 1))
+        idx = d.ext_global_indices()
+        own = d.owned_mask_local()
+        y = W.ilu0_solve(rows, r.ravel()[idx])
+        assert rel(z[idx[own]], y[own]) < tol
+    s.close()
+
+
+def test_ras_iluk2_on_the_crystal_benchmark_boxes():
+    """ILU(2) on the 1024^2 benchmark's box shape (24 x 72 cells: 16 x 64 owned, overlap 4) at its
+    mesh size and dt = 0.01, FP32 factors: two boxes of a 256^2 crystal grid against the oracle."""
+    pfc = _pfc()
+    n = 256
+    L = 400.0 * n / 1024
+    shape = (n, n)
+    h = S.spacing(shape, (L, L))
+    phi = I.hex_crystallites_ic(n=n, L=L, seed=1)
+    s = pfc.Solver(shape, (L, L), 0.25, (4, 16), 4, sub_solver="ilu2", precond_fp32=True, mass_project=False)
+    s.ras_setup(T(phi), T(phi), 0.01)
+    r = np.random.default_rng(36).standard_normal(shape)
+    z = N(s.ras_apply(T(r))).ravel()
+    J = S.jacobian_csr(phi, phi, 0.01, 0.25, h)
+    doms = W.decompose(shape, (4, 16), 4)
+    pat = W.iluk_pattern(W.subdomain_pattern(doms[0].ext_n), 2)
+    for d in (doms[5], doms[40]):
+        rows = W.ilu0(W.subdomain_matrix(J, d), pat)
+        idx = d.ext_global_indices()
+        own = d.owned_mask_local()
+        y = W.ilu0_solve(rows, r.ravel()[idx])
+        assert rel(z[idx[own]], y[own]) < 1e-4
+    s.close()
+
+
+def test_newton_with_ilu2_matches_oracle_root():
+    pfc = _pfc()
+    w = I.small_noise_64()
+    h = S.spacing(w.shape, w.lengths)
+    phi = w.initial()
+    # the Newton tolerance stays above the linear solve's absolute one (xi_a): a residual
+    # between the two would get a zero correction and stall the line search
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, sub_solver="ilu2", newton_rtol=0.0,
+                   newton_atol=1e-11, lin_atol=1e-14)
+    Phi, st = s.newton(T(phi), 0.1)
+    assert rel(N(Phi), S.newton_solve(phi, 0.1, w.gamma, h).Phi) < 1e-11
+    s.close()
+
+
+def test_iluk_options_are_checked():
+    pfc = _pfc()
+    w = I.small_noise_64()
+    with pytest.raises(ValueError):
+        pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, sub_solver="ilu9")
+    with pytest.raises(pfc.PfcError):     # boxes of 41 x 40 x 40 = 65600 cells are refused
+        pfc.Solver((64, 64, 66), (64.0, 64.0, 66.0), 0.56, (2, 2, 2), 4, sub_solver="ilu1")

@@ -209,8 +209,13 @@ __device__ __forceinline__ void tile_product(const double* A, const double* B, i
 }
 
 // Boxes of width W <= kSmallW: every block of a step is staged in LDS:
-//   G0, G1 (Gauss-Jordan), A(K+1..K+3, K) -> Pa[3], A(K, K+1..K+3) -> Pb[3], Lh -> Pl[3]
-// (11 W^2 doubles).
+//   G0, G1 (Gauss-Jordan), A(K+1..K+2, K) -> Pa[2], A(K, K+1..K+2) -> Pb[2], Lh -> Pl[2],
+//   Uh -> Pu[2] (10 W^2 doubles).
+// The blocks at distance 3, A(K+3, K) and A(K, K+3), are diagonal (the stencil reaches three
+// rows only straight up and down) and no elimination step updates them (a step K' updates
+// blocks within distance 3 of K' on both sides).  So Lh(K+3, K) = diag(dA) S^-1 and
+// Uh(K, K+3) = S^-1 diag(dB) are scalings of S^-1, and the Schur terms that involve them are
+// scalings too: 8 dense W x W products per step instead of 15.
 template <typename T, int WMAX>
 __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restrict__ cc, double* __restrict__ work,
                                                        T* __restrict__ fac, int* __restrict__ flag, LuBox b,
@@ -220,8 +225,9 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
     double* G0 = lds;
     double* G1 = lds + WW;
     double* Pa = lds + 2 * WW;
-    double* Pb = lds + 5 * WW;
-    double* Pl = lds + 8 * WW;
+    double* Pb = lds + 4 * WW;
+    double* Pl = lds + 6 * WW;
+    double* Pu = lds + 8 * WW;
     const int k = blockIdx.x;
     const int ox = (k % b.subx) * b.ownx - b.ov, oy = (k / b.subx) * b.owny - b.ov;
     double* win = work + (long)k * 16 * WW;
@@ -231,6 +237,7 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
     const int ntile = nq * nq;
     __shared__ LdsStencil sst;
     __shared__ double cring[8 * 72];        // c along the box rows entering the window
+    __shared__ double dA[WMAX], dB[WMAX];   // diagonals of A(K+3, K) and A(K, K+3)
     stage_stencil(&sst, b, st);
     for (int J = 0; J < 5 && J < H; ++J) load_c_row(cring, J, b, cc, ox, oy);
     __syncthreads();
@@ -242,53 +249,65 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
 
     for (int K = 0; K < H; ++K) {
         const int nI = min(3, H - 1 - K);
+        const int nd = min(nI, 2);          // dense neighbour blocks on each side
         T* rowK = out + (long)K * 7 * WW;
         for (int e = tid; e < WW; e += nt) G0[e] = slot(win, K, K, W)[e];
-        for (int e = tid; e < nI * WW; e += nt) {
+        for (int e = tid; e < nd * WW; e += nt) {
             const int bi = e / WW, r = e - bi * WW;
             Pa[bi * WW + r] = slot(win, K + 1 + bi, K, W)[r];
             Pb[bi * WW + r] = slot(win, K, K + 1 + bi, W)[r];
         }
+        if (nI == 3)
+            for (int q = tid; q < W; q += nt) {
+                dA[q] = slot(win, K + 3, K, W)[q * W + q];
+                dB[q] = slot(win, K, K + 3, W)[q * W + q];
+            }
         __syncthreads();
         const double* Sinv = gauss_jordan(G0, G1, W, flag);
-        // Lh(I,K) = A(I,K) S^-1 -> Pl (LDS); Uh(K,J) = S^-1 A(K,J) -> stored negated
-        for (int t = tid; t < 2 * nI * ntile; t += nt) {
+        // Lh(I,K) = A(I,K) S^-1 -> Pl and Uh(K,J) = S^-1 A(K,J) -> Pu, I, J = K+1, K+2
+        for (int t = tid; t < 2 * nd * ntile; t += nt) {
             const int blk = t / ntile, tile = t - blk * ntile;
             double acc[4][4];
             int p0, q0;
-            if (blk < nI) {
+            double* dst;
+            if (blk < nd) {
                 tile_product<WMAX>(Pa + blk * WW, Sinv, W, tile, acc, &p0, &q0);
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        if (p0 + a < W && q0 + c < W) Pl[blk * WW + (p0 + a) * W + q0 + c] = acc[a][c];
+                dst = Pl + blk * WW;
             } else {
-                const int bj = blk - nI;
-                tile_product<WMAX>(Sinv, Pb + bj * WW, W, tile, acc, &p0, &q0);
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        if (p0 + a < W && q0 + c < W)
-                            rowK[4 * WW + bj * WW + (q0 + c) * W + p0 + a] = (T)(-acc[a][c]);
+                tile_product<WMAX>(Sinv, Pb + (blk - nd) * WW, W, tile, acc, &p0, &q0);
+                dst = Pu + (blk - nd) * WW;
             }
-        }
-        // S^-1 of block row K; zero Uh blocks past the box and Lh blocks before it
-        for (int e = tid; e < WW; e += nt) {          // e = q * W + p: coalesced column-major stores
-            const int q = e / W, p = e - q * W;
-            rowK[3 * WW + e] = (T)Sinv[p * W + q];
-            for (int bj = nI; bj < 3; ++bj) rowK[4 * WW + bj * WW + e] = (T)0.0;
-            if (K < 3)
-                for (int cb = 0; cb < 3 - K; ++cb) rowK[cb * WW + e] = (T)0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (p0 + a < W && q0 + c < W) dst[(p0 + a) * W + q0 + c] = acc[a][c];
         }
         __syncthreads();
-        // Schur complement A(I,J) -= Lh(I,K) A(K,J); the C tile is loaded before the product
-        // so that its global-memory latency overlaps the LDS work
-        const int nsch = nI * nI * ntile;
+        // block row K: S^-1 and -Uh(K, K+1..K+3) (zero past the box; Lh blocks before it zero);
+        // Lh(K+1..K+3, K) into column block 2 - bi of the rows below.  e = q * W + p: coalesced
+        // column-major stores.
+        for (int e = tid; e < WW; e += nt) {
+            const int q = e / W, p = e - q * W, rm = p * W + q;
+            const double sv = Sinv[rm];
+            rowK[3 * WW + e] = (T)sv;
+            for (int bj = 0; bj < 3; ++bj) {
+                const double u = bj < nd ? Pu[bj * WW + rm] : (bj < nI ? sv * dB[q] : 0.0);
+                rowK[4 * WW + bj * WW + e] = (T)(-u);
+            }
+            if (K < 3)
+                for (int cb = 0; cb < 3 - K; ++cb) rowK[cb * WW + e] = (T)0.0;
+            for (int bi = 0; bi < nI; ++bi) {
+                const double l = bi < nd ? Pl[bi * WW + rm] : dA[p] * sv;
+                out[(long)(K + 1 + bi) * 7 * WW + (2 - bi) * WW + e] = (T)l;
+            }
+        }
+        // Schur complement A(I,J) -= Lh(I,K) A(K,J): dense for I, J = K+1, K+2 (the C tile is
+        // loaded before the product so that its global-memory latency overlaps the LDS work) ...
+        const int nsch = nd * nd * ntile;
         for (int t = tid; t < nsch; t += nt) {
             const int blk = t / ntile, tile = t - blk * ntile;
-            const int bi = blk / nI, bj = blk - bi * nI;
+            const int bi = blk / nd, bj = blk - bi * nd;
             const int tp = 4 * (tile / nq), tq = 4 * (tile - (tile / nq) * nq);
             double* C = slot(win, K + 1 + bi, K + 1 + bj, W);
             double cv[4][4];
@@ -305,12 +324,25 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
                 for (int c = 0; c < 4; ++c)
                     if (p0 + a < W && q0 + c < W) C[(p0 + a) * W + q0 + c] = cv[a][c] - acc[a][c];
         }
-        // Lh(I, K) of the rows below: column block K - I + 3 of their panel
-        for (int e = tid; e < nI * WW; e += nt) {
-            const int bi = e / WW, r = e - bi * WW;
-            const int q = r / W, p = r - q * W;
-            out[(long)(K + 1 + bi) * 7 * WW + (2 - bi) * WW + r] = (T)Pl[bi * WW + p * W + q];
-        }
+        // ... and scalings where a distance-3 block takes part:
+        //   A(I, K+3) -= Lh(I,K) diag(dB), A(K+3, J) -= diag(dA) Uh(K,J), A(K+3, K+3) -= diag(dA) S^-1 diag(dB)
+        if (nI == 3)
+            for (int e = tid; e < 5 * WW; e += nt) {
+                const int c5 = e / WW, rm = e - c5 * WW, p = rm / W, q = rm - p * W;
+                double* C;
+                double v;
+                if (c5 < 2) {
+                    C = slot(win, K + 1 + c5, K + 3, W);
+                    v = Pl[c5 * WW + rm] * dB[q];
+                } else if (c5 < 4) {
+                    C = slot(win, K + 3, K + c5 - 1, W);
+                    v = dA[p] * Pu[(c5 - 2) * WW + rm];
+                } else {
+                    C = slot(win, K + 3, K + 3, W);
+                    v = dA[p] * Sinv[rm] * dB[q];
+                }
+                C[rm] -= v;
+            }
         __syncthreads();
         // slide the window: block row and column K + 4 enter
         const int N4 = K + 4;
@@ -387,7 +419,9 @@ __device__ void gemm_cols(double* C, const double* A, const double* __restrict__
 }
 
 // Wider boxes (kSmallW < W <= 72): Gauss-Jordan in LDS, panels in the global workspace
-// (blocks 16..21), the A(K, J) blocks staged into LDS for the Schur update (3 W^2 doubles).
+// (blocks 16..21), the A(K, J) blocks staged into LDS for the Schur update (2 W^2 doubles).
+// As in k_lu_factor_lds, the diagonal blocks at distance 3 make their panels and Schur terms
+// scalings, formed elementwise.
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict__ cc, double* __restrict__ work,
                                                         T* __restrict__ fac, int* __restrict__ flag, LuBox b,
@@ -401,6 +435,7 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
     const int tid = threadIdx.x, nt = blockDim.x;
     __shared__ LdsStencil sst;
     __shared__ double cring[8 * 72];        // c along the box rows entering the window
+    __shared__ double dA[72], dB[72];       // diagonals of A(K+3, K) and A(K, K+3)
     stage_stencil(&sst, b, st);
     for (int J = 0; J < 5 && J < H; ++J) load_c_row(cring, J, b, cc, ox, oy);
     __syncthreads();
@@ -412,37 +447,62 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
 
     for (int K = 0; K < H; ++K) {
         const int nI = min(3, H - 1 - K);
+        const int nd = min(nI, 2);
         T* rowK = out + (long)K * 7 * WW;
         for (int e = tid; e < WW; e += nt) lds[e] = slot(win, K, K, W)[e];
+        if (nI == 3)
+            for (int q = tid; q < W; q += nt) {
+                dA[q] = slot(win, K + 3, K, W)[q * W + q];
+                dB[q] = slot(win, K, K + 3, W)[q * W + q];
+            }
         __syncthreads();
         const double* Sinv = gauss_jordan(lds, lds + WW, W, flag);
-        // Lh(I,K) = A(I,K) S^-1 -> blocks 16+bi; Uh(K,J) = S^-1 A(K,J) -> blocks 19+bj
-        for (int bi = 0; bi < nI; ++bi)
+        // Lh(I,K) = A(I,K) S^-1 -> blocks 16+bi; Uh(K,J) = S^-1 A(K,J) -> blocks 19+bj (I, J = K+1, K+2)
+        for (int bi = 0; bi < nd; ++bi)
             gemm_rows<24>(win + (long)(16 + bi) * WW, slot(win, K + 1 + bi, K, W), Sinv, W, 1.0, false);
-        for (int bj = 0; bj < nI; ++bj)
+        for (int bj = 0; bj < nd; ++bj)
             gemm_cols<24>(win + (long)(19 + bj) * WW, Sinv, slot(win, K, K + 1 + bj, W), W);
+        // S^-1 of block row K and, while S^-1 is in LDS, the distance-3 scalings:
+        // Lh(K+3,K) = diag(dA) S^-1, Uh(K,K+3) = S^-1 diag(dB), A(K+3,K+3) -= diag(dA) S^-1 diag(dB)
         for (int e = tid; e < WW; e += nt) {
-            const int q = e / W, p = e - q * W;
-            rowK[3 * WW + e] = (T)Sinv[p * W + q];
+            const int q = e / W, p = e - q * W, rm = p * W + q;
+            const double sv = Sinv[rm];
+            rowK[3 * WW + e] = (T)sv;
+            if (nI == 3) {
+                out[(long)(K + 3) * 7 * WW + e] = (T)(dA[p] * sv);
+                rowK[6 * WW + e] = (T)(-(sv * dB[q]));
+                slot(win, K + 3, K + 3, W)[rm] -= dA[p] * sv * dB[q];
+            }
         }
         __syncthreads();
-        double* As = lds;                // S^-1 is done: stage A(K, K+1..K+3) for the Schur update
-        for (int e = tid; e < nI * WW; e += nt) {
+        double* As = lds;                // S^-1 is done: stage A(K, K+1..K+2) for the Schur update
+        for (int e = tid; e < nd * WW; e += nt) {
             const int bj = e / WW, r = e - bj * WW;
             As[e] = slot(win, K, K + 1 + bj, W)[r];
         }
         __syncthreads();
-        for (int bi = 0; bi < nI; ++bi)
-            for (int bj = 0; bj < nI; ++bj)
+        for (int bi = 0; bi < nd; ++bi)
+            for (int bj = 0; bj < nd; ++bj)
                 gemm_rows<24>(slot(win, K + 1 + bi, K + 1 + bj, W), win + (long)(16 + bi) * WW, As + (long)bj * WW,
                               W, -1.0, true);
+        // A(I, K+3) -= Lh(I,K) diag(dB) and A(K+3, J) -= diag(dA) Uh(K,J), I, J = K+1, K+2
+        if (nI == 3)
+            for (int e = tid; e < 4 * WW; e += nt) {
+                const int c4 = e / WW, rm = e - c4 * WW, p = rm / W, q = rm - p * W;
+                if (c4 < 2)
+                    slot(win, K + 1 + c4, K + 3, W)[rm] -= win[(long)(16 + c4) * WW + rm] * dB[q];
+                else
+                    slot(win, K + 3, K + c4 - 1, W)[rm] -= dA[p] * win[(long)(19 + c4 - 2) * WW + rm];
+            }
         for (int e = tid; e < WW; e += nt) {
             const int q = e / W, p = e - q * W, rm = p * W + q;
-            for (int bj = 0; bj < 3; ++bj)
-                rowK[4 * WW + bj * WW + e] = (T)(bj < nI ? -win[(long)(19 + bj) * WW + rm] : 0.0);
+            for (int bj = 0; bj < 3; ++bj) {
+                if (bj < nd) rowK[4 * WW + bj * WW + e] = (T)(-win[(long)(19 + bj) * WW + rm]);
+                else if (bj >= nI) rowK[4 * WW + bj * WW + e] = (T)0.0;
+            }
             if (K < 3)
                 for (int cb = 0; cb < 3 - K; ++cb) rowK[cb * WW + e] = (T)0.0;
-            for (int bi = 0; bi < nI; ++bi)
+            for (int bi = 0; bi < nd; ++bi)
                 out[(long)(K + 1 + bi) * 7 * WW + (2 - bi) * WW + e] = (T)win[(long)(16 + bi) * WW + rm];
         }
         __syncthreads();
@@ -623,7 +683,7 @@ hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b
 
 }  // namespace
 
-size_t lu_factor_lds_bytes(int W) { return sizeof(double) * (W <= kSmallW ? 11 : 3) * (size_t)W * W; }
+size_t lu_factor_lds_bytes(int W) { return sizeof(double) * (W <= kSmallW ? 10 : 2) * (size_t)W * W; }
 
 size_t lu_work_blocks(int W) { return W <= kSmallW ? 16 : 22; }
 

@@ -39,7 +39,9 @@ struct IlukPlan {
     int maxrow = 0;              // longest row of the pattern
     int nfl = 0;                 // dependency levels of the factorisation (= forward levels)
     int npass_f = 0, npass_b = 0;
-    long nlanes = 0;             // lane slots of all passes (four values each)
+    long nlanes = 0;             // lane slots of all passes (epl values each)
+    int maxseg = 1;              // most lanes one row takes in a pass
+    int epl = 4;                 // entries per lane slot, 4 or 8
     int* d_rowptr = nullptr;     // [n + 1]
     uint16_t* d_col = nullptr;   // [nnz] local column
     int8_t* d_sten = nullptr;    // [nnz] stencil offset index, or -1 for a fill entry
@@ -172,8 +174,12 @@ struct Vec4Of {
     using type = T __attribute__((ext_vector_type(4)));
 };
 
-// PF passes in flight; forward passes first, then backward, in execution order.
-template <typename T, int PF>
+// PF passes in flight; forward passes first, then backward, in execution order.  A lane slot
+// holds EPL (4 or 8) consecutive entries of one row.  MAXSEG bounds the lanes of one row (a
+// power of two >= the widest row's), so a row's first lane issues all of its partial-sum reads
+// at once and adds them in lane order.  The pass table entry of the next fetch is read one
+// fetch ahead, so the factor loads of a pass never wait for it.
+template <typename T, int PF, int MAXSEG, int EPL>
 __global__ __launch_bounds__(64) void k_iluk_apply(const double* __restrict__ r, double* __restrict__ z,
                                                    const T* __restrict__ fac, const int2* __restrict__ pass,
                                                    const uint32_t* __restrict__ meta,
@@ -182,6 +188,7 @@ __global__ __launch_bounds__(64) void k_iluk_apply(const double* __restrict__ r,
                                                    double* __restrict__ zbox) {
     using V = typename Vec4Of<T>::type;
     using C4 = unsigned short __attribute__((ext_vector_type(4)));
+    constexpr int NV = EPL / 4;
     extern __shared__ unsigned char smem_raw[];
     T* x = reinterpret_cast<T*>(smem_raw);
     __shared__ T part[64];
@@ -198,44 +205,59 @@ __global__ __launch_bounds__(64) void k_iluk_apply(const double* __restrict__ r,
     if (tid == 0) x[b.n] = (T)0;   // spare slot: the column of every padding value
     const V* F = reinterpret_cast<const V*>(fac + (long)k * nvals);
     const C4* AC = reinterpret_cast<const C4*>(acol);
-    V f[PF];
-    C4 cl[PF];
+    int2 ps_next = pass[0];
+    V f[PF][NV];
+    C4 cl[PF][NV];
     uint32_t mt[PF];
     int used[PF];
     auto fetch = [&](int p, int j) {
-        const int q = min(max(p, 0), npass - 1);
-        const int2 ps = pass[q];
+        const int2 ps = ps_next;                      // entry of pass min(p, npass - 1)
+        ps_next = pass[min(p + 1, npass - 1)];
         const long slot = ps.x + min(tid, ps.y - 1);
-        used[j] = (p >= 0 && p < npass) ? ps.y : 0;
-        f[j] = __builtin_nontemporal_load(&F[slot]);
-        cl[j] = AC[slot];
+        used[j] = p < npass ? ps.y : 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            f[j][v] = __builtin_nontemporal_load(&F[slot * NV + v]);
+            cl[j][v] = AC[slot * NV + v];
+        }
         mt[j] = meta[slot];
     };
 #pragma unroll
     for (int j = 0; j < PF; ++j) {   // the first round computes on zeros against slot 0
-        f[j] = V{};
-        cl[j] = C4{0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            f[j][v] = V{};
+            cl[j][v] = C4{0, 0, 0, 0};
+        }
         mt[j] = 0u;
         used[j] = 0;
     }
     wave_order();
-    // the first round only fetches (passes -PF..-1), so the loop is entered with no loads in flight
+    // the first round only fetches (passes -PF..-1 compute nothing), so the loop is entered with
+    // no factor loads in flight
     for (int p0 = -PF; p0 < npass; p0 += PF) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int p = p0 + j;
-            const T prod = f[j][0] * x[cl[j][0]] + f[j][1] * x[cl[j][1]] + f[j][2] * x[cl[j][2]] +
-                           f[j][3] * x[cl[j][3]];
+            T prod = (T)0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                prod += f[j][v][0] * x[cl[j][v][0]] + f[j][v][1] * x[cl[j][v][1]] + f[j][v][2] * x[cl[j][v][2]] +
+                        f[j][v][3] * x[cl[j][v][3]];
             part[tid] = prod;
             wave_order();
             const int lanes = (int)(mt[j] >> 16);
             if (tid < used[j] && lanes > 0) {
+                T pv[MAXSEG];
+#pragma unroll
+                for (int u = 0; u < MAXSEG; ++u) pv[u] = part[min(tid + u, 63)];
                 T s = (T)0;
-                for (int u = 0; u < lanes; ++u) s += part[tid + u];
+#pragma unroll
+                for (int u = 0; u < MAXSEG; ++u) s += u < lanes ? pv[u] : (T)0;
                 const int i = (int)(mt[j] & 0xFFFFu);
                 // forward: x_i = r_i - sum_j l_ij x_j (unit lower factor); backward: slot 0 holds
                 // 1/u_ii against the zero slot, x_i = (x_i - sum_j u_ij x_j) / u_ii
-                x[i] = p < npass_f ? x[i] - s : (x[i] - s) * f[j][0];
+                x[i] = p < npass_f ? x[i] - s : (x[i] - s) * f[j][0][0];
             }
             wave_order();
             fetch(p + PF, j);
@@ -278,6 +300,8 @@ struct HostPlan {
     std::vector<uint16_t> acol;
     std::vector<int> src;
     int npass_f = 0, npass_b = 0;
+    int maxseg = 1;
+    int epl = 4;                 // entries per lane slot
 };
 
 // Rows of one triangle packed into passes by dependency level.  entries(i) lists the source
@@ -302,16 +326,18 @@ void pack_passes(const std::vector<std::vector<int>>& levels, Entries entries, H
             cols.clear();
             entries(i, &codes, &cols);
             if (codes.empty()) continue;
-            const int lanes = ((int)codes.size() + 3) / 4;
+            const int E = hp->epl;
+            const int lanes = ((int)codes.size() + E - 1) / E;
             if (lanes > 64) {
                 *ok = false;
                 return;
             }
             if (lanes_used + lanes > 64) flush();
+            hp->maxseg = std::max(hp->maxseg, lanes);
             for (int l = 0; l < lanes; ++l) {
                 hp->meta.push_back(l == 0 ? ((uint32_t)i | ((uint32_t)lanes << 16)) : 0u);
-                for (int e = 0; e < 4; ++e) {
-                    const int q = 4 * l + e;
+                for (int e = 0; e < E; ++e) {
+                    const int q = E * l + e;
                     hp->src.push_back(q < (int)codes.size() ? codes[q] : -1);
                     hp->acol.push_back((uint16_t)(q < (int)codes.size() ? cols[q] : hp->n));
                 }
@@ -424,6 +450,11 @@ bool build_host_plan(int ex, int ey, int ez, const StencilTable& st, int level, 
         for (int i : v) hp->frow.push_back((uint16_t)i);
         hp->flev.push_back((int)hp->frow.size());
     }
+    // entries per lane: four, or eight when a row would need more than 64 lanes of four
+    int longest = 0;
+    for (int i = 0; i < n; ++i)
+        longest = std::max({longest, (int)hp->diag[i], hp->rowptr[i + 1] - hp->rowptr[i] - hp->diag[i]});
+    hp->epl = longest > 256 ? 8 : 4;
     bool ok = true;
     pack_passes(F, [&](int i, std::vector<int>* codes, std::vector<int>* cols) {
         for (int p = hp->rowptr[i]; p < hp->rowptr[i] + hp->diag[i]; ++p) {
@@ -442,7 +473,7 @@ bool build_host_plan(int ex, int ey, int ez, const StencilTable& st, int level, 
             }
         }, hp, &hp->npass_b, &ok);
     if (!ok) {
-        *err = "ILU(k) row longer than 256 entries";
+        *err = "ILU(k) row longer than 512 entries";
         return false;
     }
     return true;
@@ -510,6 +541,8 @@ pfc_status iluk_plan_create(pfc_ctx* c, int level, std::string* err) {
     p->npass_f = hp.npass_f;
     p->npass_b = hp.npass_b;
     p->nlanes = (long)hp.meta.size();
+    p->maxseg = hp.maxseg;
+    p->epl = hp.epl;
     bool ok = upload(&p->d_rowptr, hp.rowptr) == hipSuccess && upload(&p->d_col, hp.col) == hipSuccess &&
               upload(&p->d_sten, hp.sten) == hipSuccess && upload(&p->d_diag, hp.diag) == hipSuccess &&
               upload(&p->d_flev, hp.flev) == hipSuccess && upload(&p->d_frow, hp.frow) == hipSuccess &&
@@ -522,7 +555,7 @@ pfc_status iluk_plan_create(pfc_ctx* c, int level, std::string* err) {
         return PFC_ENOMEM;
     }
     c->iluk = p;
-    c->fac_elems = (size_t)c->dec.nsub * 4 * p->nlanes;
+    c->fac_elems = (size_t)c->dec.nsub * p->epl * p->nlanes;
     return PFC_OK;
 }
 
@@ -531,14 +564,14 @@ void iluk_plan_stats(const IlukPlan* p, long* nnz, int* fac_levels, int* passes_
     *fac_levels = p->nfl;
     *passes_f = p->npass_f;
     *passes_b = p->npass_b;
-    *slots = 4 * p->nlanes;
+    *slots = (long)p->epl * p->nlanes;
 }
 
 hipError_t launch_iluk_factor(pfc_ctx* c, const StencilTable& st) {
     const IlukPlan* p = c->iluk;
     const KBox b = make_kbox(c);
     const size_t sh = factor_lds_bytes(p->n, p->maxrow);
-    const long nvals = 4 * p->nlanes;
+    const long nvals = (long)p->epl * p->nlanes;
     if (c->opts.precond_fp32)
         hipLaunchKernelGGL(k_iluk_factor<float>, dim3(c->dec.nsub), dim3(64), sh, c->stream, c->d_c, p->d_rowptr,
                            p->d_col, p->d_sten, p->d_diag, p->d_flev, p->d_frow, p->nfl, p->d_src, nvals, p->d_W,
@@ -550,29 +583,56 @@ hipError_t launch_iluk_factor(pfc_ctx* c, const StencilTable& st) {
     return hipGetLastError();
 }
 
-hipError_t launch_iluk_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {
+template <typename T, int MAXSEG, int EPL>
+hipError_t launch_iluk_apply_t(pfc_ctx* c, const double* r, double* z, double* sum_part) {
     const IlukPlan* p = c->iluk;
     const KBox b = make_kbox(c);
-    const long nvals = 4 * p->nlanes;
-    const int npass = p->npass_f + p->npass_b;
-    if (c->opts.precond_fp32)
-        return launch_k(c, k_iluk_apply<float, kApplyPF>, dim3(c->dec.nsub), dim3(64), sizeof(float) * (p->n + 1),
-                        r, z, (const float*)c->d_fac, (const int2*)p->d_pass, (const uint32_t*)p->d_meta,
-                        (const uint16_t*)p->d_acol, p->npass_f, npass, nvals, b, sum_part, c->opts.ras_kind,
-                        c->d_zbox);
-    return launch_k(c, k_iluk_apply<double, kApplyPF>, dim3(c->dec.nsub), dim3(64), sizeof(double) * (p->n + 1), r,
-                    z, (const double*)c->d_fac, (const int2*)p->d_pass, (const uint32_t*)p->d_meta,
-                    (const uint16_t*)p->d_acol, p->npass_f, npass, nvals, b, sum_part, c->opts.ras_kind, c->d_zbox);
+    return launch_k(c, k_iluk_apply<T, kApplyPF, MAXSEG, EPL>, dim3(c->dec.nsub), dim3(64), sizeof(T) * (p->n + 1),
+                    r, z, (const T*)c->d_fac, (const int2*)p->d_pass, (const uint32_t*)p->d_meta,
+                    (const uint16_t*)p->d_acol, p->npass_f, p->npass_f + p->npass_b, (long)EPL * p->nlanes, b,
+                    sum_part, c->opts.ras_kind, c->d_zbox);
 }
 
-hipError_t set_iluk_lds_limits() {
-    const void* fs[] = {(const void*)k_iluk_factor<float>, (const void*)k_iluk_factor<double>,
-                        (const void*)k_iluk_apply<float, kApplyPF>, (const void*)k_iluk_apply<double, kApplyPF>};
+template <typename T, int EPL>
+hipError_t launch_iluk_apply_e(pfc_ctx* c, const double* r, double* z, double* sum_part) {
+    const int m = c->iluk->maxseg;
+    if (m <= 4) return launch_iluk_apply_t<T, 4, EPL>(c, r, z, sum_part);
+    if (m <= 8) return launch_iluk_apply_t<T, 8, EPL>(c, r, z, sum_part);
+    if (m <= 16) return launch_iluk_apply_t<T, 16, EPL>(c, r, z, sum_part);
+    if (m <= 32) return launch_iluk_apply_t<T, 32, EPL>(c, r, z, sum_part);
+    return launch_iluk_apply_t<T, 64, EPL>(c, r, z, sum_part);
+}
+
+template <typename T>
+hipError_t launch_iluk_apply_s(pfc_ctx* c, const double* r, double* z, double* sum_part) {
+    return c->iluk->epl == 8 ? launch_iluk_apply_e<T, 8>(c, r, z, sum_part) : launch_iluk_apply_e<T, 4>(c, r, z, sum_part);
+}
+
+hipError_t launch_iluk_apply(pfc_ctx* c, const double* r, double* z, double* sum_part) {
+    return c->opts.precond_fp32 ? launch_iluk_apply_s<float>(c, r, z, sum_part)
+                                : launch_iluk_apply_s<double>(c, r, z, sum_part);
+}
+
+template <typename T, int EPL>
+hipError_t set_apply_limits() {
+    const void* fs[] = {(const void*)k_iluk_apply<T, kApplyPF, 4, EPL>, (const void*)k_iluk_apply<T, kApplyPF, 8, EPL>,
+                        (const void*)k_iluk_apply<T, kApplyPF, 16, EPL>, (const void*)k_iluk_apply<T, kApplyPF, 32, EPL>,
+                        (const void*)k_iluk_apply<T, kApplyPF, 64, EPL>};
     for (const void* f : fs) {
         const hipError_t e = set_dynamic_lds_limit(f);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t set_iluk_lds_limits() {
+    hipError_t e = set_dynamic_lds_limit((const void*)k_iluk_factor<float>);
+    if (e == hipSuccess) e = set_dynamic_lds_limit((const void*)k_iluk_factor<double>);
+    if (e == hipSuccess) e = set_apply_limits<float, 4>();
+    if (e == hipSuccess) e = set_apply_limits<float, 8>();
+    if (e == hipSuccess) e = set_apply_limits<double, 4>();
+    if (e == hipSuccess) e = set_apply_limits<double, 8>();
+    return e;
 }
 
 }  // namespace pfc

@@ -148,3 +148,28 @@ def test_iluk_options_are_checked():
         pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, sub_solver="ilu9")
     with pytest.raises(pfc.PfcError):     # boxes of 41 x 40 x 40 = 65600 cells are refused
         pfc.Solver((64, 64, 66), (64.0, 64.0, 66.0), 0.56, (2, 2, 2), 4, sub_solver="ilu1")
+
+
+def test_ras_iluk3_3d_rows_longer_than_256_entries():
+    """ILU(3) on 10^3 boxes (4^3 owned, overlap 3): rows reach 594 entries, so the apply packs
+    eight entries per lane.  One box against the oracle, FP64 and FP32 factors."""
+    pfc = _pfc()
+    shape, L = (16, 16, 16), (16.0, 16.0, 16.0)
+    h = S.spacing(shape, L)
+    g = np.random.default_rng(37)
+    phi = -0.2 + 0.05 * g.uniform(-1, 1, shape)
+    Phi = phi + 0.01 * g.standard_normal(shape)
+    r = g.standard_normal(shape)
+    J = S.jacobian_csr(Phi, phi, 0.1, 0.56, h)
+    d = W.decompose(shape, (4, 4, 4), 3)[21]
+    rows = W.iluk(W.subdomain_matrix(J, d), W.subdomain_pattern(d.ext_n), 3)
+    assert max(len(rw) for rw in rows) > 2 * 256
+    idx = d.ext_global_indices()
+    own = d.owned_mask_local()
+    y = W.ilu0_solve(rows, r.ravel()[idx])
+    for fp32, tol in ((False, 1e-11), (True, 1e-4)):
+        s = pfc.Solver(shape, L, 0.56, (4, 4, 4), 3, sub_solver="ilu3", mass_project=False, precond_fp32=fp32)
+        s.ras_setup(T(Phi), T(phi), 0.1)
+        z = N(s.ras_apply(T(r))).ravel()
+        assert rel(z[idx[own]], y[own]) < tol
+        s.close()

@@ -96,7 +96,8 @@ typedef struct {
     int timing;                       /* bitmask of the launches timed with events (pfc_kernel_time):
                                          1 preconditioner apply, 2 residual, 4 Jacobian action,
                                          8 factorisation; 0 off */
-    int precond_lag;                  /* 0: factor at the first Newton step of every time step (the
+    int precond_lag;                  /* -1: factor at every Newton step (Table 1's columns without
+                                         reuse); 0: factor at the first Newton step of every time step (the
                                          paper's reuse); L > 0: pfc_step keeps the factors for up to L
                                          time steps while dt stays within 20% of the dt they were built
                                          with and GMRES iterations per Newton step stay at most twice

@@ -121,3 +121,52 @@ def table2_study(shape=(256, 256), lengths=(128.0, 128.0), gamma=0.025, phi0=Non
         if log:
             log(f"table2 {row}")
     return rows
+
+
+def table1_study(shape=(256, 256), lengths=(128.0, 128.0), gamma=0.025, phi0=None, sub=(4, 4), steps=10, dt=0.01,
+                 solvers=("ilu0", "ilu1", "ilu2", "lu"), reuse_solver="ilu0", delta=1, ras_kind="as", fp32=False,
+                 newton_maxit=50, log=None):
+    """The subdomain-solver study of the paper's Table 1 on this library: classical AS with
+    overlap delta (3 delta mesh layers), the first ``steps`` fixed steps of ``dt`` from ``phi0``
+    (default: test A's field) with the tolerances of Sec. 5.  Each solver in ``solvers`` is
+    factored at every Newton step (the table's plain columns); ``reuse_solver`` is also run with
+    its factors built once per time step (the table's reuse column).  Returns rows with Newton
+    iterations, GMRES iterations per Newton step and seconds ("error" when a solve fails, the
+    table's n/c)."""
+    import torch
+
+    if phi0 is None:
+        import pfc_inputs as I
+        phi0 = torch.from_numpy(I.noise_ic(shape, 0.07, 0.07, 0)).cuda()
+    runs = [(name, -1) for name in solvers] + [(reuse_solver, 0)]
+    rows = []
+    for name, lag in runs:
+        row = {"sub_solver": name, "reuse": lag == 0, "ras_kind": ras_kind, "delta": delta}
+        try:
+            s = Solver(shape, lengths, gamma, sub, 3 * delta, sub_solver=name, precond_fp32=fp32, guess="previous",
+                       dt_min=dt, dt_max=dt, newton_rtol=1e-8, newton_atol=1e-10, lin_rtol=1e-3, lin_atol=1e-11,
+                       mass_project=False, ras_kind=ras_kind, precond_lag=lag, newton_maxit=newton_maxit,
+                       max_retries=0)
+        except (PfcError, ValueError) as e:
+            row["error"] = str(e)
+            rows.append(row)
+            continue
+        try:
+            phi = phi0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            newton = gmres = 0
+            for _ in range(steps):
+                st = s.step(phi)
+                newton += st["newton_its"]
+                gmres += st["gmres_its"]
+            torch.cuda.synchronize()
+            row.update(newton=newton, gmres_per_newton=gmres / max(newton, 1), seconds=time.perf_counter() - t0)
+        except PfcError as e:
+            row["error"] = str(e)
+        finally:
+            s.close()
+        rows.append(row)
+        if log:
+            log(f"table1 {row}")
+    return rows

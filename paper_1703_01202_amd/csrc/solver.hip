@@ -482,8 +482,8 @@ pfc_status newton_impl(pfc_ctx* c, const double* phi, double dt, pfc_step_stats*
     st->ls_cuts = 0;
     bool factored = reuse;                          // lagged factors of an earlier step
     for (int it = 0; it < c->opts.newton_maxit && fn > target; ++it) {
-        if (!factored) {
-            CHK(setup_impl(c, c->d_X, phi, dt));    // factor once per solve, reuse afterwards
+        if (!factored || c->opts.precond_lag < 0) {
+            CHK(setup_impl(c, c->d_X, phi, dt));    // factor once per solve (or at every iteration), reuse afterwards
             factored = true;
         } else {
             HIPCHK(launch_coef(c, c->d_X, phi, c->d_c));
@@ -660,7 +660,7 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     if (s == PFC_OK && op->overlap < 0) s = bad("negative overlap");
     if (s == PFC_OK && (op->gmres_restart < 1 || op->gmres_restart > 60)) s = bad("gmres_restart must be 1..60");
     if (s == PFC_OK && (op->gmres_maxit < 1 || op->newton_maxit < 1)) s = bad("iteration limits must be >= 1");
-    if (s == PFC_OK && op->precond_lag < 0) s = bad("precond_lag must be >= 0");
+    if (s == PFC_OK && op->precond_lag < -1) s = bad("precond_lag must be >= -1");
     if (s == PFC_OK && op->use_graph && !stream) s = bad("use_graph needs a non-default stream (graph capture)");
     if (s == PFC_OK && (op->ras_kind < PFC_RAS_LEFT || op->ras_kind > PFC_RAS_RIGHT)) s = bad("unknown ras_kind");
     if (s == PFC_OK && op->ras_kind != PFC_RAS_LEFT)   // boxes covering a cell, per axis, for the sum

@@ -366,3 +366,29 @@ def test_natural_order_iluk_on_test_b_mesh_size(dt, own, ov, stable_levels):
         else:
             assert piv.min() < 0, k
             assert abs(ev).max() > 1e4, (k, abs(ev).max())
+
+
+@pytest.mark.slow
+def test_natural_order_iluk_on_test_d_mesh_size():
+    """Why test D's production steps (dt 0.5..10) run with ILU(2): on its mesh size, for the same
+    3-D subdomain matrix as the ILU(0) pin above, ILU(2) keeps positive pivots and a
+    preconditioned spectrum near 1 up to dt = 10, while ILU(1) loses them at dt = 10."""
+    import math
+
+    n_own, ov = 4, 3
+    hv = 80 * math.pi / 256
+    shape = (4 * n_own,) * 3
+    h = S.spacing(shape, (hv * shape[0],) * 3)
+    phi = np.full(shape, -0.35)
+    dom = W.decompose(shape, (4, 4, 4), ov)[0]
+    A = W.subdomain_matrix_zero_ring(phi, phi, 10.0, 0.35, h, dom)
+    pat = W.subdomain_pattern(dom.ext_n)
+    for k, stable in ((1, False), (2, True)):
+        rows = W.iluk(A, pat, k)
+        piv = np.array([r[i] for i, r in enumerate(rows)])
+        L, U = W.ilu0_dense_factors(rows)
+        ev = np.linalg.eigvals(np.linalg.solve(U, np.linalg.solve(L, A)))
+        if stable:
+            assert piv.min() > 0 and 0.5 < ev.real.min() and abs(ev).max() < 2, k
+        else:
+            assert piv.min() < 0 and abs(ev).max() > 10, k

@@ -352,3 +352,107 @@ def test_run_dt_history_three_steps():
     assert flat.dts == [0.05, 2.0, 2.0]
     free = S.run(phi0, 2, w.gamma, h, 0.05, 2.0, eta=0.0)
     assert free.dts == [0.05, 2.0]
+
+
+# ---------------------------------------------------------------------------
+# Variable mobility M = 1 - phi^2 and Neumann-type boundary conditions (Sec. 2; Sec. 3,
+# Eq. (12) with M_d at the averaged state; Sec. 5, test B's four variants)
+# ---------------------------------------------------------------------------
+
+VARIANTS = [("periodic", None), ("periodic", S.mobility_one_minus_sq), ("neumann", None),
+            ("neumann", S.mobility_one_minus_sq)]
+
+
+def _pair(shape, seed, amp=0.3):
+    g = np.random.default_rng(seed)
+    phi = -0.2 + amp * g.uniform(-1, 1, shape)
+    return phi + 0.1 * g.standard_normal(shape), phi
+
+
+def _mirror_ext(u):
+    """Even reflection across every upper face: a periodic field on twice the grid whose
+    wrap reproduces the Neumann mirror ghosts of ``u``."""
+    for a in range(u.ndim):
+        u = np.concatenate([u, np.flip(u, axis=a)], axis=a)
+    return u
+
+
+@pytest.mark.parametrize("bc,mob", VARIANTS)
+def test_jacobian_complex_step_all_variants(bc, mob):
+    shape, h, gam, dt = (9, 11), (0.7, 0.9), 0.3, 0.37
+    Phi, phi = _pair(shape, 11)
+    v = np.random.default_rng(12).standard_normal(shape)
+    cs = S.residual(Phi + 1e-30j * v, phi, dt, gam, h, mobility=mob, bc=bc).imag / 1e-30
+    scale = np.abs(cs).max()
+    assert np.abs(S.jv(Phi, phi, dt, gam, h, v, mobility=mob, bc=bc) - cs).max() <= 1e-14 * scale
+    J = S.jacobian_csr(Phi, phi, dt, gam, h, mobility=mob, bc=bc)
+    assert np.abs(J @ v.ravel() - cs.ravel()).max() <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("mob", [None, S.mobility_one_minus_sq])
+def test_neumann_equals_periodic_on_the_mirror_extended_grid(mob):
+    """The Neumann mirror ghosts are what a periodic grid of twice the size gives for the even
+    reflection of the field, so every Neumann quantity is the periodic one restricted."""
+    shape, h, gam, dt = (7, 10), (0.8, 0.6), 0.25, 0.5
+    Phi, phi = _pair(shape, 13)
+    F = S.residual(Phi, phi, dt, gam, h, mobility=mob, bc="neumann")
+    Fe = S.residual(_mirror_ext(Phi), _mirror_ext(phi), dt, gam, h, mobility=mob)
+    np.testing.assert_allclose(F, Fe[:7, :10], rtol=0, atol=1e-12 * np.abs(F).max())
+    v = np.random.default_rng(14).standard_normal(shape)
+    Jv = S.jv(Phi, phi, dt, gam, h, v, mobility=mob, bc="neumann")
+    Jve = S.jv(_mirror_ext(Phi), _mirror_ext(phi), dt, gam, h, _mirror_ext(v), mobility=mob)
+    np.testing.assert_allclose(Jv, Jve[:7, :10], rtol=0, atol=1e-12 * np.abs(Jv).max())
+    E = S.free_energy(phi, gam, h, "neumann")
+    assert abs(4.0 * E - S.free_energy(_mirror_ext(phi), gam, h)) <= 1e-12 * abs(E)
+
+
+def test_neumann_laplacian_spectrum_is_the_cosine_symbol():
+    """Under the mirror ghosts Delta_d is diagonalised by the cosines cos(pi k (i + 1/2) / n),
+    eigenvalue -(4/h^2) sin^2(pi k / (2n)) per axis."""
+    shape, h = (6, 9), (0.7, 1.3)
+    L = S.laplacian_matrix(shape, h, "neumann").toarray()
+    lam = [(4.0 / h[a] ** 2) * np.sin(np.pi * np.arange(shape[a]) / (2 * shape[a])) ** 2 for a in range(2)]
+    expect = np.sort(-(lam[0][:, None] + lam[1][None, :]).ravel())
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(L)), expect, atol=1e-12 * np.abs(expect).max())
+
+
+@pytest.mark.parametrize("bc,mob", VARIANTS)
+def test_dvd_energy_law_and_mass_all_variants(bc, mob):
+    """For any Phi (not only the root): the DVD identity vol sum(G(Phi) - G(phi)) =
+    vol sum mu (Phi - phi) (Eq. (10)); with it and summation by parts the energy law
+    F(Phi) - F(phi) = dt vol [sum mu F(Phi) - sum_faces M_e (D^+ mu)^2] (Eqs. (14)-(15), here with
+    the mobility on the faces and no flux through Neumann faces); and sum F = sum (Phi - phi)/dt."""
+    shape, h, gam, dt = (10, 12), (0.7, 0.9), 0.3, 0.41
+    Phi, phi = _pair(shape, 15)
+    vol = h[0] * h[1]
+    mu = S.dvd_derivative(Phi, phi, gam, h, bc)
+    dE = S.free_energy(Phi, gam, h, bc) - S.free_energy(phi, gam, h, bc)
+    assert abs(dE - vol * np.sum(mu * (Phi - phi))) <= 1e-12 * abs(dE)
+    F = S.residual(Phi, phi, dt, gam, h, mobility=mob, bc=bc)
+    m = np.ones(shape) if mob is None else mob(0.5 * (Phi + phi))
+    diss = 0.0
+    for a in range(2):
+        n = shape[a]
+        dmu = np.diff(mu, axis=a) if bc == "neumann" else np.roll(mu, -1, axis=a) - mu
+        me = 0.5 * (np.take(m, range(n - 1), axis=a) + np.take(m, range(1, n), axis=a)) if bc == "neumann" \
+            else 0.5 * (m + np.roll(m, -1, axis=a))
+        diss += np.sum(me * dmu ** 2) / h[a] ** 2
+    rhs = dt * vol * (np.sum(mu * F) - diss)
+    assert abs(dE - rhs) <= 1e-11 * max(abs(dE), 1.0)
+    assert abs(np.sum(F) - np.sum(Phi - phi) / dt) <= 1e-12 * np.abs(Phi - phi).sum() / dt
+
+
+@pytest.mark.parametrize("bc,mob", VARIANTS)
+def test_newton_root_and_short_run_all_variants(bc, mob):
+    """Newton with the exact Jacobian converges quadratically to the rounding floor for all
+    four variants of test B (Sec. 5); over a short run the energy does not increase and the
+    mass is kept."""
+    shape = (16, 16)
+    L = (16 * 400.0 / 1024,) * 2
+    h = S.spacing(shape, L)
+    phi = I.noise_ic(shape, -0.285, 0.1, 3)
+    res = S.newton_solve(phi, 0.1, 0.25, h, mobility=mob, bc=bc)
+    assert res.converged and res.res_norms[-1] < 1e-9
+    tr = S.run(phi, 3, 0.25, h, 0.1, 0.1, mobility=mob, bc=bc)
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(tr.energies, tr.energies[1:]))
+    assert max(abs(m - tr.masses[0]) for m in tr.masses) <= 1e-12 * abs(tr.masses[0])

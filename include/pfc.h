@@ -61,10 +61,21 @@ typedef struct {
     double L[3];
 } pfc_grid;
 
-/* Model (Sec. 2, Eq. (1)): gamma is the quench depth; mobility 0 means M = 1. */
+/* Model (Sec. 2, Eq. (1)): gamma is the quench depth.
+ * mobility: PFC_MOBILITY_1 (M = 1) or PFC_MOBILITY_1_MINUS_SQ (M(phi) = 1 - phi^2, taken at the
+ *   averaged state (Phi + phi)/2 as Eq. (12) says, on a face as the mean of its two cells, Sec. 3).
+ * boundary: PFC_BC_PERIODIC or PFC_BC_NEUMANN, the Neumann-type conditions of Sec. 2 read as zero
+ *   normal differences: the ghost cell beyond a boundary face mirrors the cell inside it, for
+ *   every field a difference operator acts on (so no flux crosses the boundary and mass is kept).
+ * With a variable mobility or Neumann boundaries the residual, Jacobian action and energy are
+ * exact; the Schwarz subdomain matrices stay those of M = 1 with periodic box gathers (a
+ * preconditioner only: flexible GMRES converges to the same root). */
+enum { PFC_MOBILITY_1 = 0, PFC_MOBILITY_1_MINUS_SQ = 1 };
+enum { PFC_BC_PERIODIC = 0, PFC_BC_NEUMANN = 1 };
 typedef struct {
     double gamma;
     int mobility;
+    int boundary;
 } pfc_model;
 
 /* Schwarz preconditioners (Sec. 4): left-RAS (Eq. (23)): restrict with overlap, extend the owned
@@ -218,7 +229,7 @@ pfc_status pfc_checkpoint_load(pfc_ctx* ctx, double* phi, const char* path);
 /* The residual of pfc_residual (same kernel, bitwise the same F and norm) without a context
  * and without allocating: for callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc).  2-D grids only (PFC_EUNSUP for
- * dim 3, whose residual needs two grid-sized work vectors); mobility must be 0; n >= 8 per
+ * dim 3, whose residual needs two grid-sized work vectors); M = 1 and periodic; n >= 8 per
  * axis, dt > 0, F aliasing neither input (PFC_EINVAL otherwise).  Phi, phi, src (nullable), F:
  * device FP64 [ny][nx]; stream: hipStream_t (NULL = default).  The kernel's per-block partial
  * sums of ||F||^2 (at most 1024) go to a fixed 8 KiB device array of the library, one per GPU,

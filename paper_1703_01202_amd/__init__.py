@@ -25,7 +25,8 @@ def _ptr(t):
 def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precond_fp32=False, dt_min=0.1,
              dt_max=None, eta=0.0, newton_rtol=1e-8, newton_atol=1e-10, lin_rtol=1e-3, lin_atol=1e-11,
              gmres_restart=30, gmres_maxit=300, newton_maxit=50, guess="previous", mass_project=True,
-             max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True, use_graph=False, ras_kind="left"):
+             max_retries=4, timing=False, precond_lag=0, newton_rel_ref=True, use_graph=False, ras_kind="left",
+             mobility="1", boundary="periodic"):
     """pfc_grid, pfc_model and pfc_opts for a grid given in array-axis order."""
     shape = tuple(int(s) for s in shape)
     dim = len(shape)
@@ -41,7 +42,8 @@ def _structs(lib, shape, lengths, gamma, sub, overlap, sub_solver="ilu0", precon
         g.L[a] = revL[a] if a < dim else 1.0
     m = _lib.PfcModel()
     m.gamma = float(gamma)
-    m.mobility = 0
+    m.mobility = _lib.MOBILITY[mobility]
+    m.boundary = _lib.BOUNDARY[boundary]
     o = _lib.PfcOpts()
     lib.pfc_default_opts(ctypes.byref(o))
     o.newton_rtol, o.newton_atol = newton_rtol, newton_atol
@@ -82,7 +84,8 @@ class Solver:
         ("previous" | "extrap" | "learned"), mass_project, max_retries, timing (True, or the
         bitmask of pfc_opts.timing), precond_lag,
         newton_rel_ref, use_graph (needs ``stream``: a non-default stream handle), ras_kind
-        ("left" | "as" | "right": left-RAS, classical AS, right-RAS)."""
+        ("left" | "as" | "right": left-RAS, classical AS, right-RAS), mobility ("1" | "1-phi^2"),
+        boundary ("periodic" | "neumann")."""
         import torch
         self._torch = torch
         self.lib = _lib.load()

@@ -40,7 +40,11 @@ class PfcGrid(ctypes.Structure):
 
 
 class PfcModel(ctypes.Structure):
-    _fields_ = [("gamma", ctypes.c_double), ("mobility", ctypes.c_int)]
+    _fields_ = [("gamma", ctypes.c_double), ("mobility", ctypes.c_int), ("boundary", ctypes.c_int)]
+
+
+MOBILITY = {"1": 0, "1-phi^2": 1}
+BOUNDARY = {"periodic": 0, "neumann": 1}
 
 
 class PfcOpts(ctypes.Structure):

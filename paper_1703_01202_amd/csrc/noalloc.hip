@@ -46,7 +46,8 @@ extern "C" pfc_status pfc_residual_noalloc(const pfc_grid* g, const pfc_model* m
                                            double* norm2, void* stream) {
     if (!g || !m || !Phi || !phi || !F || !(dt > 0) || F == Phi || F == phi) return PFC_EINVAL;
     if (g->dim == 3) return PFC_EUNSUP;
-    if (g->dim != 2 || g->n[0] < 8 || g->n[1] < 8 || !(g->L[0] > 0) || !(g->L[1] > 0) || m->mobility != 0)
+    if (g->dim != 2 || g->n[0] < 8 || g->n[1] < 8 || !(g->L[0] > 0) || !(g->L[1] > 0) || m->mobility != 0 ||
+        m->boundary != 0)
         return PFC_EINVAL;
     const int nx = g->n[0], ny = g->n[1];
     const int blocks = pfc::residual2d_blocks(nx, ny);

@@ -116,7 +116,9 @@ struct pfc_ctx {
     double* d_V = nullptr;             // (restart+1) * N
     double* d_Z = nullptr;             // restart * N
     double* d_prev = nullptr;          // phi^(n-1) for extrapolation
-    double* d_tmp3 = nullptr;          // 3-D multi-pass temporaries (2 * N)
+    double* d_tmp3 = nullptr;          // multi-pass temporaries (2 * N): 3-D, variable mobility, Neumann
+    double* d_u = nullptr;             // variable mobility: u = (Phi + phi)/2 of the iterate ...
+    double* d_mu = nullptr;            // ... and its mu_d, for the Jacobian action
 
     // reductions
     double* d_part = nullptr;          // partials summed on the device (Gram-Schmidt, apply sums)
@@ -188,6 +190,7 @@ inline hipError_t set_dynamic_lds_limit(const void* f) {
 
 // ---- stencil kernels (stencil.hip) ----
 // Reductions leave per-block partials (device_reduce.h); partial_count gives their number.
+bool fused2d(const pfc_ctx* c);                 // 2-D, M = 1, periodic: the single-kernel stencils
 int residual_partial_count(const pfc_ctx* c);   // blocks of the residual kernel
 // The 2-D residual kernel outside a context: grid nx x ny with 1/h^2 per axis, on stream s;
 // writes residual2d_blocks(nx, ny) (at most 1024) partial sums of F^2 to norm_part.

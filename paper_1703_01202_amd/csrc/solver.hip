@@ -168,7 +168,7 @@ pfc_status shift_by_sum(pfc_ctx* c, double* x, const double* y, double scale) {
 pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* src,
                          double* F, double* nrm) {
     int ts;
-    timer_begin(c, 1, &ts, c->g.dim == 2);
+    timer_begin(c, 1, &ts, fused2d(c));
     HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_hpin + SC_P : nullptr, nullptr));
     timer_end(c, ts);
     if (!nrm) return PFC_OK;
@@ -184,7 +184,7 @@ pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, doubl
 pfc_status jv_impl(pfc_ctx* c, const double* v, double dt, const double* shift_part, double* shift_out,
                    double* out) {
     int ts;
-    timer_begin(c, 2, &ts, c->g.dim == 2);
+    timer_begin(c, 2, &ts, fused2d(c));
     HIPCHK(launch_jv(c, v, c->d_c, dt, shift_part, c->dec.nsub, 1.0 / (double)c->g.N, shift_out, out));
     timer_end(c, ts);
     return PFC_OK;
@@ -542,7 +542,7 @@ pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
 }
 
 void free_all(pfc_ctx* c) {
-    void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_work, c->d_fac, c->d_flag, c->d_c,
+    void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_work, c->d_fac, c->d_flag, c->d_c, c->d_u, c->d_mu,
                     c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
                     c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.a, c->d_zbox};
     for (void* p : ptrs)
@@ -647,7 +647,9 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     pfc_status s = PFC_OK;
     const int dim = gr->dim;
     if (dim != 2 && dim != 3) s = bad("dim must be 2 or 3");
-    if (s == PFC_OK && md->mobility != 0) s = bad("only mobility M = 1 is built");
+    if (s == PFC_OK && md->mobility != PFC_MOBILITY_1 && md->mobility != PFC_MOBILITY_1_MINUS_SQ)
+        s = bad("unknown mobility");
+    if (s == PFC_OK && md->boundary != PFC_BC_PERIODIC && md->boundary != PFC_BC_NEUMANN) s = bad("unknown boundary");
     for (int a = 0; s == PFC_OK && a < dim; ++a) {
         if (gr->n[a] < 8) s = bad("grid extent below 8");
         else if (!(gr->L[a] > 0)) s = bad("domain length must be positive");
@@ -742,7 +744,12 @@ pfc_status pfc_create(const pfc_grid* gr, const pfc_model* md, const pfc_opts* o
     A(dalloc(c, &c->d_prev, N));
     A(dalloc(c, &c->d_V, (size_t)(m + 1) * N));
     A(dalloc(c, &c->d_Z, (size_t)m * N));
-    if (dim == 3) A(dalloc(c, &c->d_tmp3, 2 * (size_t)N));
+    if (dim == 3 || md->mobility != PFC_MOBILITY_1 || md->boundary != PFC_BC_PERIODIC)
+        A(dalloc(c, &c->d_tmp3, 2 * (size_t)N));
+    if (md->mobility == PFC_MOBILITY_1_MINUS_SQ) {
+        A(dalloc(c, &c->d_u, N));
+        A(dalloc(c, &c->d_mu, N));
+    }
     A(dalloc(c, &c->d_part, 128 * (size_t)kRedBlocks + 64 * (size_t)c->dec.nsub));
     c->n_scal = SC_P + std::max({kRedBlocks, 3 * residual_partial_count(c), 2 * energy_partial_count(c)});
     A(dalloc(c, &c->d_scal, (size_t)c->n_scal));

@@ -25,6 +25,8 @@ struct P {
     int nx, ny, nz;
     double ihx2, ihy2, ihz2;
     double gamma, inv_dt;
+    int neu;   // Neumann-type boundaries: the ghost beyond a face mirrors the cell inside it
+    int mob;   // variable mobility M(u) = 1 - u^2, u = (Phi + phi)/2
 };
 
 __device__ __forceinline__ int wrap(int i, int n) {
@@ -252,19 +254,42 @@ __global__ __launch_bounds__(NT) void k_energy2d(const double* __restrict__ phi,
 // Generic N-d multi-pass kernels (3-D; also valid for 2-D with nz = 1)
 // ---------------------------------------------------------------------------
 
+// Neighbour index i + 1 / i - 1 along an axis of n cells: periodic wrap, or the mirror ghost
+// (the cell itself) of the Neumann-type boundaries.
+__device__ __forceinline__ int nxt(int i, int n, int neu) { return i + 1 < n ? i + 1 : (neu ? i : 0); }
+__device__ __forceinline__ int prv(int i, int n, int neu) { return i > 0 ? i - 1 : (neu ? i : n - 1); }
+
 __device__ __forceinline__ double lap7(const double* __restrict__ a, int x, int y, int z, const P& p) {
     const long sxy = (long)p.nx * p.ny;
     const long c = z * sxy + (long)y * p.nx + x;
     const double ac = a[c];
-    const int xp = x + 1 == p.nx ? 0 : x + 1, xm = x == 0 ? p.nx - 1 : x - 1;
-    const int yp = y + 1 == p.ny ? 0 : y + 1, ym = y == 0 ? p.ny - 1 : y - 1;
+    const int xp = nxt(x, p.nx, p.neu), xm = prv(x, p.nx, p.neu);
+    const int yp = nxt(y, p.ny, p.neu), ym = prv(y, p.ny, p.neu);
     const long row = z * sxy + (long)y * p.nx;
     double r = (a[row + xp] + a[row + xm] - 2.0 * ac) * p.ihx2 +
                (a[z * sxy + (long)yp * p.nx + x] + a[z * sxy + (long)ym * p.nx + x] - 2.0 * ac) * p.ihy2;
     if (p.nz > 1) {
-        const int zp = z + 1 == p.nz ? 0 : z + 1, zm = z == 0 ? p.nz - 1 : z - 1;
+        const int zp = nxt(z, p.nz, p.neu), zm = prv(z, p.nz, p.neu);
         r += (a[zp * sxy + (long)y * p.nx + x] + a[zm * sxy + (long)y * p.nx + x] - 2.0 * ac) * p.ihz2;
     }
+    return r;
+}
+
+// nabla_d . M nabla_d g at cell (x, y, z) with the face mobility the mean of the node values
+// (Sec. 3); node mobilities from mfun(i).  A Neumann face has a zero difference, so no flux.
+template <typename MF>
+__device__ __forceinline__ double div_m_grad(const double* __restrict__ g, MF mfun, int x, int y, int z, const P& p) {
+    const long sxy = (long)p.nx * p.ny;
+    const long c = z * sxy + (long)y * p.nx + x;
+    const double gc = g[c], mc = mfun(c);
+    auto face = [&](long j) { return 0.5 * (mc + mfun(j)) * (g[j] - gc); };
+    const long row = z * sxy + (long)y * p.nx;
+    double r = (face(row + nxt(x, p.nx, p.neu)) + face(row + prv(x, p.nx, p.neu))) * p.ihx2 +
+               (face(z * sxy + (long)nxt(y, p.ny, p.neu) * p.nx + x) + face(z * sxy + (long)prv(y, p.ny, p.neu) * p.nx + x)) *
+                   p.ihy2;
+    if (p.nz > 1)
+        r += (face(nxt(z, p.nz, p.neu) * sxy + (long)y * p.nx + x) + face(prv(z, p.nz, p.neu) * sxy + (long)y * p.nx + x)) *
+             p.ihz2;
     return r;
 }
 
@@ -325,6 +350,32 @@ __global__ void k_mp_final(const double* a, const double* __restrict__ b,
     out[i] = f;
 }
 
+// The last pass with the variable mobility M(u) = 1 - u^2.  Residual (jv = 0, a = Phi, b = phi,
+// m = mu): F = (Phi - phi)/dt - nabla . M nabla mu - src, u = (Phi + phi)/2 at each node.
+// Jacobian action (jv = 1, a = v, m = the inner operator w, u and mu of the iterate given):
+// out = v/dt - nabla . M nabla w - nabla . (M'(u) v / 2) nabla mu, M'(u) v / 2 = -u v.
+// a is read at the cell itself only, so out may be a.
+__global__ void k_mp_final_mob(const double* a, const double* __restrict__ b, const double* __restrict__ m,
+                               const double* __restrict__ src, int jv, const double* __restrict__ u,
+                               const double* __restrict__ mu, double* out, P p) {
+    MP_INDEX
+    if (!jv) {
+        auto mob = [&](long j) {
+            const double uj = 0.5 * (a[j] + b[j]);
+            return 1.0 - uj * uj;
+        };
+        double f = (a[i] - b[i]) * p.inv_dt - div_m_grad(m, mob, x, y, z, p);
+        if (src) f -= src[i];
+        out[i] = f;
+    } else {
+        auto mob = [&](long j) { return 1.0 - u[j] * u[j]; };
+        auto dmob = [&](long j) { return -u[j] * a[j]; };
+        const double t1 = div_m_grad(m, mob, x, y, z, p);
+        const double t2 = div_m_grad(mu, dmob, x, y, z, p);
+        out[i] = a[i] * p.inv_dt - t1 - t2;
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_mp_energy(const double* __restrict__ phi,
                                                   double* __restrict__ part, P p) {
     __shared__ double red[NT / 64];
@@ -334,14 +385,14 @@ __global__ __launch_bounds__(NT) void k_mp_energy(const double* __restrict__ phi
     for (long i = blockIdx.x * (long)NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
         const int x = (int)(i % p.nx), y = (int)((i / p.nx) % p.ny), z = (int)(i / sxy);
         const double f = phi[i];
-        const int xp = x + 1 == p.nx ? 0 : x + 1, xm = x == 0 ? p.nx - 1 : x - 1;
-        const int yp = y + 1 == p.ny ? 0 : y + 1, ym = y == 0 ? p.ny - 1 : y - 1;
+        const int xp = nxt(x, p.nx, p.neu), xm = prv(x, p.nx, p.neu);
+        const int yp = nxt(y, p.ny, p.neu), ym = prv(y, p.ny, p.neu);
         const double dxp = phi[z * sxy + (long)y * p.nx + xp] - f, dxm = f - phi[z * sxy + (long)y * p.nx + xm];
         const double dyp = phi[z * sxy + (long)yp * p.nx + x] - f, dym = f - phi[z * sxy + (long)ym * p.nx + x];
         double lap = (dxp - dxm) * p.ihx2 + (dyp - dym) * p.ihy2;
         double grad = (dxp * dxp + dxm * dxm) * p.ihx2 + (dyp * dyp + dym * dym) * p.ihy2;
         if (p.nz > 1) {
-            const int zp = z + 1 == p.nz ? 0 : z + 1, zm = z == 0 ? p.nz - 1 : z - 1;
+            const int zp = nxt(z, p.nz, p.neu), zm = prv(z, p.nz, p.neu);
             const double dzp = phi[zp * sxy + (long)y * p.nx + x] - f, dzm = f - phi[zm * sxy + (long)y * p.nx + x];
             lap += (dzp - dzm) * p.ihz2;
             grad += (dzp * dzp + dzm * dzm) * p.ihz2;
@@ -382,6 +433,8 @@ P make_params(const pfc_ctx* c, double dt) {
     p.ihz2 = c->g.ihz2;
     p.gamma = c->model.gamma;
     p.inv_dt = dt > 0 ? 1.0 / dt : 0.0;
+    p.neu = c->model.boundary == PFC_BC_NEUMANN;
+    p.mob = c->model.mobility == PFC_MOBILITY_1_MINUS_SQ;
     return p;
 }
 
@@ -395,14 +448,18 @@ dim3 mp_grid(const pfc_ctx* c) { return dim3((c->g.nx + 63) / 64, (c->g.ny + 3) 
 
 }  // namespace
 
-int residual_partial_count(const pfc_ctx* c) { return c->g.dim == 2 ? (int)residual_grid(c).x : kRedBlocks; }
+bool fused2d(const pfc_ctx* c) {
+    return c->g.dim == 2 && c->model.mobility == PFC_MOBILITY_1 && c->model.boundary == PFC_BC_PERIODIC;
+}
 
-int energy_partial_count(const pfc_ctx* c) { return c->g.dim == 2 ? (int)tiles2d(c).x : kRedBlocks; }
+int residual_partial_count(const pfc_ctx* c) { return fused2d(c) ? (int)residual_grid(c).x : kRedBlocks; }
+
+int energy_partial_count(const pfc_ctx* c) { return fused2d(c) ? (int)tiles2d(c).x : kRedBlocks; }
 
 hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* phi, double dt,
                            const double* src, double* F, double* norm_part, double* xnorm_part) {
     const P p = make_params(c, dt);
-    if (c->g.dim == 2) {
+    if (fused2d(c)) {
         return launch_k(c, k_residual2d, residual_grid(c), dim3(NT), 0, Phi, phi, src, F, norm_part, xnorm_part, p);
     }
     if (xnorm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, Phi, c->g.N, xnorm_part);
@@ -413,20 +470,34 @@ hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* ph
     hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, u, Lu, p);
     // mu replaces u in place (u is read at the cell only); F is then written directly
     hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, Lu, nullptr, 0, u, p);
-    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, src, 0, F, p);
+    if (p.mob)
+        hipLaunchKernelGGL(k_mp_final_mob, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, src, 0, nullptr,
+                           nullptr, F, p);
+    else
+        hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, u, src, 0, F, p);
     if (norm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, F, c->g.N, norm_part);
     return hipGetLastError();
 }
 
 hipError_t launch_coef(const pfc_ctx* c, const double* Phi, const double* phi, double* cbuf) {
     hipLaunchKernelGGL(k_coef, dim3(2048), dim3(256), 0, c->stream, Phi, phi, cbuf, c->g.N);
+    if (c->model.mobility == PFC_MOBILITY_1_MINUS_SQ && cbuf == c->d_c) {
+        // the mobility term of the Jacobian action needs u = (Phi + phi)/2 and mu_d of the iterate
+        const P p = make_params(c, 1.0);
+        double* Lu = c->d_tmp3;
+        hipLaunchKernelGGL(k_mp_combine, dim3(2048), dim3(256), 0, c->stream, Phi, phi, nullptr, 0, 0.0, nullptr, 0,
+                           c->d_u, c->g.N);
+        hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, c->d_u, Lu, p);
+        hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, Phi, phi, c->d_u, Lu, nullptr, 0,
+                           c->d_mu, p);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, double dt, const double* shift_part,
                      int shift_n, double shift_scale, double* shift_out, double* Jv) {
     const P p = make_params(c, dt);
-    if (c->g.dim == 2) {
+    if (fused2d(c)) {
         return launch_k(c, k_jv2d, tiles2d(c), dim3(NT), 0, v, cbuf, shift_part, shift_n, shift_scale, shift_out,
                         Jv, p);
     }
@@ -438,7 +509,11 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
                        shift_scale, shift_out, 1, Jv, c->g.N);
     hipLaunchKernelGGL(k_mp_lap, mp_grid(c), dim3(64, 4), 0, c->stream, Jv, Lu, p);
     hipLaunchKernelGGL(k_mp_inner, mp_grid(c), dim3(64, 4), 0, c->stream, nullptr, nullptr, Jv, Lu, cbuf, 1, w, p);
-    hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Jv, nullptr, w, nullptr, 1, Jv, p);
+    if (p.mob)
+        hipLaunchKernelGGL(k_mp_final_mob, mp_grid(c), dim3(64, 4), 0, c->stream, Jv, nullptr, w, nullptr, 1, c->d_u,
+                           c->d_mu, Jv, p);
+    else
+        hipLaunchKernelGGL(k_mp_final, mp_grid(c), dim3(64, 4), 0, c->stream, Jv, nullptr, w, nullptr, 1, Jv, p);
     return hipGetLastError();
 }
 
@@ -459,6 +534,8 @@ hipError_t launch_residual2d_plain(hipStream_t s, int nx, int ny, double ihx2, d
     p.ihz2 = 0.0;
     p.gamma = gamma;
     p.inv_dt = dt > 0 ? 1.0 / dt : 0.0;
+    p.neu = 0;
+    p.mob = 0;
     hipLaunchKernelGGL(k_residual2d, dim3(residual2d_blocks(nx, ny)), dim3(NT), 0, s, Phi, phi, src, F, norm_part,
                        (double*)nullptr, p);
     return hipGetLastError();
@@ -466,7 +543,7 @@ hipError_t launch_residual2d_plain(hipStream_t s, int nx, int ny, double ihx2, d
 
 hipError_t launch_energy(const pfc_ctx* c, const double* phi, double* part2, double* acc_phi, double* acc_prev) {
     const P p = make_params(c, 0.0);
-    if (c->g.dim == 2) {
+    if (fused2d(c)) {
         hipLaunchKernelGGL(k_energy2d, tiles2d(c), dim3(NT), 0, c->stream, phi, part2, p, acc_phi, acc_prev);
     } else {
         if (acc_phi) {

@@ -57,7 +57,7 @@ def _create(lib, n=(64, 64, 1), sub=(4, 4, 1), overlap=2, dim=2, **kw):
     for a in range(3):
         g.n[a] = n[a]
         g.L[a] = 10.0
-    m = _lib.PfcModel(gamma=0.25, mobility=kw.pop("mobility", 0))
+    m = _lib.PfcModel(gamma=0.25, mobility=kw.pop("mobility", 0), boundary=kw.pop("boundary", 0))
     o = _lib.PfcOpts()
     lib.pfc_default_opts(ctypes.byref(o))
     for a in range(3):
@@ -76,7 +76,11 @@ def _create(lib, n=(64, 64, 1), sub=(4, 4, 1), overlap=2, dim=2, **kw):
     (dict(n=(4, 64, 1)), -1),                   # grid too small
     (dict(gmres_restart=0), -1),
     (dict(gmres_restart=100), -1),
-    (dict(mobility=1), -1),                     # only M = 1 built
+    (dict(mobility=2), -1),                     # M = 1 and M = 1 - phi^2 only
+    (dict(boundary=2), -1),                     # periodic and Neumann-type only
+    (dict(sub_solver=2, ilu_level=5), -1),      # ILU(k) up to k = 4
+    (dict(sub_solver=3), -1),                   # no such subdomain solver
+    (dict(precond_lag=-2), -1),
     (dict(dt_min=0.0), -1),
     (dict(sub_solver=1, dim=3, n=(32, 32, 32), sub=(4, 4, 4)), -8),   # exact LU is 2-D only
     (dict(ras_kind=3), -1),                     # no such Schwarz variant
@@ -107,8 +111,9 @@ def test_opts_struct_size_matches_header():
     from paper_1703_01202_amd import _lib
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "pfc.h"\n'
-           'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(pfc_opts), offsetof(pfc_opts, newton_rel_ref),'
-           ' sizeof(pfc_step_stats), sizeof(pfc_grid)); return 0;}\n')
+           'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pfc_opts), offsetof(pfc_opts, newton_rel_ref),'
+           ' sizeof(pfc_step_stats), sizeof(pfc_grid), sizeof(pfc_model), offsetof(pfc_model, boundary),'
+           ' offsetof(pfc_opts, ilu_level)); return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         cpath, exe = os.path.join(d, "p.c"), os.path.join(d, "p")
         open(cpath, "w").write(src)
@@ -118,6 +123,9 @@ def test_opts_struct_size_matches_header():
     assert int(out[1]) == _lib.PfcOpts.newton_rel_ref.offset
     assert int(out[2]) == ctypes.sizeof(_lib.PfcStepStats)
     assert int(out[3]) == ctypes.sizeof(_lib.PfcGrid)
+    assert int(out[4]) == ctypes.sizeof(_lib.PfcModel)
+    assert int(out[5]) == _lib.PfcModel.boundary.offset
+    assert int(out[6]) == _lib.PfcOpts.ilu_level.offset
 
 
 def test_autotune_box_candidates_tile_the_grid():

@@ -395,6 +395,51 @@ def run_crack(steps):
     return out
 
 
+def run_test_b_variants(steps):
+    """Test B's four variants (Sec. 5: periodic or Neumann-type boundaries, M = 1 or 1 - phi^2) on
+    the 1024^2 crystal workload: FP32 exact-LU RAS on 16 x 64 boxes (overlap 4), extrapolated
+    guess, factors lagged up to 20 steps; the variable-mobility and Neumann residual and Jacobian
+    action run as the multi-pass stencil kernels."""
+    import torch
+    import paper_1703_01202_amd as pfc
+    import pfc_inputs as I
+    out = {}
+    for w in I.test_b_variants():
+        s = pfc.Solver(w.shape, w.lengths, w.gamma, w.sub, w.overlap, sub_solver="lu", precond_fp32=True,
+                       guess="extrap", dt_min=w.dt_min, dt_max=w.dt_max, eta=w.eta, newton_rtol=w.newton_rtol,
+                       newton_atol=w.newton_atol, lin_rtol=w.lin_rtol, lin_atol=w.lin_atol, precond_lag=20,
+                       mobility=w.mobility, boundary=w.boundary)
+        phi = torch.from_numpy(w.initial()).cuda()
+        s.step(phi)   # untimed: first factorisation
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [s.step(phi) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.close()
+        e = [st["energy"] for st in stats]
+        m = [st["mass"] for st in stats]
+        out[w.name] = {"mobility": w.mobility, "boundary": w.boundary, "steps": steps, "steps_per_s": steps / el,
+                       "newton_its": sum(st["newton_its"] for st in stats),
+                       "gmres_its": sum(st["gmres_its"] for st in stats),
+                       "energy_monotone": all(b <= a for a, b in zip(e, e[1:])),
+                       "mass_drift_rel": max(abs(x - m[0]) for x in m) / abs(m[0]), "t_end": stats[-1]["t"]}
+        print(f"[bench] test B variant {w.name}: {steps / el:.1f} steps/s", file=sys.stderr, flush=True)
+    return out
+
+
+def run_table1():
+    """Table 1's test A row (256^2, first 10 steps of dt = 0.01, classical AS delta 1 on 4 x 4
+    boxes): ILU(0), ILU(1), ILU(2), exact LU factored at every Newton step and ILU(0) reused for
+    the whole step."""
+    from paper_1703_01202_amd.autotune import table1_study
+
+    rows = table1_study()
+    for r in rows:
+        print(f"[bench] table1 {r}", file=sys.stderr, flush=True)
+    return rows
+
+
 def run_table2():
     """Table 2's Test A block (256^2, first 10 steps of dt = 0.01, ILU(0), 4 x 4 boxes): Newton and
     GMRES counts and seconds for classical AS delta 0..2 and left/right-RAS delta 1..2."""
@@ -426,6 +471,9 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=LEARNED_TRAINING["epochs"])
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     ap.add_argument("--no-table2", action="store_true", help="skip the Test A preconditioner study (Table 2)")
+    ap.add_argument("--no-table1", action="store_true", help="skip the Test A subdomain-solver study (Table 1)")
+    ap.add_argument("--steps-variants", type=int, default=10,
+                    help="steps of each of test B's four variants at 1024^2 (0 skips them)")
     ap.add_argument("--steps-3d-256", type=int, default=6, help="steps of the 256^3 test-D grid (0 skips it)")
     ap.add_argument("--steps-crack", type=int, default=20, help="steps of the 4096x1024 test-C grid (0 skips it)")
     ap.add_argument("--steps-3d", type=int, default=50)
@@ -470,6 +518,8 @@ def main():
     hbm_ref = None if args.no_hbm_reference else hbm_reference()
     three_d = None if args.no_3d else run_3d(args.steps_3d)
     table2 = None if args.no_table2 else run_table2()
+    table1 = None if args.no_table1 else run_table1()
+    variants = run_test_b_variants(args.steps_variants) if args.steps_variants > 0 else None
     three_d_256 = run_3d_256(args.steps_3d_256) if args.steps_3d_256 > 0 else None
     crack = run_crack(args.steps_crack) if args.steps_crack > 0 else None
     out = {
@@ -512,6 +562,10 @@ def main():
         out["detail"]["hbm_reference"] = hbm_ref
     if table2 is not None:
         out["detail"]["table2_test_a"] = table2
+    if table1 is not None:
+        out["detail"]["table1_test_a"] = table1
+    if variants is not None:
+        out["detail"]["test_b_variants_1024"] = variants
     if three_d_256 is not None:
         out["detail"]["pfc3d_bcc_256"] = three_d_256
     if crack is not None:

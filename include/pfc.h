@@ -217,10 +217,10 @@ pfc_status pfc_reset(pfc_ctx* ctx);
 
 /* Checkpoint: write phi (device) and the time history a restart needs (step count, t,
  * F^n, F^(n-1), dt_(n-1) of Eq. (16), and phi^(n-1) for the extrapolated and learned
- * guesses) to the file at path (binary, little-endian, with the grid and gamma for
+ * guesses) to the file at path (binary, little-endian, with the grid and the model for
  * checking).  Factors are not saved: a restarted run factors at its first step.
  * pfc_checkpoint_load reads such a file into phi (device) and the context; PFC_EINVAL if the
- * file is not a checkpoint of this grid and gamma (the context is then unchanged).  A run
+ * file is not a checkpoint of this grid and model (the context is then unchanged).  A run
  * with precond_lag = 0 continues from a checkpoint exactly as it would have without one.
  * Both synchronise the stream. */
 pfc_status pfc_checkpoint_save(pfc_ctx* ctx, const double* phi, const char* path);

@@ -955,14 +955,15 @@ pfc_status pfc_reset(pfc_ctx* c) {
 namespace {
 // checkpoint file: header, then phi (N doubles) and, if have_prev, phi^(n-1) (N doubles)
 struct CkptHeader {
-    char magic[8];                 // "PFCCKPT1"
+    char magic[8];                 // "PFCCKPT2"
     int32_t dim, n[3];
     double L[3], gamma;
+    int32_t mobility, boundary;
     int64_t step;
     double t, F_n, F_nm1, dt_nm1;
     int32_t have_prev, have_energy;
 };
-const char kMagic[8] = {'P', 'F', 'C', 'C', 'K', 'P', 'T', '1'};
+const char kMagic[8] = {'P', 'F', 'C', 'C', 'K', 'P', 'T', '2'};
 }  // namespace
 
 pfc_status pfc_checkpoint_save(pfc_ctx* c, const double* phi, const char* path) {
@@ -982,6 +983,8 @@ pfc_status pfc_checkpoint_save(pfc_ctx* c, const double* phi, const char* path) 
         h.L[a] = c->grid.L[a];
     }
     h.gamma = c->model.gamma;
+    h.mobility = c->model.mobility;
+    h.boundary = c->model.boundary;
     h.step = c->step;
     h.t = c->t;
     h.F_n = c->F_n;
@@ -1002,7 +1005,8 @@ pfc_status pfc_checkpoint_load(pfc_ctx* c, double* phi, const char* path) {
     if (!f) return fail(c, PFC_EINVAL, std::string("cannot open ") + path);
     CkptHeader h;
     bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.dim == c->grid.dim &&
-              h.gamma == c->model.gamma && (h.have_prev == 0 || h.have_prev == 1);
+              h.gamma == c->model.gamma && h.mobility == c->model.mobility && h.boundary == c->model.boundary &&
+              (h.have_prev == 0 || h.have_prev == 1);
     for (int a = 0; ok && a < 3; ++a) ok = h.n[a] == c->grid.n[a] && h.L[a] == c->grid.L[a];
     const size_t N = (size_t)c->g.N;
     std::vector<double> buf;

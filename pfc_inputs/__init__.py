@@ -158,6 +158,8 @@ class Workload:
     lin_rtol: float = 1e-3
     lin_atol: float = 1e-11
     ic: dict = field(default_factory=dict)
+    mobility: str = "1"             # "1" or "1-phi^2"
+    boundary: str = "periodic"      # "periodic" or "neumann"
 
     def initial(self):
         kind = self.ic["kind"]
@@ -194,6 +196,20 @@ def crystal_growth(n, sub, overlap=4, nsteps=200, seed=1):
     L = 400.0 * n / 1024.0
     return Workload(f"pfc2d_{n}_crystal", (n, n), (L, L), 0.25, 1e-2, 10.0, 5000.0, nsteps,
                     tuple(sub), overlap, ic=dict(kind="hex", mean=-0.285, seed=seed))
+
+
+def test_b_variants(n=1024, nsteps=200):
+    """Test B's four variants (Sec. 5): the crystal-growth field on an n^2 grid of mesh size
+    400/1024 with (a) periodic boundaries, M = 1; (b) Neumann-type boundaries, M = 1;
+    (c) periodic, M = 1 - phi^2; (d) Neumann-type, M = 1 - phi^2."""
+    out = []
+    for tag, mob, bc in (("a", "1", "periodic"), ("b", "1", "neumann"), ("c", "1-phi^2", "periodic"),
+                         ("d", "1-phi^2", "neumann")):
+        w = crystal_growth(n, (16, 64), overlap=4, nsteps=nsteps)
+        w.name = f"pfc2d_{n}_crystal_{tag}"
+        w.mobility, w.boundary = mob, bc
+        out.append(w)
+    return out
 
 
 def crack_4096x1024():

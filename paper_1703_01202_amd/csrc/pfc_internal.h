@@ -37,7 +37,20 @@ struct StencilTable {
     int8_t dx[kMaxStencil], dy[kMaxStencil], dz[kMaxStencil];
     double kconst[kMaxStencil];
     double d1[kMaxStencil];
+    double inv_dt;                     // the 1/dt that kconst holds at the zero offset
 };
+
+// Entry (i, j) of a subdomain matrix, offset s: kconst(s) - d1(s) c_j; with a variable mobility
+// (u = (Phi + phi)/2 given) the spatial part of row i is scaled by the node mobility
+// M_i = 1 - u_i^2 at its cell gi: the subdomain operator freezes M at the row's cell, a
+// preconditioner for nabla . M nabla.
+__host__ __device__ inline double subdomain_entry(const StencilTable& t, int s, double cj, const double* u, long gi) {
+    const double a = t.kconst[s] - t.d1[s] * cj;
+    if (!u) return a;
+    const double m = 1.0 - u[gi] * u[gi];
+    const double d = s == t.diag ? t.inv_dt : 0.0;
+    return d + m * (a - d);
+}
 
 // Overlapping decomposition: equal boxes of own[a] cells, extended by `ov` layers.
 struct Decomp {

@@ -72,6 +72,7 @@ void build_stencil_table(const Geom& g, double gamma, double dt, StencilTable* t
                     kc += 1.0 / dt;
                     t->diag = s;
                 }
+                t->inv_dt = 1.0 / dt;
                 t->kconst[s] = kc;
                 t->d1[s] = k1;
                 ++s;
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ c
                                                     const int* __restrict__ lptr,
                                                     const int* __restrict__ lpts, double* __restrict__ work,
                                                     T* __restrict__ fac, int* __restrict__ flag, Box b,
-                                                    StencilTable st, int nlev) {
+                                                    StencilTable st, int nlev, const double* __restrict__ uu) {
     constexpr int D = S / 2;                  // the zero offset sits in the middle (natural order)
     const int k = blockIdx.x;
     int ox, oy, oz;
@@ -171,10 +172,11 @@ __global__ __launch_bounds__(256) void k_ilu_factor(const double* __restrict__ c
     // assemble A_k row by row
     for (int i = threadIdx.x; i < b.next; i += blockDim.x) {
         const int x = i % b.ex, y = (i / b.ex) % b.ey, z = i / (b.ex * b.ey);
+        const long gi = gidx(b, ox, oy, oz, x, y, z);
         for (int s = 0; s < S; ++s) {
             const int xx = x + kIluPairs<S>.dx[s], yy = y + kIluPairs<S>.dy[s], zz = z + kIluPairs<S>.dz[s];
             double v = 0.0;
-            if (inbox(b, xx, yy, zz)) v = st.kconst[s] - st.d1[s] * cc[gidx(b, ox, oy, oz, xx, yy, zz)];
+            if (inbox(b, xx, yy, zz)) v = subdomain_entry(st, s, cc[gidx(b, ox, oy, oz, xx, yy, zz)], uu, gi);
             W[(long)i * S + s] = v;
         }
     }
@@ -500,10 +502,12 @@ hipError_t launch_ilu_factor_s(pfc_ctx* c, const StencilTable& st, const Box& b)
             return hipErrorInvalidValue;
     if (c->opts.precond_fp32)
         hipLaunchKernelGGL((k_ilu_factor<float, S>), dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c,
-                           c->d_level_ptr, c->d_level_pts, c->d_work, (float*)c->d_fac, c->d_flag, b, st, c->nlev);
+                           c->d_level_ptr, c->d_level_pts, c->d_work, (float*)c->d_fac, c->d_flag, b, st, c->nlev,
+                           (const double*)c->d_u);
     else
         hipLaunchKernelGGL((k_ilu_factor<double, S>), dim3(c->dec.nsub), dim3(256), 0, c->stream, c->d_c,
-                           c->d_level_ptr, c->d_level_pts, c->d_work, (double*)c->d_fac, c->d_flag, b, st, c->nlev);
+                           c->d_level_ptr, c->d_level_pts, c->d_work, (double*)c->d_fac, c->d_flag, b, st, c->nlev,
+                           (const double*)c->d_u);
     return hipGetLastError();
 }
 

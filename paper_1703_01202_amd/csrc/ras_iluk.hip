@@ -105,7 +105,8 @@ __global__ __launch_bounds__(64) void k_iluk_factor(const double* __restrict__ c
                                                     const uint16_t* __restrict__ frow, int nfl,
                                                     const int* __restrict__ src, long nvals, double* __restrict__ W,
                                                     T* __restrict__ fac, int* __restrict__ flag, KBox b,
-                                                    StencilTable st, long nnz, int maxrow) {
+                                                    StencilTable st, long nnz, int maxrow,
+                                                    const double* __restrict__ uu) {
     extern __shared__ unsigned char smem_raw[];
     double* rbuf = reinterpret_cast<double*>(smem_raw);
     short* pmap = reinterpret_cast<short*>(rbuf + kRowsPerWave * maxrow);
@@ -118,11 +119,13 @@ __global__ __launch_bounds__(64) void k_iluk_factor(const double* __restrict__ c
     korigin(b, k, &ox, &oy, &oz);
     double* Wk = W + (long)k * nnz;
     // assemble A_k on the pattern: A(i, j) = kconst(s) - d1(s) c(j) on stencil entries, 0 on fill
-    for (int i = tid; i < b.n; i += 64)
+    for (int i = tid; i < b.n; i += 64) {
+        const long gi = kgidx(b, ox, oy, oz, i);
         for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
             const int s = sten[e];
-            Wk[e] = s >= 0 ? st.kconst[s] - st.d1[s] * cc[kgidx(b, ox, oy, oz, col[e])] : 0.0;
+            Wk[e] = s >= 0 ? subdomain_entry(st, s, cc[kgidx(b, ox, oy, oz, col[e])], uu, gi) : 0.0;
         }
+    }
     for (int j = g; j < mstride; j += kGroup) map[j] = -1;
     __syncthreads();
     for (int lev = 0; lev < nfl; ++lev) {
@@ -575,11 +578,11 @@ hipError_t launch_iluk_factor(pfc_ctx* c, const StencilTable& st) {
     if (c->opts.precond_fp32)
         hipLaunchKernelGGL(k_iluk_factor<float>, dim3(c->dec.nsub), dim3(64), sh, c->stream, c->d_c, p->d_rowptr,
                            p->d_col, p->d_sten, p->d_diag, p->d_flev, p->d_frow, p->nfl, p->d_src, nvals, p->d_W,
-                           (float*)c->d_fac, c->d_flag, b, st, p->nnz, p->maxrow);
+                           (float*)c->d_fac, c->d_flag, b, st, p->nnz, p->maxrow, (const double*)c->d_u);
     else
         hipLaunchKernelGGL(k_iluk_factor<double>, dim3(c->dec.nsub), dim3(64), sh, c->stream, c->d_c, p->d_rowptr,
                            p->d_col, p->d_sten, p->d_diag, p->d_flev, p->d_frow, p->nfl, p->d_src, nvals, p->d_W,
-                           (double*)c->d_fac, c->d_flag, b, st, p->nnz, p->maxrow);
+                           (double*)c->d_fac, c->d_flag, b, st, p->nnz, p->maxrow, (const double*)c->d_u);
     return hipGetLastError();
 }
 

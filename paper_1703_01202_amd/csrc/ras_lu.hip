@@ -57,10 +57,13 @@ __device__ void stage_stencil(LdsStencil* t, const LuBox& b, const StencilTable&
     }
 }
 
-// Block (I, J) of A_k into dst (row-major).  crow holds c along box row J (W values).
+// Block (I, J) of A_k into dst (row-major).  crow holds c along box row J (W values).  With a
+// variable mobility (uu: u = (Phi + phi)/2, else null) the spatial part of row (I, p) is scaled
+// by its node mobility 1 - u^2, as subdomain_entry says.
 __device__ void assemble_block(double* dst, int I, int J, const LuBox& b, const LdsStencil* t,
-                               const double* crow) {
+                               const double* crow, const double* __restrict__ uu, int ox, int oy, double inv_dt) {
     const int W = b.W, dy = J - I;
+    const long grow = (long)wrapg(oy + I, b.ny) * b.nx;
     for (int e = threadIdx.x; e < W * W; e += blockDim.x) {
         const int p = e / W, q = e - p * W;
         const int dx = q - p;
@@ -68,6 +71,11 @@ __device__ void assemble_block(double* dst, int I, int J, const LuBox& b, const 
         if (abs(dx) + abs(dy) <= 3) {
             const int o = (dy + 3) * 7 + dx + 3;
             v = t->k[o] - t->d1[o] * crow[q];
+            if (uu) {
+                const double u = uu[grow + wrapg(ox + p, b.nx)];
+                const double d = o == 24 ? inv_dt : 0.0;
+                v = d + (1.0 - u * u) * (v - d);
+            }
         }
         dst[e] = v;
     }
@@ -219,7 +227,7 @@ __device__ __forceinline__ void tile_product(const double* A, const double* B, i
 template <typename T, int WMAX>
 __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restrict__ cc, double* __restrict__ work,
                                                        T* __restrict__ fac, int* __restrict__ flag, LuBox b,
-                                                       StencilTable st) {
+                                                       StencilTable st, const double* __restrict__ uu) {
     extern __shared__ double lds[];
     const int W = b.W, H = b.H, WW = W * W;
     double* G0 = lds;
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
 
     for (int I = 0; I < 4 && I < H; ++I)
         for (int J = 0; J < 4 && J < H; ++J)
-            assemble_block(slot(win, I, J, W), I, J, b, &sst, cring + (J & 7) * 72);
+            assemble_block(slot(win, I, J, W), I, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy, st.inv_dt);
     __syncthreads();
 
     for (int K = 0; K < H; ++K) {
@@ -347,8 +355,10 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
         // slide the window: block row and column K + 4 enter
         const int N4 = K + 4;
         if (N4 < H) {
-            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72);
-            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72);
+            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy,
+                                                     st.inv_dt);
+            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72, uu, ox, oy,
+                                                     st.inv_dt);
         }
         if (N4 + 1 < H) load_c_row(cring, N4 + 1, b, cc, ox, oy);   // ring slot of row K-3, no longer read
         __syncthreads();
@@ -425,7 +435,7 @@ __device__ void gemm_cols(double* C, const double* A, const double* __restrict__
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict__ cc, double* __restrict__ work,
                                                         T* __restrict__ fac, int* __restrict__ flag, LuBox b,
-                                                        StencilTable st) {
+                                                        StencilTable st, const double* __restrict__ uu) {
     extern __shared__ double lds[];
     const int W = b.W, H = b.H, WW = W * W;
     const int k = blockIdx.x;
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
 
     for (int I = 0; I < 4 && I < H; ++I)
         for (int J = 0; J < 4 && J < H; ++J)
-            assemble_block(slot(win, I, J, W), I, J, b, &sst, cring + (J & 7) * 72);
+            assemble_block(slot(win, I, J, W), I, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy, st.inv_dt);
     __syncthreads();
 
     for (int K = 0; K < H; ++K) {
@@ -508,8 +518,10 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
         __syncthreads();
         const int N4 = K + 4;
         if (N4 < H) {
-            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72);
-            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72);
+            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy,
+                                                     st.inv_dt);
+            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72, uu, ox, oy,
+                                                     st.inv_dt);
         }
         if (N4 + 1 < H) load_c_row(cring, N4 + 1, b, cc, ox, oy);   // ring slot of row K-3, no longer read
         __syncthreads();
@@ -699,24 +711,24 @@ hipError_t launch_lu_factor(pfc_ctx* c, const StencilTable& st) {
     if (b.W <= 24) {
         if (f32)
             hipLaunchKernelGGL((k_lu_factor_lds<float, 24>), grid, blk, sh, c->stream, c->d_c, c->d_work, ff,
-                               c->d_flag, b, st);
+                               c->d_flag, b, st, (const double*)c->d_u);
         else
             hipLaunchKernelGGL((k_lu_factor_lds<double, 24>), grid, blk, sh, c->stream, c->d_c, c->d_work, fd,
-                               c->d_flag, b, st);
+                               c->d_flag, b, st, (const double*)c->d_u);
     } else if (b.W <= kSmallW) {
         if (f32)
             hipLaunchKernelGGL((k_lu_factor_lds<float, kSmallW>), grid, blk, sh, c->stream, c->d_c, c->d_work, ff,
-                               c->d_flag, b, st);
+                               c->d_flag, b, st, (const double*)c->d_u);
         else
             hipLaunchKernelGGL((k_lu_factor_lds<double, kSmallW>), grid, blk, sh, c->stream, c->d_c, c->d_work, fd,
-                               c->d_flag, b, st);
+                               c->d_flag, b, st, (const double*)c->d_u);
     } else {
         if (f32)
             hipLaunchKernelGGL(k_lu_factor_wide<float>, grid, blk, sh, c->stream, c->d_c, c->d_work, ff, c->d_flag,
-                               b, st);
+                               b, st, (const double*)c->d_u);
         else
             hipLaunchKernelGGL(k_lu_factor_wide<double>, grid, blk, sh, c->stream, c->d_c, c->d_work, fd, c->d_flag,
-                               b, st);
+                               b, st, (const double*)c->d_u);
     }
     return hipGetLastError();
 }

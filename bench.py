@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 # they were taken on: the sha256 prefix of the source file must match.
 MEASURED_TRAFFIC = {   # keyed by kernel and decomposition: (kernel, sub, overlap, sub_solver, fp32)
     ("ras_apply", (16, 64), 4, "lu", True): {"file": "paper_1703_01202_amd/csrc/ras_lu.hip",
-                                             "sha": "8652333b345eecd5", "bytes": 1.2245e9},
+                                             "sha": "0c6fee0a91101a9b", "bytes": 1.2246e9},
 }
 
 
@@ -65,8 +65,21 @@ VARIANTS = {
 LEARNED_TRAINING = dict(n=512, trajectories=10, steps=201, epochs=8, lr=3e-3)
 
 
+def apply_bytes_table(shape, sub, overlap, fp32):
+    """Algorithmic HBM bytes of one preconditioner apply by the per-DOF figure of the hot-path
+    table: FP64 factors 208 omega + 8, FP32 factors 108 omega + 8 bytes per DOF (25 stencil
+    factors per extended cell, the gather of r over the extended boxes, the write of z), with
+    omega = extended / owned cells.  This is the ILU(0) apply's byte count; the exact-LU apply
+    the 1024^2 workload runs reads far more (its band factors), see apply_bytes."""
+    ny, nx = shape
+    oy, ox = ny // sub[0], nx // sub[1]
+    omega = (oy + 2 * overlap) * (ox + 2 * overlap) / (oy * ox)
+    return ((108.0 if fp32 else 208.0) * omega + 8.0) * ny * nx
+
+
 def apply_bytes(shape, sub, overlap, sub_solver, fp32):
-    """Algorithmic HBM bytes of one preconditioner apply (factor reads + r gather + z write)."""
+    """Bytes one preconditioner apply of this sub-solver must move (factor reads + r gather +
+    z write): the exact LU's stored band blocks, or the ILU(0) pattern's factors."""
     ny, nx = shape
     esz = 4 if fp32 else 8
     oy, ox = ny // sub[0], nx // sub[1]
@@ -228,10 +241,10 @@ def _run_variant(name, v, steps, warmup, timing, net, net_meta, tuned, stream):
                      "res0_over_ref_median": sorted(guess_ratio)[len(guess_ratio) // 2] if guess_ratio else None}}
     if net_meta is not None:
         res["guess_net"] = net_meta
-    # roofline of the dominant kernel (largest summed event time)
+    # roofline of the dominant kernel (largest summed event time), with the table's per-DOF
+    # bytes; the bytes the sub-solver itself has to stream are reported beside them
     names = {0: "ras_apply", 1: "residual", 2: "jacobian_action", 3: "factorisation"}
-    bytes_per = {0: apply_bytes(w.shape, v["sub"], v["overlap"], v["sub_solver"], v["precond_fp32"]),
-                 1: 24 * N, 2: 24 * N}
+    bytes_per = {0: apply_bytes_table(w.shape, v["sub"], v["overlap"], v["precond_fp32"]), 1: 24 * N, 2: 24 * N}
     if not timing:
         res["roofline"] = None
         return res
@@ -244,6 +257,18 @@ def _run_variant(name, v, steps, warmup, timing, net, net_meta, tuned, stream):
                        "traffic": measured_traffic(v, names[dom]),
                        "bytes_per_launch": bytes_per[dom], "avg_launch_us": avg_s * 1e6, "launches": cnt,
                        "factorisation_ms_total": kt[3][1]}
+    if dom == 0:
+        own = apply_bytes(w.shape, v["sub"], v["overlap"], v["sub_solver"], v["precond_fp32"])
+        res["roofline"].update(
+            bytes_basis=f"{'108' if v['precond_fp32'] else '208'} omega + 8 B/DOF (RAS apply, per-DOF table figure)",
+            subsolver_bytes_per_launch=own, achieved_subsolver_bytes=own / avg_s / 1e9,
+            frac_subsolver_bytes=own / avg_s / 1e9 / PEAK_HBM_GBS)
+    for k in (1, 2):                      # the stencils, when this run timed them
+        if kt[k][0]:
+            sa = kt[k][1] / 1e3 / kt[k][0]
+            res["roofline"].setdefault("stencils", {})[names[k]] = {
+                "bytes_per_launch": 24 * N, "avg_launch_us": sa * 1e6, "achieved": 24 * N / sa / 1e9,
+                "frac": 24 * N / sa / 1e9 / PEAK_HBM_GBS}
     return res
 
 
@@ -516,6 +541,8 @@ def main():
                           net_meta=net_meta, tuned=tuned)
         main_res["kernel_breakdown"] = {"steps": brk["steps"], "steps_per_s_all_kinds_timed": brk["steps_per_s"],
                                         "kernels": brk["kernels"]}
+        if main_res.get("roofline") and brk.get("roofline") and "stencils" in brk["roofline"]:
+            main_res["roofline"]["stencils"] = brk["roofline"]["stencils"]
     graph_res = None
     if not args.no_graph and args.variant == "learned":
         graph_res = run_variant("learned_graph", args.steps, args.warmup, net=net, net_meta=net_meta, tuned=tuned)

@@ -2,11 +2,14 @@
 // coefficient and exact Jacobian action (Sec. 4, Eq. (19)), discrete energy and
 // mass (Sec. 3, Eqs. (7)-(8)).
 //
-// 2-D: one fused kernel per operator.  A 64x16 output tile is staged in LDS with a
-// three-cell periodic halo; the composite radius-3 operator is applied as three
-// successive five-point Laplacians inside LDS (halo 3 -> 2 -> 1 -> 0), so each
-// field is read from HBM once and the result written once.
-// 3-D: three seven-point passes through global memory (L2-resident neighbours).
+// 2-D, M = 1, periodic: one kernel per operator.  On large grids a wave sweeps a strip of
+// columns down a segment of rows; the composite radius-3 operator is three five-point
+// Laplacians applied one row behind each other, row neighbours in registers and column
+// neighbours from the adjacent lanes.  On small grids a block stages a tile with its halo in
+// LDS and applies the three Laplacians there.  Either way each field is read from HBM once
+// and the result written once.
+// 3-D, and 2-D with a variable mobility or Neumann boundaries: seven-point passes through
+// global memory (L2-resident neighbours).
 #include "device_reduce.h"
 #include "pfc_internal.h"
 #include "tiling.h"
@@ -34,6 +37,213 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
+
+
+// ---------------------------------------------------------------------------
+// 2-D sliding-window stencils (M = 1, periodic): one wave sweeps a strip of SW_OUT = 58 columns
+// down a segment of rows.  Each lane holds one column (the strip plus three halo columns on
+// either side); a new input row enters every iteration and the three radius-1 stages of the
+// composite operator follow it one row behind each other, their row neighbours in registers
+// and their column neighbours from the adjacent lanes.  Each field value is read from HBM once
+// per strip (plus the halo columns and the three rows above and below a segment), the result
+// written once, and no LDS pass or barrier stands between the stages.  The input rows are
+// loaded several rows ahead.  Work items (strip, segment) are dealt to the waves in a fixed
+// order, so the per-block partial sums are reproducible.
+// ---------------------------------------------------------------------------
+
+constexpr int SW_OUT = 58;   // output columns per strip (64 lanes minus 3 halo lanes per side)
+constexpr int SW_PF = 4;         // input rows in flight ahead of the sweep
+// Grids of at least this many cells take the sliding sweeps; smaller ones the LDS tiles, whose
+// blocks have every load of a tile in flight at once (a small grid gives the sweeps too few
+// waves to hide their row-by-row latency).
+constexpr long SW_MIN_CELLS = 1L << 21;
+constexpr int SW_WAVES = 4096;   // waves of the largest grid (1024 blocks of NT = 256 threads)
+
+struct SwGeom {
+    int nstrip, seg, nseg, items;
+};
+
+__host__ __device__ inline SwGeom sw_geom(int nx, int ny) {
+    SwGeom g;
+    g.nstrip = (nx + SW_OUT - 1) / SW_OUT;
+    // rows per segment: as short as lets every item have a wave of its own in one round of the
+    // grid (SW_WAVES waves), but at least 16 rows to amortise the 6 warm-up rows
+    const int nseg_max = max(1, SW_WAVES / g.nstrip);
+    g.seg = max(16, (ny + nseg_max - 1) / nseg_max);
+    g.nseg = (ny + g.seg - 1) / g.seg;
+    g.items = g.nstrip * g.nseg;
+    return g;
+}
+
+// The value of the next (dpp 0x130, wave_shl:1) or previous (0x138, wave_shr:1) lane of the
+// wave, moved by the data-parallel primitives of the vector ALU (no LDS round trip); a lane
+// with no such neighbour keeps its own value.
+template <int CTRL>
+__device__ __forceinline__ double lane_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    const int rl = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const int rh = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)rh << 32) | (unsigned int)rl);
+}
+
+// lap along x of a value held one column per lane (lanes at the strip edges get garbage, unused)
+__device__ __forceinline__ double lapx(double v, double ihx2) {
+    return (lane_move<0x130>(v) + lane_move<0x138>(v) - 2.0 * v) * ihx2;
+}
+
+// F = (Phi - phi)/dt - Delta_d mu_d - src with per-block partial sums of F^2 (and Phi^2).
+__global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Phi,
+                                                   const double* __restrict__ phi,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ F,
+                                                   double* __restrict__ part, double* __restrict__ xpart, P p) {
+    __shared__ double red[NT / 64];
+    const SwGeom G = sw_geom(p.nx, p.ny);
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), nwave = gridDim.x * (NT / 64);
+    double acc = 0.0, accx = 0.0;
+    for (int it = wave; it < G.items; it += nwave) {
+        const int strip = it % G.nstrip, sg = it / G.nstrip;
+        const int xo = strip * SW_OUT + lane - 3;                 // this lane's column
+        const int x = wrap(xo, p.nx);
+        const bool out = lane >= 3 && lane < 3 + SW_OUT && xo < p.nx;
+        const int y0 = sg * G.seg, y1 = min(y0 + G.seg, p.ny);
+        // rows y0-3 .. y1+2 enter; F of row r-3 leaves when row r has entered
+        double pa[SW_PF], pb[SW_PF];
+        int yl = wrap(y0 - 3, p.ny);                               // row of the next load
+#pragma unroll
+        for (int k = 0; k < SW_PF; ++k) {
+            const long gi = (long)yl * p.nx + x;
+            pa[k] = Phi[gi];
+            pb[k] = phi[gi];
+            yl = yl + 1 == p.ny ? 0 : yl + 1;
+        }
+        // windows at the top of iteration k (row r = y0 - 3 + k entering):
+        double u0 = 0, u1 = 0;                  // u at rows r-1, r-2
+        double q1 = 0, q2 = 0;                  // q at rows r-1, r-2
+        double l1 = 0, l2 = 0;                  // Lu at rows r-2, r-3
+        double m2 = 0, m3 = 0;                  // mu at rows r-3, r-4
+        double d1 = 0, d2 = 0, d3 = 0;          // Phi - phi at rows r-1, r-2, r-3
+        double a1 = 0, a2 = 0, a3 = 0;          // Phi at rows r-1, r-2, r-3
+        const int nrow = y1 - y0 + 6;
+        // unrolled by SW_PF so that every prefetch slot is a fixed register: a slot is read
+        // only when its row is consumed and refilled right after, so up to SW_PF rows stay in
+        // flight (rotating the slots would read, and so wait for, every pending load)
+        for (int k0 = 0; k0 < nrow; k0 += SW_PF) {
+#pragma unroll
+            for (int j = 0; j < SW_PF; ++j) {
+                const int k = k0 + j;
+                if (k >= nrow) break;
+                const int r = y0 - 3 + k;
+                const double a = pa[j], bb = pb[j];
+                if (k + SW_PF < nrow) {
+                    const long gi = (long)yl * p.nx + x;
+                    pa[j] = Phi[gi];
+                    pb[j] = phi[gi];
+                    yl = yl + 1 == p.ny ? 0 : yl + 1;
+                }
+                const double un = 0.5 * (a + bb);
+                const double qn = 0.25 * (a * a * a + a * a * bb + a * bb * bb + bb * bb * bb);
+                // Lu at row r-1, mu at row r-2, F at row r-3
+                const double ln = lapx(u0, p.ihx2) + (un + u1 - 2.0 * u0) * p.ihy2;
+                const double mn =
+                    (1.0 - p.gamma) * u1 + 2.0 * l1 + lapx(l1, p.ihx2) + (ln + l2 - 2.0 * l1) * p.ihy2 + q2;
+                const double lm = lapx(m2, p.ihx2) + (mn + m3 - 2.0 * m2) * p.ihy2;
+                if (k >= 6 && out) {
+                    double f = d3 * p.inv_dt - lm;
+                    const long gi = (long)(r - 3) * p.nx + xo;
+                    if (src) f -= src[gi];
+                    F[gi] = f;
+                    acc += f * f;
+                    accx += a3 * a3;
+                }
+                // shift the windows by one row
+                m3 = m2; m2 = mn;
+                l2 = l1; l1 = ln;
+                q2 = q1; q1 = qn;
+                u1 = u0; u0 = un;
+                a3 = a2; a2 = a1; a1 = a;
+                d3 = d2; d2 = d1; d1 = a - bb;
+            }
+        }
+    }
+    if (part) {
+        const double s = block_sum_det(acc, red);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    }
+    if (xpart) {
+        const double s = block_sum_det(accx, red);
+        if (threadIdx.x == 0) xpart[blockIdx.x] = s;
+    }
+}
+
+// Jv = v/dt - Delta_d[(1-gamma)/2 v + Delta_d v + 1/2 Delta_d^2 v + c v] with v shifted by -s,
+// s = shift_scale * sum(shift_part[0..shift_n)) when shift_part is given (zero-mean projection
+// fused into the load; every block forms s in the same order and block 0 stores it in
+// *shift_out).
+__global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
+                                             const double* __restrict__ cc,
+                                             const double* __restrict__ shift_part, int shift_n,
+                                             double shift_scale, double* __restrict__ shift_out,
+                                             double* __restrict__ Jv, P p) {
+    __shared__ double red[NT / 64];
+    double sh = 0.0;
+    if (shift_part) {
+        sh = shift_scale * sum_partials_bcast(shift_part, shift_n, red);
+        if (shift_out && threadIdx.x == 0 && blockIdx.x == 0) *shift_out = sh;
+    }
+    const SwGeom G = sw_geom(p.nx, p.ny);
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), nwave = gridDim.x * (NT / 64);
+    for (int it = wave; it < G.items; it += nwave) {
+        const int strip = it % G.nstrip, sg = it / G.nstrip;
+        const int xo = strip * SW_OUT + lane - 3;
+        const int x = wrap(xo, p.nx);
+        const bool out = lane >= 3 && lane < 3 + SW_OUT && xo < p.nx;
+        const int y0 = sg * G.seg, y1 = min(y0 + G.seg, p.ny);
+        double pv[SW_PF], pc[SW_PF];
+        int yl = wrap(y0 - 3, p.ny);                               // row of the next load
+#pragma unroll
+        for (int k = 0; k < SW_PF; ++k) {
+            const long gi = (long)yl * p.nx + x;
+            pv[k] = v[gi];
+            pc[k] = cc[gi];
+            yl = yl + 1 == p.ny ? 0 : yl + 1;
+        }
+        // windows at the top of iteration k (row r = y0 - 3 + k entering):
+        double v0 = 0, v1 = 0, v2 = 0;          // v at rows r-1, r-2, r-3
+        double c1 = 0, c2 = 0;                   // c at rows r-1, r-2
+        double l1 = 0, l2 = 0;                   // Lv at rows r-2, r-3
+        double w2 = 0, w3 = 0;                   // inner operator at rows r-3, r-4
+        const int nrow = y1 - y0 + 6;
+        for (int k0 = 0; k0 < nrow; k0 += SW_PF) {   // unrolled as in k_residual2d
+#pragma unroll
+            for (int j = 0; j < SW_PF; ++j) {
+                const int k = k0 + j;
+                if (k >= nrow) break;
+                const int r = y0 - 3 + k;
+                const double vn = pv[j] - sh, cn = pc[j];
+                if (k + SW_PF < nrow) {
+                    const long gi = (long)yl * p.nx + x;
+                    pv[j] = v[gi];
+                    pc[j] = cc[gi];
+                    yl = yl + 1 == p.ny ? 0 : yl + 1;
+                }
+                const double ln = lapx(v0, p.ihx2) + (vn + v1 - 2.0 * v0) * p.ihy2;
+                const double wn = 0.5 * (1.0 - p.gamma) * v1 + l1 +
+                                  0.5 * (lapx(l1, p.ihx2) + (ln + l2 - 2.0 * l1) * p.ihy2) + c2 * v1;
+                const double lw = lapx(w2, p.ihx2) + (wn + w3 - 2.0 * w2) * p.ihy2;
+                if (k >= 6 && out) Jv[(long)(r - 3) * p.nx + xo] = v2 * p.inv_dt - lw;
+                w3 = w2; w2 = wn;
+                l2 = l1; l1 = ln;
+                c2 = c1; c1 = cn;
+                v2 = v1; v1 = v0; v0 = vn;
+            }
+        }
+    }
+}
+
 // Periodic index for i in [-n, 2n): one compare and add instead of a division.
 __device__ __forceinline__ int wrap1(int i, int n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
@@ -50,11 +260,17 @@ constexpr int NIT0 = (TY * TX + NT - 1) / NT;     // interior cells per thread
     (((A)[y][(x) + 1] + (A)[y][(x)-1] - 2.0 * (A)[y][x]) * p.ihx2 +       \
      ((A)[(y) + 1][x] + (A)[(y)-1][x] - 2.0 * (A)[y][x]) * p.ihy2)
 
+// ---------------------------------------------------------------------------
+// 2-D tile stencils (M = 1, periodic), for grids too small to give the sliding sweeps enough
+// waves: a 64x16 output tile is staged in LDS with a three-cell halo and the composite
+// operator applied as three successive five-point Laplacians inside LDS (halo 3 -> 2 -> 1 -> 0).
+// ---------------------------------------------------------------------------
+
 // F = (Phi - phi)/dt - Delta_d mu_d - src, plus one partial sum of F^2 per block (and of
 // Phi^2 in xpart when given).
 // Persistent blocks walk their tiles; the halo of the next tile is loaded into registers
 // while the current one is computed from LDS.
-__global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Phi,
+__global__ __launch_bounds__(NT) void k_residual2d_tile(const double* __restrict__ Phi,
                                                    const double* __restrict__ phi,
                                                    const double* __restrict__ src,
                                                    double* __restrict__ F,
@@ -143,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
 // -s, s = shift_scale * sum(shift_part[0..shift_n)) when shift_part is given (zero-mean
 // projection fused into the load; every block forms s in the same order and block 0
 // stores it in *shift_out).
-__global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
+__global__ __launch_bounds__(NT) void k_jv2d_tile(const double* __restrict__ v,
                                              const double* __restrict__ cc,
                                              const double* __restrict__ shift_part, int shift_n,
                                              double shift_scale, double* __restrict__ shift_out,
@@ -439,11 +655,16 @@ P make_params(const pfc_ctx* c, double dt) {
 }
 
 dim3 tiles2d(const pfc_ctx* c) { return dim3(((c->g.nx + TX - 1) / TX) * ((c->g.ny + TY - 1) / TY)); }
-// persistent grid of the residual: four resident blocks per CU (LDS-limited) on 256 CUs
-dim3 residual_grid(const pfc_ctx* c) {
-    const unsigned t = tiles2d(c).x;
-    return dim3(t < 1024u ? t : 1024u);
+inline bool sliding(int nx, int ny) { return (long)nx * ny >= SW_MIN_CELLS; }
+// grid of the 2-D residual and Jacobian action, at most 1024 blocks: one wave per (strip,
+// segment) item of the sliding sweeps, or persistent blocks over the tiles (four resident
+// blocks per CU, LDS-limited, on 256 CUs)
+inline unsigned grid2d(int nx, int ny) {
+    const long b = sliding(nx, ny) ? ((long)sw_geom(nx, ny).items + NT / 64 - 1) / (NT / 64)
+                                   : (long)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
+    return (unsigned)(b < 1024 ? b : 1024);
 }
+dim3 residual_grid(const pfc_ctx* c) { return dim3(grid2d(c->g.nx, c->g.ny)); }
 dim3 mp_grid(const pfc_ctx* c) { return dim3((c->g.nx + 63) / 64, (c->g.ny + 3) / 4, c->g.nz); }
 
 }  // namespace
@@ -460,7 +681,10 @@ hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* ph
                            const double* src, double* F, double* norm_part, double* xnorm_part) {
     const P p = make_params(c, dt);
     if (fused2d(c)) {
-        return launch_k(c, k_residual2d, residual_grid(c), dim3(NT), 0, Phi, phi, src, F, norm_part, xnorm_part, p);
+        return sliding(c->g.nx, c->g.ny)
+                   ? launch_k(c, k_residual2d, residual_grid(c), dim3(NT), 0, Phi, phi, src, F, norm_part, xnorm_part, p)
+                   : launch_k(c, k_residual2d_tile, residual_grid(c), dim3(NT), 0, Phi, phi, src, F, norm_part,
+                              xnorm_part, p);
     }
     if (xnorm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, Phi, c->g.N, xnorm_part);
     double* u = c->d_tmp3;
@@ -498,8 +722,11 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
                      int shift_n, double shift_scale, double* shift_out, double* Jv) {
     const P p = make_params(c, dt);
     if (fused2d(c)) {
-        return launch_k(c, k_jv2d, tiles2d(c), dim3(NT), 0, v, cbuf, shift_part, shift_n, shift_scale, shift_out,
-                        Jv, p);
+        return sliding(c->g.nx, c->g.ny)
+                   ? launch_k(c, k_jv2d, residual_grid(c), dim3(NT), 0, v, cbuf, shift_part, shift_n, shift_scale,
+                              shift_out, Jv, p)
+                   : launch_k(c, k_jv2d_tile, residual_grid(c), dim3(NT), 0, v, cbuf, shift_part, shift_n,
+                              shift_scale, shift_out, Jv, p);
     }
     // the shifted v lives in the output buffer, the inner operator in the scratch vector, and the
     // last pass updates the output in place (it reads the shifted v at the cell only)
@@ -517,10 +744,7 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
     return hipGetLastError();
 }
 
-int residual2d_blocks(int nx, int ny) {
-    const unsigned t = (unsigned)(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY));
-    return (int)(t < 1024u ? t : 1024u);
-}
+int residual2d_blocks(int nx, int ny) { return (int)grid2d(nx, ny); }
 
 hipError_t launch_residual2d_plain(hipStream_t s, int nx, int ny, double ihx2, double ihy2, double gamma,
                                    double dt, const double* Phi, const double* phi, const double* src, double* F,
@@ -536,8 +760,12 @@ hipError_t launch_residual2d_plain(hipStream_t s, int nx, int ny, double ihx2, d
     p.inv_dt = dt > 0 ? 1.0 / dt : 0.0;
     p.neu = 0;
     p.mob = 0;
-    hipLaunchKernelGGL(k_residual2d, dim3(residual2d_blocks(nx, ny)), dim3(NT), 0, s, Phi, phi, src, F, norm_part,
-                       (double*)nullptr, p);
+    if (sliding(nx, ny))
+        hipLaunchKernelGGL(k_residual2d, dim3(grid2d(nx, ny)), dim3(NT), 0, s, Phi, phi, src, F, norm_part,
+                           (double*)nullptr, p);
+    else
+        hipLaunchKernelGGL(k_residual2d_tile, dim3(grid2d(nx, ny)), dim3(NT), 0, s, Phi, phi, src, F, norm_part,
+                           (double*)nullptr, p);
     return hipGetLastError();
 }
 

@@ -86,6 +86,49 @@ def test_residual_jv_full_size_1024():
     s.close()
 
 
+@pytest.mark.parametrize("shape,sub", [((1430, 1500), (11, 12)), ((1024, 4096), (8, 32))])
+def test_residual_jv_sliding_sweeps(shape, sub):
+    """Grids of 2^21 cells and more take the sliding-sweep kernels: a ragged one (26 strips of 58
+    columns, the last with 50; segments of 16 rows, the last with 6) and test C's 1024 x 4096
+    mesh at dx = dy = pi/3, with and without a source term, two time steps."""
+    pfc = _pfc()
+    L = (shape[0] * math.pi / 3, shape[1] * math.pi / 3)
+    h = S.spacing(shape, L)
+    s = pfc.Solver(shape, L, 0.25, sub, 2)
+    Phi, phi = _pair(shape, 31)
+    src = np.random.default_rng(32).standard_normal(shape) * 0.1
+    v = np.random.default_rng(33).standard_normal(shape)
+    for dt in (0.1, 7.0):
+        F, nrm = s.residual(T(Phi), T(phi), dt, src=T(src))
+        ref = S.residual(Phi, phi, dt, 0.25, h, src=src)
+        assert rel(N(F), ref) < 1e-12
+        assert abs(nrm - np.linalg.norm(ref)) < 1e-12 * np.linalg.norm(ref)
+        assert rel(N(s.jv(T(Phi), T(phi), dt, T(v))), S.jv(Phi, phi, dt, 0.25, h, v)) < 1e-12
+    s.close()
+
+
+def test_projected_gmres_on_the_sliding_sweeps():
+    """FGMRES with the zero-mean projection (the Jacobian action takes the mean of its input off
+    while loading it) on a 1024 x 2048 grid, which the sliding-sweep kernels handle: the solution
+    has zero mean and meets the tolerance in the oracle's Jacobian action (exact LU on 64 x 64
+    boxes, dt = 0.01)."""
+    pfc = _pfc()
+    shape = (1024, 2048)
+    L = (shape[0] * 400.0 / 1024, shape[1] * 400.0 / 1024)
+    h = S.spacing(shape, L)
+    Phi, phi = _pair(shape, 34)
+    b = np.random.default_rng(35).standard_normal(shape)
+    b -= b.mean()
+    s = pfc.Solver(shape, L, 0.25, (16, 32), 2, sub_solver="lu", mass_project=True)
+    s.ras_setup(T(Phi), T(phi), 0.01)
+    x, its, res = s.gmres(T(Phi), T(phi), 0.01, T(b), 1e-8, 0.0)
+    xn = N(x)
+    assert 0 < its < 300
+    assert abs(xn.mean()) <= 1e-12 * np.abs(xn).max()
+    assert np.linalg.norm(S.jv(Phi, phi, 0.01, 0.25, h, xn) - b) <= 1.05e-8 * np.linalg.norm(b)
+    s.close()
+
+
 def test_residual_jv_energy_3d():
     pfc = _pfc()
     shape, L = (12, 16, 20), (9.0, 12.0, 15.0)

@@ -1,5 +1,6 @@
 """Pins of the FP64 network reference (oracle/cnn.py) against library routines, brute force,
-adjoint identities, finite differences and the closed form of Adam's first steps."""
+adjoint identities, finite differences, the closed form of Adam's first steps, the
+constant-plane reading of the step-size input and the scale invariance of the guess."""
 import numpy as np
 import pytest
 import scipy.ndimage
@@ -65,25 +66,94 @@ def test_adjoints_satisfy_inner_product_identities():
     assert abs(lhs - np.sum(w * cnn.conv3x3_adjoint_weight(g, a))) < 1e-11 * abs(lhs) + 1e-11
 
 
-def test_backward_matches_central_differences():
+@pytest.mark.parametrize("cond", [0.0, 0.7])
+def test_backward_matches_central_differences(cond):
     width = 4
     r = _rng(4)
-    theta = cnn.init_params(5, cin=2, width=width, out_scale=1.0)
+    theta = cnn.init_params(5, cin=2, width=width, out_scale=1.0, cond_scale=0.5)
     theta += 0.1 * r.standard_normal(theta.size)     # non-zero biases too
     x = r.standard_normal((2, 5, 6))
     t = r.standard_normal((5, 6))
-    y, acts = cnn.forward(theta, x, round_weights=False, width=width)
-    g = cnn.backward(theta, acts, y, t, round_weights=False, width=width)
-    idx = r.choice(theta.size, 60, replace=False)
+    y, acts = cnn.forward(theta, x, cond, round_weights=False, width=width)
+    g = cnn.backward(theta, acts, y, t, cond, round_weights=False, width=width)
+    # 60 sampled parameters and every entry of u1 (the last `width` ones)
+    idx = np.concatenate([r.choice(theta.size - width, 60, replace=False), theta.size - width + np.arange(width)])
     h = 1e-6
     for k in idx:
         tp, tm = theta.copy(), theta.copy()
         tp[k] += h
         tm[k] -= h
-        lp = cnn.loss(cnn.forward(tp, x, round_weights=False, width=width)[0], t)
-        lm = cnn.loss(cnn.forward(tm, x, round_weights=False, width=width)[0], t)
+        lp = cnn.loss(cnn.forward(tp, x, cond, round_weights=False, width=width)[0], t)
+        lm = cnn.loss(cnn.forward(tm, x, cond, round_weights=False, width=width)[0], t)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
+    if cond == 0.0:
+        assert not np.any(g[-width:])
+
+
+def test_step_size_input_is_a_constant_third_plane():
+    """Layer 1 at condition c equals a three-channel periodic correlation (scipy) whose third
+    input plane is the constant c and whose third-channel taps (unrounded) sum to u1."""
+    width = 4
+    r = _rng(12)
+    theta = cnn.init_params(13, width=width, out_scale=1.0, cond_scale=1.0)
+    layers, u1 = cnn.unpack(theta, width=width)
+    x = r.standard_normal((2, 6, 7))
+    c = -1.3
+    taps = r.uniform(0.5, 1.5, (width, 3, 3))
+    taps *= (u1 / taps.sum(axis=(1, 2)))[:, None, None]      # any taps with these sums
+    w1 = cnn.bf16_round(layers[0][0])
+    planes = [x[0], x[1], np.full((6, 7), c)]
+    z1 = np.stack([layers[0][1][o] + sum(scipy.ndimage.correlate(planes[k], w1[o, k], mode="wrap") for k in range(2))
+                   + scipy.ndimage.correlate(planes[2], taps[o], mode="wrap") for o in range(width)])
+    a = np.tanh(z1)
+    for w, b in layers[1:3]:
+        a = np.tanh(np.stack([b[o] + sum(scipy.ndimage.correlate(a[k], cnn.bf16_round(w)[o, k], mode="wrap")
+                                         for k in range(width)) for o in range(width)]))
+    w4, b4 = layers[3]
+    y = b4[0] + sum(scipy.ndimage.correlate(a[k], cnn.bf16_round(w4)[0, k], mode="wrap") for k in range(width))
+    np.testing.assert_allclose(cnn.forward(theta, x, c, width=width)[0], y, rtol=1e-12, atol=1e-12)
+
+
+def test_step_size_enters_through_its_scale_and_condition_only():
+    """At dt = dt_ref the scale g is 1 and c = 0: the guess is the unconditioned network on
+    x1 = d / s_b with output s_o y.  At another dt it is that network with x1 / g, c and the
+    output times g; and a zero history with a zero output layer gives phi^n."""
+    r = _rng(14)
+    phi = -0.3 + 0.1 * r.standard_normal((8, 8))
+    d = 0.01 * r.standard_normal((8, 8))
+    theta = cnn.init_params(15, out_scale=1.0, cond_scale=0.3)
+    sc = (0.1, 0.02, 0.5, 2.0, 0.8, -0.05)
+    x = np.stack([(phi - phi.mean()) / sc[0], 1.3 * d / sc[1]])
+    y0, _ = cnn.forward(theta, x, 0.0)
+    g0 = phi + sc[2] * y0
+    np.testing.assert_allclose(cnn.guess(theta, phi, phi - d, 1.3, 0.05, sc, 0.05), g0 + (phi.mean() - g0.mean()),
+                               rtol=0, atol=1e-15)
+    l = np.log(0.7 / 0.05)
+    gs = np.exp(0.8 * l - 0.05 * l * l)
+    assert abs(cnn.step_scale(0.7, 0.05, 0.8, -0.05) - gs) < 1e-15 * gs
+    y1, _ = cnn.forward(theta, np.stack([x[0], x[1] / gs]), l / 2.0)
+    g1 = phi + sc[2] * gs * y1
+    np.testing.assert_allclose(cnn.guess(theta, phi, phi - d, 1.3, 0.7, sc, 0.05), g1 + (phi.mean() - g1.mean()),
+                               rtol=0, atol=1e-14)
+    layers, u1 = cnn.unpack(theta)
+    layers[3][0][:] = 0.0
+    layers[3][1][:] = 0.0
+    np.testing.assert_array_equal(cnn.guess(cnn.pack(layers, u1), phi, phi, 1.3, 0.7, sc, 0.05), phi)
+
+
+def test_guess_is_the_same_on_a_periodically_repeated_domain():
+    """The network is a periodic convolution and the mean does not change when a periodic
+    field is repeated 2 x 3 times, so the guess on the repeated field is the repeated guess
+    (what lets a network trained on one grid size serve a larger one)."""
+    r = _rng(16)
+    phi = -0.3 + 0.1 * r.standard_normal((8, 6))
+    prev = phi - 0.01 * r.standard_normal((8, 6))
+    theta = cnn.init_params(17, out_scale=1.0, cond_scale=0.3)
+    sc = (0.1, 0.02, 0.5, 2.0, 0.8, -0.05)
+    g = cnn.guess(theta, phi, prev, 1.1, 0.3, sc, 0.05)
+    gt = cnn.guess(theta, np.tile(phi, (2, 3)), np.tile(prev, (2, 3)), 1.1, 0.3, sc, 0.05)
+    np.testing.assert_allclose(gt, np.tile(g, (2, 3)), rtol=0, atol=1e-14)
 
 
 def test_gradient_uses_rounded_weights():
@@ -94,8 +164,8 @@ def test_gradient_uses_rounded_weights():
     r = _rng(6)
     x = r.standard_normal((2, 4, 4))
     t = r.standard_normal((4, 4))
-    rounded = np.concatenate([np.concatenate([cnn.bf16_round(w).ravel(), b.ravel()])
-                              for w, b in cnn.unpack(theta, width=width)])
+    layers, u1 = cnn.unpack(theta, width=width)
+    rounded = cnn.pack([(cnn.bf16_round(w), b) for w, b in layers], u1)
     y1, a1 = cnn.forward(theta, x, width=width)
     y2, a2 = cnn.forward(rounded, x, round_weights=False, width=width)
     np.testing.assert_array_equal(y1, y2)
@@ -118,25 +188,25 @@ def test_adam_closed_form_first_steps():
 
 
 def test_parameter_count_and_layout():
-    assert cnn.n_params() == 32 * 2 * 9 + 32 + 2 * (32 * 32 * 9 + 32) + 32 * 9 + 1 == 19393
+    assert cnn.n_params() == 32 * 2 * 9 + 32 + 2 * (32 * 32 * 9 + 32) + 32 * 9 + 1 + 32 == 19425
     theta = np.arange(cnn.n_params(), dtype=np.float64)
-    layers = cnn.unpack(theta)
+    layers, u1 = cnn.unpack(theta)
     assert layers[0][0][0, 0, 0, 0] == 0 and layers[0][1][0] == 576
-    assert layers[3][1][0] == cnn.n_params() - 1
-    np.testing.assert_array_equal(cnn.pack(layers), theta)
+    assert layers[3][1][0] == 19392 and u1[0] == 19393 and u1[-1] == cnn.n_params() - 1
+    np.testing.assert_array_equal(cnn.pack(layers, u1), theta)
 
 
 def test_guess_keeps_mass_and_reduces_to_previous_without_output_layer():
     r = _rng(8)
     phi = -0.3 + 0.1 * r.standard_normal((8, 8))
     prev = phi + 0.01 * r.standard_normal((8, 8))
-    theta = cnn.init_params(9, out_scale=1.0)
-    g = cnn.guess(theta, phi, prev, 1.0, (0.1, 0.01, 0.01))
+    theta = cnn.init_params(9, out_scale=1.0, cond_scale=0.5)
+    g = cnn.guess(theta, phi, prev, 1.0, 0.3, (0.1, 0.01, 1.0, 1.0, 1.0, 0.0), 0.01)
     assert abs(g.mean() - phi.mean()) < 1e-15
-    layers = cnn.unpack(theta)
+    layers, u1 = cnn.unpack(theta)
     layers[3][0][:] = 0.0
     layers[3][1][:] = 0.0
-    g0 = cnn.guess(cnn.pack(layers), phi, prev, 1.0, (0.1, 0.01, 0.01))
+    g0 = cnn.guess(cnn.pack(layers, u1), phi, prev, 1.0, 0.3, (0.1, 0.01, 1.0, 1.0, 1.0, 0.0), 0.01)
     np.testing.assert_allclose(g0, phi, rtol=0, atol=1e-15)
 
 

@@ -62,7 +62,7 @@ VARIANTS = {
     "learned_graph": dict(sub=(16, 64), overlap=4, sub_solver="lu", precond_fp32=True, guess="learned",
                           precond_lag=20, use_graph=True),
 }
-LEARNED_TRAINING = dict(n=512, trajectories=10, steps=201, epochs=8, lr=3e-3)
+LEARNED_TRAINING = dict(n=512, trajectories=8, hold=200, epochs=8, lr=3e-3, w_sweep=0.1)
 
 
 def apply_bytes_table(shape, sub, overlap, fp32):
@@ -143,27 +143,29 @@ def train_guess_net(cfg):
     from paper_1703_01202_amd import learned
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)   # noqa: E731
     t0 = time.perf_counter()
-    data = learned.generate(cfg["n"], trajectories=cfg["trajectories"], steps=cfg["steps"], log=log)
+    data = learned.generate(cfg["n"], trajectories=cfg["trajectories"], hold=cfg["hold"], log=log)
     t1 = time.perf_counter()
-    net, hist = learned.train(data["X"], data["T"], epochs=cfg["epochs"], lr=cfg["lr"], log=log)
+    net, hist = learned.train(data["X"], data["T"], data["C"], epochs=cfg["epochs"], lr=cfg["lr"],
+                              weights=learned.sweep_weights(data["C"], cfg["w_sweep"]), log=log)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     # inference cost at the benchmark grid
     x = torch.zeros((2, 1024, 1024), dtype=torch.float32, device="cuda")
     y = torch.empty((1024, 1024), dtype=torch.float32, device="cuda")
     for _ in range(3):
-        net.forward(x, y)
+        net.forward(x, out=y)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     for _ in range(20):
-        net.forward(x, y)
+        net.forward(x, out=y)
     torch.cuda.synchronize()
     fwd_ms = (time.perf_counter() - t3) / 20 * 1e3
     del x, y
-    meta = {"scales": data["scales"], "dt_train": data["dt"], "samples": data["stats"]["samples"],
+    meta = {"scales": data["scales"], "dt_range": data["dt_range"], "samples": data["stats"]["samples"],
+            "failed_steps": data["stats"]["failed_steps"],
             "data_seconds": t1 - t0, "train_seconds": t2 - t1, "held_out_loss": hist[-1][2],
             "loss_history": [h[2] for h in hist], "forward_ms_1024": fwd_ms, "config": cfg,
-            "arch": "4 x conv3x3 periodic, 2-32-32-32-1, tanh; bf16 weights, fp32 accumulate"}
+            "arch": "4 x conv3x3 periodic, 2(+log dt plane)-32-32-32-1, tanh; bf16 weights, fp32 accumulate"}
     del data
     torch.cuda.empty_cache()
     return net, meta
@@ -204,7 +206,7 @@ def _run_variant(name, v, steps, warmup, timing, net, net_meta, tuned, stream):
                    lin_atol=w.lin_atol, timing=timing, precond_lag=v.get("precond_lag", 0),
                    use_graph=v.get("use_graph", False), stream=stream)
     if v["guess"] == "learned":
-        s.attach_net(net, net_meta["scales"], net_meta["dt_train"])
+        s.attach_net(net, net_meta["scales"], net_meta["dt_range"])
     phi = phi0.clone()
     for i in range(warmup):
         s.step(phi)
@@ -391,6 +393,101 @@ def run_3d_256(steps):
     return out
 
 
+def _crystal_solver(w, sub, overlap, guess, fp32, lag, net, net_meta, timing=False):
+    import paper_1703_01202_amd as pfc
+    s = pfc.Solver(w.shape, w.lengths, w.gamma, sub, overlap, sub_solver="lu", precond_fp32=fp32, guess=guess,
+                   dt_min=w.dt_min, dt_max=w.dt_max, eta=w.eta, newton_rtol=w.newton_rtol,
+                   newton_atol=w.newton_atol, lin_rtol=w.lin_rtol, lin_atol=w.lin_atol, precond_lag=lag,
+                   timing=timing)
+    if net is not None:
+        s.attach_net(net, net_meta["scales"], net_meta["dt_range"])
+    return s
+
+
+def run_ablation(steps, net, net_meta, tuned):
+    """Where the speed-up comes from: the headline workload's first steps on the headline
+    decomposition for every combination of initial guess (previous solution, linear
+    extrapolation, learned), subdomain factor precision (FP32, FP64) and factor lag (0: factor
+    once per time step as the paper does; 100), each from the same initial state after one
+    untimed step."""
+    import torch
+    import pfc_inputs as I
+    w = I.crystal_growth_1024()
+    sub = tuple(tuned["sub"]) if tuned else VARIANTS["learned"]["sub"]
+    ov = tuned["overlap"] if tuned else VARIANTS["learned"]["overlap"]
+    phi0 = torch.tensor(w.initial(), dtype=torch.float64, device="cuda")
+    rows = []
+    for guess in ("previous", "extrap", "learned"):
+        for fp32 in (True, False):
+            for lag in (0, 100):
+                s = _crystal_solver(w, sub, ov, guess, fp32, lag, net, net_meta, timing=1 | 8)
+                phi = phi0.clone()
+                s.step(phi)
+                s.reset()
+                phi.copy_(phi0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = [s.step(phi) for _ in range(steps)]
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                kt = {k: s.kernel_time(k) for k in (0, 3)}
+                s.close()
+                rows.append({"guess": guess, "factors": "fp32" if fp32 else "fp64", "lag": lag, "steps": steps,
+                             "steps_per_s": steps / el, "newton_its": sum(x["newton_its"] for x in st),
+                             "gmres_its": sum(x["gmres_its"] for x in st),
+                             "factorisations": kt[3][0], "factorisation_ms": kt[3][1],
+                             "apply_launches": kt[0][0], "apply_ms": kt[0][1]})
+                print(f"[bench] ablation {rows[-1]}", file=sys.stderr, flush=True)
+    return {"workload": "pfc2d_1024_crystal", "sub": list(sub), "overlap": ov, "rows": rows}
+
+
+def run_dt_sweep(net, net_meta, tuned, hold=10, growth=1.25, tail=10):
+    """The headline workload over the decades of dt that the adaptive step (Eq. (21)) spans:
+    a fixed schedule (hold steps at dt_min = 0.01, dt growing by `growth` per step to
+    dt_max = 10, tail steps at 10), each step's Newton started from the guess of each kind
+    (the learned guess conditioned on the step size).  On this workload the controller itself
+    keeps dt at dt_min for as long as a run here lasts (|dE/dt| of the total energy stays far
+    above the ~14 at which Eq. (21) with eta = 5000 lets dt grow), so the schedule stands in
+    for the late stretch of a long run."""
+    import torch
+    import pfc_inputs as I
+    from paper_1703_01202_amd import learned
+    w = I.crystal_growth_1024()
+    sub = tuple(tuned["sub"]) if tuned else VARIANTS["learned"]["sub"]
+    ov = tuned["overlap"] if tuned else VARIANTS["learned"]["overlap"]
+    sched = learned.step_schedule(w.dt_min, w.dt_max, hold, growth, tail)
+    bands = ((0.0, 0.05), (0.05, 1.0), (1.0, 11.0))
+    out = {"workload": "pfc2d_1024_crystal", "schedule": {"hold": hold, "growth": growth, "tail": tail,
+                                                          "steps": len(sched)},
+           "bands": [list(b) for b in bands], "runs": {}}
+    phi0 = torch.tensor(w.initial(), dtype=torch.float64, device="cuda")
+    for guess in ("previous", "extrap", "learned"):
+        s = _crystal_solver(w, sub, ov, guess, True, 100, net, net_meta)
+        phi = phi0.clone()
+        prev = dprev = None
+        newton = [0] * len(bands)
+        ratios = [[] for _ in bands]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for dt in sched:
+            X = s.guess("previous", phi) if prev is None else s.guess(guess, phi, prev, dt, dprev)
+            r0 = s.residual(X, phi, dt)[1] / s.residual(phi, phi, dt)[1]
+            Phi, st = s.newton(phi, dt, Phi0=X)
+            b = next(i for i, (lo, hi) in enumerate(bands) if lo <= dt < hi)
+            newton[b] += st["newton_its"]
+            if prev is not None:
+                ratios[b].append(r0)
+            prev, dprev, phi = phi, dt, Phi
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.close()
+        out["runs"][guess] = {"seconds": el, "steps_per_s": len(sched) / el, "newton_its": newton,
+                              "res0_over_ref_median": [float(sorted(r)[len(r) // 2]) if r else None for r in ratios]}
+        print(f"[bench] dt sweep {guess}: newton per band {newton}, residual ratio "
+              f"{out['runs'][guess]['res0_over_ref_median']}", file=sys.stderr, flush=True)
+    return out
+
+
 def run_crack(steps):
     """Test C's grid: 4096 x 1024 on [0, 4096 pi/3] x [0, 1024 pi/3], the notched lattice, gamma 1,
     adaptive dt 1..5 (eta 100); FP32 exact-LU subdomain solves on 16 x 64 boxes of 64 x 64 owned
@@ -510,6 +607,10 @@ def main():
                     help="steps of each of test B's four variants at 1024^2 (0 skips them)")
     ap.add_argument("--steps-3d-256", type=int, default=6, help="steps of the 256^3 test-D grid (0 skips it)")
     ap.add_argument("--steps-crack", type=int, default=20, help="steps of the 4096x1024 test-C grid (0 skips it)")
+    ap.add_argument("--steps-ablation", type=int, default=20,
+                    help="steps of each guess x factor precision x lag combination (0 skips the ablation)")
+    ap.add_argument("--no-dt-sweep", action="store_true",
+                    help="skip the guess comparison over a dt schedule from 0.01 to 10")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -558,6 +659,9 @@ def main():
     variants = run_test_b_variants(args.steps_variants) if args.steps_variants > 0 else None
     three_d_256 = run_3d_256(args.steps_3d_256) if args.steps_3d_256 > 0 else None
     crack = run_crack(args.steps_crack) if args.steps_crack > 0 else None
+    ablation = run_ablation(args.steps_ablation, net, net_meta, tuned) \
+        if args.steps_ablation > 0 and net is not None else None
+    dt_sweep = run_dt_sweep(net, net_meta, tuned) if not args.no_dt_sweep and net is not None else None
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
@@ -606,6 +710,10 @@ def main():
         out["detail"]["pfc3d_bcc_256"] = three_d_256
     if crack is not None:
         out["detail"]["pfc2d_crack_4096x1024"] = crack
+    if ablation is not None:
+        out["detail"]["ablation_guess_precision_lag"] = ablation
+    if dt_sweep is not None:
+        out["detail"]["dt_sweep_guess"] = dt_sweep
     print(json.dumps(out), flush=True)
 
 

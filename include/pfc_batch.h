@@ -46,7 +46,7 @@ pfc_status pfc_batch_step(pfc_batch* b, double* const* phis, pfc_step_stats* st,
 pfc_status pfc_batch_reset(pfc_batch* b);
 
 /* pfc_attach_net on every instance (one network shared read-only by all of them). */
-pfc_status pfc_batch_attach_net(pfc_batch* b, pfc_net* net, const double* scales, double dt_train);
+pfc_status pfc_batch_attach_net(pfc_batch* b, pfc_net* net, const double* scales, const double* dt_range);
 
 /* Instance i's context (owned by the batch; for pfc_energy, pfc_kernel_time and the like,
  * not to be destroyed by the caller). */

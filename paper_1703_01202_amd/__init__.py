@@ -194,16 +194,25 @@ class Solver:
     def checkpoint_load(self, phi, path):
         self._check(self.lib.pfc_checkpoint_load(self.ctx, self._field(phi, "phi"), str(path).encode()))
 
-    def attach_net(self, net, scales, dt_train):
-        """Use ``net`` (a GuessNet) for ``guess="learned"``; scales = (s_a, s_b, s_o)."""
-        sc = (ctypes.c_double * 3)(*[float(v) for v in scales])
-        self._check(self.lib.pfc_attach_net(self.ctx, net.handle if net is not None else None, sc, float(dt_train)))
+    def attach_net(self, net, scales, dt_range):
+        """Use ``net`` (a GuessNet) for ``guess="learned"``; scales = (s_a, s_b, s_o, s_c, beta,
+        gamma), dt_range = (dt_ref, dt_lo, dt_hi) (include/pfc_net.h)."""
+        sc, dr = _net_args(scales, dt_range)
+        self._check(self.lib.pfc_attach_net(self.ctx, net.handle if net is not None else None, sc, dr))
         self._net = net          # the context keeps the pointer: keep the object alive
 
     def kernel_time(self, which):
         cnt, ms = ctypes.c_long(0), ctypes.c_double(0.0)
         self._check(self.lib.pfc_kernel_time(self.ctx, int(which), ctypes.byref(cnt), ctypes.byref(ms)))
         return cnt.value, ms.value
+
+
+def _net_args(scales, dt_range):
+    if len(scales) != 6 or len(dt_range) != 3:
+        raise ValueError("scales = (s_a, s_b, s_o, s_c, beta, gamma), dt_range = (dt_ref, dt_lo, dt_hi)")
+    sc = (ctypes.c_double * 6)(*[float(v) for v in scales])
+    dr = (ctypes.c_double * 3)(*[float(v) for v in dt_range])
+    return sc, dr
 
 
 class GuessNet:
@@ -252,17 +261,18 @@ class GuessNet:
         self._check(self.lib.pfc_net_get_params(self.handle, p.ctypes.data_as(_lib.c_float_p)))
         return p
 
-    def forward(self, x, out=None):
+    def forward(self, x, cond=0.0, out=None):
+        """y = network(x; c = cond)."""
         ny, nx = x.shape[1:]
         y = out if out is not None else self._torch.empty((ny, nx), dtype=self._torch.float32, device="cuda")
-        self._check(self.lib.pfc_net_forward(self.handle, self._plane(x, (2, ny, nx), "x"), ny, nx,
+        self._check(self.lib.pfc_net_forward(self.handle, self._plane(x, (2, ny, nx), "x"), float(cond), ny, nx,
                                              self._plane(y, (ny, nx), "y")))
         return y
 
-    def gradient(self, x, t, scale=1.0, accumulate=False, want_loss=True):
+    def gradient(self, x, t, cond=0.0, scale=1.0, accumulate=False, want_loss=True):
         ny, nx = x.shape[1:]
         loss = ctypes.c_double(0.0)
-        self._check(self.lib.pfc_net_gradient(self.handle, self._plane(x, (2, ny, nx), "x"),
+        self._check(self.lib.pfc_net_gradient(self.handle, self._plane(x, (2, ny, nx), "x"), float(cond),
                                               self._plane(t, (ny, nx), "t"), ny, nx, float(scale),
                                               int(bool(accumulate)), ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
@@ -338,10 +348,9 @@ class Batch:
     def reset(self):
         self._check(self.lib.pfc_batch_reset(self.handle))
 
-    def attach_net(self, net, scales, dt_train):
-        sc = (ctypes.c_double * 3)(*[float(v) for v in scales])
-        self._check(self.lib.pfc_batch_attach_net(self.handle, net.handle if net is not None else None, sc,
-                                                  float(dt_train)))
+    def attach_net(self, net, scales, dt_range):
+        sc, dr = _net_args(scales, dt_range)
+        self._check(self.lib.pfc_batch_attach_net(self.handle, net.handle if net is not None else None, sc, dr))
         self._net = net
 
     def close(self):

@@ -107,15 +107,16 @@ SIGNATURES = {
     "pfc_net_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "pfc_net_set_params": (ctypes.c_int, [ctypes.c_void_p, c_float_p]),
     "pfc_net_get_params": (ctypes.c_int, [ctypes.c_void_p, c_float_p]),
-    "pfc_net_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
-    "pfc_net_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                        ctypes.c_double, ctypes.c_int, c_double_p]),
+    "pfc_net_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_void_p]),
+    "pfc_net_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_int, c_double_p]),
     "pfc_net_get_gradient": (ctypes.c_int, [ctypes.c_void_p, c_float_p]),
     "pfc_net_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double]),
     "pfc_guess": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_void_p]),
-    "pfc_attach_net": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, ctypes.c_double]),
+    "pfc_attach_net": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_double_p]),
     # batched instances (include/pfc_batch.h)
     "pfc_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(PfcGrid), ctypes.POINTER(PfcModel),
                                         ctypes.POINTER(PfcOpts), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
@@ -124,11 +125,11 @@ SIGNATURES = {
     "pfc_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(PfcStepStats),
                                       ctypes.POINTER(ctypes.c_int)]),
     "pfc_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
-    "pfc_batch_attach_net": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, ctypes.c_double]),
+    "pfc_batch_attach_net": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_double_p]),
     "pfc_batch_instance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
 }
 
-NET_NPARAM = 19393
+NET_NPARAM = 19425
 
 _lib = None
 

@@ -48,7 +48,7 @@ def autotune(shape, lengths, gamma, phi0, solver_kwargs, candidates, steps=30, w
             continue
         try:
             if net is not None:
-                s.attach_net(net, net_meta["scales"], net_meta["dt_train"])
+                s.attach_net(net, net_meta["scales"], net_meta["dt_range"])
             phi = phi0.clone()
             for _ in range(warmup):
                 s.step(phi)

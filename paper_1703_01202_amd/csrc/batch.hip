@@ -164,10 +164,10 @@ pfc_status pfc_batch_reset(pfc_batch* b) {
     return PFC_OK;
 }
 
-pfc_status pfc_batch_attach_net(pfc_batch* b, pfc_net* net, const double* scales, double dt_train) {
+pfc_status pfc_batch_attach_net(pfc_batch* b, pfc_net* net, const double* scales, const double* dt_range) {
     if (!b) return PFC_EINVAL;
     for (size_t i = 0; i < b->ctx.size(); ++i) {
-        const pfc_status s = pfc_attach_net(b->ctx[i], net, scales, dt_train);
+        const pfc_status s = pfc_attach_net(b->ctx[i], net, scales, dt_range);
         if (s != PFC_OK) {
             b->err = "instance " + std::to_string(i) + ": " + pfc_last_error(b->ctx[i]);
             return s;

@@ -30,9 +30,9 @@ namespace {
 
 constexpr int CIN = PFC_NET_CIN, WID = PFC_NET_WIDTH, NG = WID / 4;
 constexpr int OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 608, OFF_B2 = 9824, OFF_W3 = 9856, OFF_B3 = 19072,
-              OFF_W4 = 19104, OFF_B4 = 19392;
+              OFF_W4 = 19104, OFF_B4 = 19392, OFF_U1 = 19393;
 constexpr int NPARAM = PFC_NET_NPARAM;
-static_assert(OFF_B4 + 1 == NPARAM, "parameter layout");
+static_assert(OFF_U1 + WID == NPARAM, "parameter layout");
 constexpr int KSTEPS = 18;                 // 9 taps x 2 blocks of 16 input channels
 constexpr int PACK = KSTEPS * 64;          // packed A operands (8 bf16 each) per layer and direction
 constexpr int PACK4 = 2 * 64;              // packed A operands of the output layer's tap sums
@@ -127,8 +127,9 @@ __global__ void k_prepare(const float* __restrict__ theta, float* __restrict__ q
 }
 
 // layer 1 at cell (y, x): the 32 channels of a1 = tanh(conv(x; W1) + b1) as 8 split groups
-__device__ __forceinline__ void layer1_cell(const float* __restrict__ x, const float* __restrict__ q, long HW, int ny,
-                                            int nx, int y, int xx, uint4* out) {
+__device__ __forceinline__ void layer1_cell(const float* __restrict__ x, const float* __restrict__ q,
+                                            const float* __restrict__ b1, long HW, int ny, int nx, int y, int xx,
+                                            uint4* out) {
     float in[CIN][9];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
@@ -146,7 +147,7 @@ __device__ __forceinline__ void layer1_cell(const float* __restrict__ x, const f
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int co = 4 * g + j;
-            float z = q[OFF_B1 + co];
+            float z = b1[co];
 #pragma unroll
             for (int c = 0; c < CIN; ++c)
 #pragma unroll
@@ -157,15 +158,17 @@ __device__ __forceinline__ void layer1_cell(const float* __restrict__ x, const f
     }
 }
 
-// layer 1: a1 = tanh(conv(x; W1) + b1), x planar [2][HW], a1 grouped and split
+// layer 1: a1 = tanh(conv(x; W1) + b1c), x planar [2][HW], a1 grouped and split; b1c the
+// bias with the step-size term (k_cond_bias)
 __global__ __launch_bounds__(256) void k_in_fwd(const float* __restrict__ x, const float* __restrict__ q,
-                                                float* __restrict__ a1, int ny, int nx) {
+                                                const float* __restrict__ b1c, float* __restrict__ a1, int ny,
+                                                int nx) {
     const long HW = (long)ny * nx;
     const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;   // one cell per thread
     if (p >= HW) return;
     const int y = (int)(p / nx), xx = (int)(p - (long)y * nx);
     uint4 o[NG];
-    layer1_cell(x, q, HW, ny, nx, y, xx, o);
+    layer1_cell(x, q, b1c, HW, ny, nx, y, xx, o);
 #pragma unroll
     for (int g = 0; g < NG; ++g) *grp(a1, g, HW, p) = o[g];
 }
@@ -733,6 +736,25 @@ __global__ void k_wreduce(const float* __restrict__ part, int nblocks, int n, fl
     grad[k] = accumulate ? grad[k] + s : s;
 }
 
+// Gradient of the step-size weights u1: z_1 depends on b1 + c u1, so d/du1 = c d/db1.  The
+// layer-1 bias partials (entries koff..koff+WID of each block's row of n) are summed in the
+// order k_wreduce sums them.
+__global__ void k_ureduce(const float* __restrict__ part, int nblocks, int n, int koff, float c,
+                          float* __restrict__ grad, int accumulate) {
+    const int k = threadIdx.x;
+    if (k >= WID) return;
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += part[(long)b * n + koff + k];
+    grad[k] = accumulate ? grad[k] + c * s : c * s;
+}
+
+// b1c = b1 + c u1: layer 1's bias with the constant step-size plane folded in (its 3x3 taps
+// sum to u1, so over a constant plane c the convolution adds c u1)
+__global__ void k_cond_bias(const float* __restrict__ q, float c, float* __restrict__ b1c) {
+    const int k = threadIdx.x;
+    if (k < WID) b1c[k] = q[OFF_B1 + k] + c * q[OFF_U1 + k];
+}
+
 __global__ void k_adam(float* __restrict__ theta, const float* __restrict__ grad, float* __restrict__ m,
                        float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -746,8 +768,10 @@ __global__ void k_adam(float* __restrict__ theta, const float* __restrict__ grad
 }
 
 // solver side: network input planes and the guess
+// x[0] = (phi - mean)/s_a, x[1] = ratio (phi - prev) * inv_x1; every block sums the mean's
+// partials in the same order
 __global__ __launch_bounds__(256) void k_net_input(const double* __restrict__ phi, const double* __restrict__ prev,
-                                                   long n, double ratio, double inv_sa, double inv_sb,
+                                                   long n, double ratio, double inv_sa, double inv_x1,
                                                    const double* __restrict__ sum_part, int np,
                                                    float* __restrict__ x) {
     __shared__ double red[4];
@@ -755,7 +779,7 @@ __global__ __launch_bounds__(256) void k_net_input(const double* __restrict__ ph
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const double f = phi[i];
         x[i] = (float)((f - mean) * inv_sa);
-        x[n + i] = (float)(ratio * (f - prev[i]) * inv_sb);
+        x[n + i] = (float)(ratio * (f - prev[i]) * inv_x1);
     }
 }
 
@@ -775,6 +799,7 @@ struct pfc_net {
     hipStream_t stream = nullptr;
     float* d_theta = nullptr;   // master parameters
     float* d_q = nullptr;       // rounded weights + biases
+    float* d_b1c = nullptr;     // layer-1 bias with the step-size term, b1 + c u1
     unsigned short* d_pack = nullptr;
     float* d_grad = nullptr;
     float* d_m = nullptr;
@@ -859,7 +884,7 @@ unsigned conv_grid(const pfc_net* net, int ny, int nx) {   // persistent: one bl
 pfc_status forward_into(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* y_out, float* a1,
                         float* a2, float* a3) {
     const long HW = (long)ny * nx;
-    hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, a1, ny, nx);
+    hipLaunchKernelGGL(k_in_fwd, dim3(cell_grid(HW)), dim3(256), 0, s, x, net->d_q, net->d_b1c, a1, ny, nx);
     hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a1, pack_of(net, 0),
                        net->d_q + OFF_B2, nullptr, nullptr, a2, ny, nx);
     hipLaunchKernelGGL(k_conv32_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
@@ -871,26 +896,30 @@ pfc_status forward_into(pfc_net* net, hipStream_t s, const float* x, int ny, int
 
 // inference pass on stream s, three kernels: layers 1-2 (a1 stays in LDS) into a2 (32 HW
 // floats), layer 3 with the output layer's per-tap sums into taps (9 HW floats; a3 is never
-// stored), and the output sum.  Output y_out, or X = phi + s_o y when X is given.
-pfc_status infer_into(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* a2, float* taps,
-                      float* y_out, const double* phi, double s_o, double* X, double* diff_part = nullptr) {
+// stored), and the output sum.  b1c: layer 1's conditioned bias.  Output y_out, or
+// X = phi + s_o y when X is given.
+pfc_status infer_into(pfc_net* net, hipStream_t s, const float* x, const float* b1c, int ny, int nx, float* a2,
+                      float* taps, float* y_out, const double* phi, double s_o, double* X,
+                      double* diff_part = nullptr) {
     const long HW = (long)ny * nx;
-    hipLaunchKernelGGL(k_conv12_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, x, pack1_of(net),
-                       net->d_q + OFF_B1, pack_of(net, 0), net->d_q + OFF_B2, a2, ny, nx);
+    hipLaunchKernelGGL(k_conv12_fwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, x, pack1_of(net), b1c,
+                       pack_of(net, 0), net->d_q + OFF_B2, a2, ny, nx);
     hipLaunchKernelGGL(k_conv32_taps, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, a2, pack_of(net, 2),
                        net->d_q + OFF_B3, nullptr, pack_of(net, 4), taps, ny, nx);
     const dim3 sum_grid = diff_part ? dim3(kRedBlocks) : dim3(cell_grid(HW));
-    hipLaunchKernelGGL(k_out_sum, sum_grid, dim3(256), 0, s, taps, net->d_q, ny, nx, y_out, phi, s_o, X, diff_part);
+    hipLaunchKernelGGL(k_out_sum, sum_grid, dim3(256), 0, s, taps, net->d_q, ny, nx, y_out, phi, s_o, X,
+                       diff_part);
     NETCHK(hipGetLastError());
     return PFC_OK;
 }
 
 // forward pass on stream s with the network's own activation buffers (kept for a backward pass)
-pfc_status forward_impl(pfc_net* net, hipStream_t s, const float* x, int ny, int nx, float* y_out) {
+pfc_status forward_impl(pfc_net* net, hipStream_t s, const float* x, double cond, int ny, int nx, float* y_out) {
     pfc_status st = ensure(net, (long)ny * nx);
     if (st != PFC_OK) return st;
     st = prepare(net, s);
     if (st != PFC_OK) return st;
+    hipLaunchKernelGGL(k_cond_bias, dim3(1), dim3(64), 0, s, net->d_q, (float)cond, net->d_b1c);
     return forward_into(net, s, x, ny, nx, y_out, net->a1, net->a2, net->a3);
 }
 
@@ -907,19 +936,22 @@ pfc_status wgrad(pfc_net* net, const float* g, const float* a, int ny, int nx, i
 }  // namespace
 
 namespace pfc {
-// for the solver: learned initial guess X = phi + s_o * net(x(phi, prev)), before the mass shift
+// for the solver: learned initial guess X = phi + out_scale net(x(phi, prev); c), before the
+// mass shift; sum_part holds np partial sums of phi
 pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
-                     double ratio, const double* scales, const double* sum_part, int np, const NetWork& w,
-                     double* X, double* diff_part) {
+                     double ratio, double cond, double inv_sa, double inv_x1, double out_scale,
+                     const double* sum_part, int np, const NetWork& w, double* X, double* diff_part) {
     const long n = (long)ny * nx;
     if (!net->prepared) {
         net->err = "network parameters changed since pfc_attach_net: attach it again";
         return PFC_EINVAL;
     }
-    hipLaunchKernelGGL(k_net_input, dim3(grid_for(n)), dim3(256), 0, s, phi, prev, n, ratio, 1.0 / scales[0],
-                       1.0 / scales[1], sum_part, np, w.x);
+    hipLaunchKernelGGL(k_cond_bias, dim3(1), dim3(64), 0, s, net->d_q, (float)cond, w.b1c);
+    hipLaunchKernelGGL(k_net_input, dim3(grid_for(n)), dim3(256), 0, s, phi, prev, n, ratio, inv_sa, inv_x1,
+                       sum_part, np, w.x);
     static_assert(kNetWorkFloats == WID + 9, "inference workspace: a2, then the tap sums");
-    return infer_into(net, s, w.x, ny, nx, w.a, w.a + (size_t)WID * n, nullptr, phi, scales[2], X, diff_part);
+    return infer_into(net, s, w.x, w.b1c, ny, nx, w.a, w.a + (size_t)WID * n, nullptr, phi, out_scale, X,
+                      diff_part);
 }
 
 pfc_status net_prepare(pfc_net* net) {
@@ -941,6 +973,7 @@ pfc_status pfc_net_create(void* stream, pfc_net** out) {
     net->stream = (hipStream_t)stream;
     bool ok = hipMalloc((void**)&net->d_theta, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_q, sizeof(float) * NPARAM) == hipSuccess &&
+              hipMalloc((void**)&net->d_b1c, sizeof(float) * WID) == hipSuccess &&
               hipMalloc((void**)&net->d_pack, sizeof(unsigned short) * PACK_ALL * 8) == hipSuccess &&
               hipMalloc((void**)&net->d_grad, sizeof(float) * NPARAM) == hipSuccess &&
               hipMalloc((void**)&net->d_m, sizeof(float) * NPARAM) == hipSuccess &&
@@ -974,7 +1007,8 @@ pfc_status pfc_net_create(void* stream, pfc_net** out) {
 void pfc_net_destroy(pfc_net* net) {
     if (!net) return;
     free_acts(net);
-    void* ptrs[] = {net->d_theta, net->d_q, net->d_pack, net->d_grad, net->d_m, net->d_v, net->d_wpart, net->d_lpart};
+    void* ptrs[] = {net->d_theta, net->d_q, net->d_b1c, net->d_pack, net->d_grad, net->d_m, net->d_v,
+                    net->d_wpart, net->d_lpart};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (net->h_lpart) (void)hipHostFree(net->h_lpart);
@@ -1001,9 +1035,9 @@ pfc_status pfc_net_get_params(pfc_net* net, float* host_params) {
     return PFC_OK;
 }
 
-pfc_status pfc_net_forward(pfc_net* net, const float* x, int ny, int nx, float* y) {
+pfc_status pfc_net_forward(pfc_net* net, const float* x, double cond, int ny, int nx, float* y) {
     if (!net) return PFC_EINVAL;
-    if (!x || !y || ny < 3 || nx < 3) {
+    if (!x || !y || ny < 3 || nx < 3 || !std::isfinite(cond)) {
         net->err = "bad argument";
         return PFC_EINVAL;
     }
@@ -1011,13 +1045,14 @@ pfc_status pfc_net_forward(pfc_net* net, const float* x, int ny, int nx, float* 
     if (st != PFC_OK) return st;
     st = prepare(net, net->stream);
     if (st != PFC_OK) return st;
-    return infer_into(net, net->stream, x, ny, nx, net->a2, net->a3, y, nullptr, 0.0, nullptr);
+    hipLaunchKernelGGL(k_cond_bias, dim3(1), dim3(64), 0, net->stream, net->d_q, (float)cond, net->d_b1c);
+    return infer_into(net, net->stream, x, net->d_b1c, ny, nx, net->a2, net->a3, y, nullptr, 0.0, nullptr);
 }
 
-pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny, int nx, double scale,
+pfc_status pfc_net_gradient(pfc_net* net, const float* x, double cond, const float* t, int ny, int nx, double scale,
                             int accumulate, double* loss) {
     if (!net) return PFC_EINVAL;
-    if (!x || !t || ny < 3 || nx < 3) {
+    if (!x || !t || ny < 3 || nx < 3 || !std::isfinite(cond)) {
         net->err = "bad argument";
         return PFC_EINVAL;
     }
@@ -1025,7 +1060,7 @@ pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny
     hipStream_t s = net->stream;
     pfc_status st = ensure(net, HW);
     if (st != PFC_OK) return st;
-    st = forward_impl(net, s, x, ny, nx, net->y);
+    st = forward_impl(net, s, x, cond, ny, nx, net->y);
     if (st != PFC_OK) return st;
     hipLaunchKernelGGL(k_loss, dim3(kRedBlocks), dim3(256), 0, s, net->y, t, net->dy, HW,
                        (float)(2.0 * scale / (double)HW), net->d_lpart);
@@ -1041,8 +1076,10 @@ pfc_status pfc_net_gradient(pfc_net* net, const float* x, const float* t, int ny
     if ((st = wgrad<WID, WID>(net, net->b2, net->a1, ny, nx, OFF_W2, accumulate)) != PFC_OK) return st;
     hipLaunchKernelGGL(k_conv32_bwd, dim3(conv_grid(net, ny, nx)), dim3(256), 0, s, net->b2, pack_of(net, 1), nullptr, net->a1,
                        nullptr, net->b1, ny, nx);
-    // layer 1: g1 in b1
+    // layer 1: g1 in b1; then u1 from layer 1's bias partials, still in d_wpart
     if ((st = wgrad<WID, CIN>(net, net->b1, x, ny, nx, OFF_W1, accumulate)) != PFC_OK) return st;
+    hipLaunchKernelGGL(k_ureduce, dim3(1), dim3(64), 0, s, net->d_wpart, WG_BLOCKS, WID * CIN * 9 + WID,
+                       WID * CIN * 9, (float)cond, net->d_grad + OFF_U1, accumulate);
     NETCHK(hipGetLastError());
     if (loss) {
         NETCHK(hipMemcpyAsync(net->h_lpart, net->d_lpart, sizeof(double) * kRedBlocks, hipMemcpyDeviceToHost, s));

@@ -86,6 +86,7 @@ struct NetWork {
     float* x = nullptr;    // input planes [2][N]
     float* a = nullptr;    // second-layer activations, 32 channels x N (16 bytes per 4 channels),
                            // then the output layer's 9 per-tap sum planes of N
+    float* b1c = nullptr;  // layer-1 bias with the step-size term (32 floats)
 };
 constexpr int kNetWorkFloats = 32 + 9;   // floats of NetWork::a per cell
 
@@ -157,8 +158,8 @@ struct pfc_ctx {
 
     // learned initial guess (pfc_attach_net); the network is not owned
     pfc_net* net = nullptr;
-    double net_scale[3] = {1.0, 1.0, 1.0};   // s_a, s_b, s_o
-    double net_dt = 0.0;                     // time step of the training data
+    double net_scale[6] = {1.0, 1.0, 1.0, 1.0, 0.0, 0.0};   // s_a, s_b, s_o, s_c, beta, gamma
+    double net_dt[3] = {0.0, 0.0, 0.0};      // dt_ref, and the range [dt_lo, dt_hi] it is used in
     pfc::NetWork netw;                       // inference buffers
 
     // HIP graphs of the Arnoldi steps (opts.use_graph): one per Krylov index, valid for arn_dt
@@ -265,12 +266,12 @@ hipError_t launch_lu_apply(pfc_ctx* c, const double* r, double* z, double* sum_p
 hipError_t launch_schwarz_sum(const pfc_ctx* c, const double* zbox, double* z);
 
 // ---- learned initial guess (net.hip) ----
-// X = phi + s_o * net(x), x from phi, prev (mean from sum_part[0..np)), using the buffers w;
-// before the mass shift.  diff_part (nullable) receives kRedBlocks partial sums of phi - X for
+// X = phi + out_scale net(x; c), x[0] = (phi - mean) inv_sa (mean from sum_part[0..np)),
+// x[1] = ratio (phi - prev) inv_x1, c = cond, using the buffers w; before the mass shift.  diff_part (nullable) receives kRedBlocks partial sums of phi - X for
 // that shift.  The network must be prepared (net_prepare) and not trained meanwhile.
 pfc_status net_guess(pfc_net* net, hipStream_t s, const double* phi, const double* prev, int ny, int nx,
-                     double ratio, const double* scales, const double* sum_part, int np, const NetWork& w,
-                     double* X, double* diff_part);
+                     double ratio, double cond, double inv_sa, double inv_x1, double out_scale,
+                     const double* sum_part, int np, const NetWork& w, double* X, double* diff_part);
 // Round and pack the current parameters for inference (synchronises the network's stream).
 pfc_status net_prepare(pfc_net* net);
 const char* net_error(const pfc_net* net);

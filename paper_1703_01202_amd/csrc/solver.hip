@@ -544,7 +544,7 @@ pfc_status dalloc(pfc_ctx* c, T** p, size_t count) {
 void free_all(pfc_ctx* c) {
     void* ptrs[] = {c->d_level_ptr, c->d_level_pts, c->d_work, c->d_fac, c->d_flag, c->d_c, c->d_u, c->d_mu,
                     c->d_F, c->d_X, c->d_T, c->d_S, c->d_w, c->d_r, c->d_V, c->d_Z, c->d_prev,
-                    c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.a, c->d_zbox};
+                    c->d_tmp3, c->d_part, c->d_scal, c->netw.x, c->netw.a, c->netw.b1c, c->d_zbox};
     for (void* p : ptrs)
         if (p) hipFree(p);
     drop_graphs(c);
@@ -556,21 +556,22 @@ void free_all(pfc_ctx* c) {
 }
 
 // Which initial guess this step uses: the learned one when a network is attached, the
-// history exists and dt is within 20% of the network's training step; otherwise linear
-// extrapolation when asked for (or as the learned guess's fallback) and the history exists;
-// otherwise the previous solution (the paper's choice, Sec. 4).
+// history exists and dt is within the range of step sizes the network was trained on;
+// otherwise linear extrapolation when asked for (or as the learned guess's fallback) and the
+// history exists; otherwise the previous solution (the paper's choice, Sec. 4).
 int guess_kind(const pfc_ctx* c, double dt) {
     const int g = c->opts.guess;
     if (!c->have_prev) return PFC_GUESS_PREVIOUS;
-    if (g == PFC_GUESS_LEARNED && c->net && std::fabs(dt - c->net_dt) <= 0.2 * c->net_dt) return PFC_GUESS_LEARNED;
+    if (g == PFC_GUESS_LEARNED && c->net && dt >= c->net_dt[1] && dt <= c->net_dt[2]) return PFC_GUESS_LEARNED;
     if (g == PFC_GUESS_EXTRAP || g == PFC_GUESS_LEARNED) return PFC_GUESS_EXTRAP;
     return PFC_GUESS_PREVIOUS;
 }
 
-// X = initial guess of kind `used` for the step phi^n -> phi^(n+1), from phi = phi^n,
-// prev = phi^(n-1) and ratio = dt_n / dt_(n-1); the extrapolated and learned guesses are
-// shifted to the mass of phi^n when mass_project is set.
-pfc_status guess_into(pfc_ctx* c, const double* phi, const double* prev, double ratio, int used, double* X) {
+// X = initial guess of kind `used` for the step phi^n -> phi^(n+1) of size dt, from
+// phi = phi^n, prev = phi^(n-1) and ratio = dt_n / dt_(n-1); the extrapolated and learned
+// guesses are shifted to the mass of phi^n when mass_project is set.
+pfc_status guess_into(pfc_ctx* c, const double* phi, const double* prev, double dt, double ratio, int used,
+                      double* X) {
     const long N = c->g.N;
     if (used == PFC_GUESS_PREVIOUS) {
         HIPCHK(hipMemcpyAsync(X, phi, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
@@ -582,8 +583,11 @@ pfc_status guess_into(pfc_ctx* c, const double* phi, const double* prev, double 
         double* part = part_md1(c);
         HIPCHK(launch_dot(c->stream, phi, nullptr, N, part));
         double* diff = c->opts.mass_project ? part_md2(c) : nullptr;   // partials of phi - X
-        pfc_status s = net_guess(c->net, c->stream, phi, prev, c->g.ny, c->g.nx, ratio, c->net_scale,
-                                 part, kRedBlocks, c->netw, X, diff);
+        // l = ln(dt/dt_ref), step scale g = exp(beta l + gamma l^2), condition c = l/s_c
+        const double* sc = c->net_scale;
+        const double l = std::log(dt / c->net_dt[0]), g = std::exp(sc[4] * l + sc[5] * l * l);
+        pfc_status s = net_guess(c->net, c->stream, phi, prev, c->g.ny, c->g.nx, ratio, l / sc[3], 1.0 / sc[0],
+                                 1.0 / (sc[1] * g), sc[2] * g, part, kRedBlocks, c->netw, X, diff);
         if (s != PFC_OK) return fail(c, s, std::string("learned guess: ") + net_error(c->net));
         if (diff) HIPCHK(launch_shift(c->stream, X, diff, kRedBlocks, 1.0 / (double)N, N));
         return PFC_OK;
@@ -597,7 +601,7 @@ pfc_status guess_into(pfc_ctx* c, const double* phi, const double* prev, double 
 
 // d_X = the guess of kind `used` for the step of size dt from the stored history.
 pfc_status make_guess(pfc_ctx* c, const double* phi, double dt, int used) {
-    return guess_into(c, phi, c->d_prev, used == PFC_GUESS_PREVIOUS ? 1.0 : dt / c->dt_nm1, used, c->d_X);
+    return guess_into(c, phi, c->d_prev, dt, used == PFC_GUESS_PREVIOUS ? 1.0 : dt / c->dt_nm1, used, c->d_X);
 }
 
 }  // namespace
@@ -1054,28 +1058,33 @@ pfc_status pfc_guess(pfc_ctx* c, int kind, const double* phi, const double* phi_
     if (kind != PFC_GUESS_PREVIOUS && (!phi_prev || !(dt > 0) || !(dt_prev > 0)))
         return fail(c, PFC_EINVAL, "the extrapolated and learned guesses need phi_prev and positive dt, dt_prev");
     if (kind == PFC_GUESS_LEARNED && !c->net) return fail(c, PFC_EINVAL, "no network attached");
-    return guess_into(c, phi, phi_prev, kind == PFC_GUESS_PREVIOUS ? 1.0 : dt / dt_prev, kind, X);
+    return guess_into(c, phi, phi_prev, dt, kind == PFC_GUESS_PREVIOUS ? 1.0 : dt / dt_prev, kind, X);
 }
 
-pfc_status pfc_attach_net(pfc_ctx* c, pfc_net* net, const double* scales, double dt_train) {
+pfc_status pfc_attach_net(pfc_ctx* c, pfc_net* net, const double* scales, const double* dt_range) {
     if (!c) return PFC_EINVAL;
     if (!net) {
         c->net = nullptr;
         return PFC_OK;
     }
     if (c->g.dim != 2) return fail(c, PFC_EUNSUP, "the learned guess is built for 2-D grids");
-    if (!scales || !(scales[0] > 0) || !(scales[1] > 0) || !(scales[2] > 0) || !(dt_train > 0))
-        return fail(c, PFC_EINVAL, "scales and dt_train must be positive");
+    bool sc_ok = scales != nullptr;
+    for (int i = 0; sc_ok && i < 6; ++i) sc_ok = std::isfinite(scales[i]) && (i >= 4 || scales[i] > 0);
+    if (!sc_ok) return fail(c, PFC_EINVAL, "scales must be finite, s_a, s_b, s_o, s_c positive");
+    if (!dt_range || !(dt_range[0] > 0) || !(dt_range[1] > 0) || !(dt_range[2] >= dt_range[1]) ||
+        !std::isfinite(dt_range[0]) || !std::isfinite(dt_range[2]))
+        return fail(c, PFC_EINVAL, "dt_range must be dt_ref > 0 and 0 < dt_lo <= dt_hi, finite");
     if (!c->netw.x) {
         const size_t N = (size_t)c->g.N;
         if (hipMalloc((void**)&c->netw.x, sizeof(float) * 2 * N) != hipSuccess ||
-            hipMalloc((void**)&c->netw.a, sizeof(float) * kNetWorkFloats * N) != hipSuccess)
+            hipMalloc((void**)&c->netw.a, sizeof(float) * kNetWorkFloats * N) != hipSuccess ||
+            hipMalloc((void**)&c->netw.b1c, sizeof(float) * 32) != hipSuccess)
             return fail(c, PFC_ENOMEM, "out of device memory for the network buffers");
     }
     if (net_prepare(net) != PFC_OK) return fail(c, PFC_EHIP, std::string("network: ") + net_error(net));
     c->net = net;
-    for (int i = 0; i < 3; ++i) c->net_scale[i] = scales[i];
-    c->net_dt = dt_train;
+    for (int i = 0; i < 6; ++i) c->net_scale[i] = scales[i];
+    for (int i = 0; i < 3; ++i) c->net_dt[i] = dt_range[i];
     return PFC_OK;
 }
 

@@ -38,11 +38,11 @@ def pfc():
     return m
 
 
-SCALES = (0.3, 0.01, 0.002)
+SCALES = (0.3, 0.01, 0.002, 1.5, 0.7, 0.0)        # s_a, s_b, s_o, s_c, beta, gamma
 
 
 def _net(pfc):
-    theta = cnn.init_params(31, out_scale=0.1).astype(np.float32)
+    theta = cnn.init_params(31, out_scale=0.1, cond_scale=0.5).astype(np.float32)
     return pfc.GuessNet(theta)
 
 
@@ -51,7 +51,7 @@ def _headline_solver(pfc, w, sub, stream, net):
                    precond_fp32=True, precond_lag=100, guess="learned", use_graph=True, dt_min=w.dt_min,
                    dt_max=w.dt_max, eta=w.eta, newton_rtol=w.newton_rtol, newton_atol=w.newton_atol,
                    lin_rtol=w.lin_rtol, lin_atol=w.lin_atol)
-    s.attach_net(net, SCALES, w.dt_min)
+    s.attach_net(net, SCALES, (0.1, w.dt_min, w.dt_max))
     return s
 
 

@@ -442,12 +442,12 @@ def run_ablation(steps, net, net_meta, tuned):
 
 
 def run_dt_sweep(net, net_meta, tuned, hold=10, growth=1.25, tail=10):
-    """The headline workload over the decades of dt that the adaptive step (Eq. (21)) spans:
+    """The headline workload over the decades of dt that the adaptive step (Eq. (16)) spans:
     a fixed schedule (hold steps at dt_min = 0.01, dt growing by `growth` per step to
     dt_max = 10, tail steps at 10), each step's Newton started from the guess of each kind
     (the learned guess conditioned on the step size).  On this workload the controller itself
     keeps dt at dt_min for as long as a run here lasts (|dE/dt| of the total energy stays far
-    above the ~14 at which Eq. (21) with eta = 5000 lets dt grow), so the schedule stands in
+    above the ~14 at which Eq. (16) with eta = 5000 lets dt grow), so the schedule stands in
     for the late stretch of a long run."""
     import torch
     import pfc_inputs as I

@@ -6,7 +6,7 @@
  * phi^(n+1) - phi^n of one time step of size dt, trained on solver trajectories by the
  * library's own kernels.  Newton's residual test still decides when a step is solved
  * (Eq. (20)), so the accepted solution does not depend on the guess; only the iteration
- * count does.  The adaptive step of Sec. 3 (Eq. (21)) spans decades of dt, so dt is an input.
+ * count does.  The adaptive step of Sec. 3 (Eq. (16)) spans decades of dt, so dt is an input.
  *
  * Network (fixed architecture)
  *   input  x: two planes, [2][ny][nx] FP32, periodic in both axes, and a condition c (the

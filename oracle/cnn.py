@@ -7,7 +7,7 @@ The paper solves each time step by Newton from the previous solution (Sec. 4); t
 network here is an addition that predicts the time increment phi^(n+1) - phi^n from
 planes built from the history and the step size, so that Newton starts closer to its root.
 Newton's own residual test (Sec. 4, Eq. (20)) still decides when a step is solved, so the
-accepted solution does not depend on the guess.  The adaptive step of Sec. 3 (Eq. (21))
+accepted solution does not depend on the guess.  The adaptive step of Sec. 3 (Eq. (16))
 moves dt over three decades, so the step size is an input of the network.
 
 Definition (what both this reference and the GPU kernels compute)

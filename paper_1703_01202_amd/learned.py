@@ -3,7 +3,7 @@
 Data: trajectories of the crystal-growth problem solved by the library's Newton-Krylov
 solver (exact-LU RAS, FP32 factors) from the previous solution, the method without the
 network.  The step sizes of a trajectory follow a schedule that holds dt at dt_min, then
-grows it geometrically to dt_max and holds it there, as the adaptive step of Eq. (21) does
+grows it geometrically to dt_max and holds it there, as the adaptive step of Eq. (16) does
 while the system relaxes; the growth factor differs between trajectories.  Each step
 n -> n+1 with a predecessor gives one sample: with d = r (phi^n - phi^(n-1)),
 r = dt_n / dt_(n-1), l = ln(dt_n / dt_ref) and the step scale g = exp(beta l + gamma l^2),

@@ -187,7 +187,7 @@ def test_trained_network_gains_over_the_method_without_it(pfc):
     """Train on solver runs of the crystal-growth physics at 128^2 (same mesh size as the
     1024^2 workload) whose step sizes sweep dt_min = 0.01 .. dt_max = 10, then solve a held-out
     problem two ways with the previous-step guess (the paper's), linear extrapolation and
-    the learned guess: (a) 40 adaptive steps (Eq. (21); dt stays at dt_min there), and (b) a
+    the learned guess: (a) 40 adaptive steps (Eq. (16); dt stays at dt_min there), and (b) a
     step schedule from dt_min up to dt_max with Newton started from each guess.  The learned
     guess must start Newton closer to the root at every step size (initial residual at most
     half of F(phi^n) in each decade band) and save Newton iterations, while every variant

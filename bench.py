@@ -488,6 +488,46 @@ def run_dt_sweep(net, net_meta, tuned, hold=10, growth=1.25, tail=10):
     return out
 
 
+def run_stencil_sizes(reps=20):
+    """The residual and Jacobian-action kernels alone at 1024^2, 2048^2, 4096^2 (2-D: LDS tiles
+    below 2^21 cells, sliding sweeps above) and 128^3 (3-D multi-pass), each timed with events
+    over `reps` calls after 3 untimed ones; 24 algorithmic bytes per cell (two fields read,
+    one written)."""
+    import math
+    import torch
+    import paper_1703_01202_amd as pfc
+    out = []
+    for shape, sub in (((1024, 1024), (32, 32)), ((2048, 2048), (32, 32)), ((4096, 4096), (32, 32)),
+                       ((128, 128, 128), (8, 8, 8))):
+        L = tuple(400.0 * n / 1024 for n in shape) if len(shape) == 2 else (40 * math.pi,) * 3
+        s = pfc.Solver(shape, L, 0.25, sub, 2, timing=2 | 4, gmres_restart=2)
+        g = torch.Generator(device="cuda").manual_seed(0)
+        phi = -0.285 + 0.3 * torch.rand(shape, dtype=torch.float64, device="cuda", generator=g)
+        Phi = phi + 0.01 * torch.randn(shape, dtype=torch.float64, device="cuda", generator=g)
+        v = torch.randn(shape, dtype=torch.float64, device="cuda", generator=g)
+        F, J = torch.empty_like(phi), torch.empty_like(phi)
+        for _ in range(3):
+            s.residual(Phi, phi, 0.1, out=F, want_norm=False)
+            s.jv(Phi, phi, 0.1, v, out=J)
+        s.reset()
+        for _ in range(reps):
+            s.residual(Phi, phi, 0.1, out=F, want_norm=False)
+            s.jv(Phi, phi, 0.1, v, out=J)
+        N = phi.numel()
+        row = {"shape": list(shape)}
+        for k, name in ((1, "residual"), (2, "jacobian_action")):
+            cnt, ms = s.kernel_time(k)
+            us = ms / cnt * 1e3
+            row[name] = {"avg_us": us, "achieved_GBs": 24 * N / us / 1e3, "frac": 24 * N / us / 1e3 / PEAK_HBM_GBS}
+        s.close()
+        del phi, Phi, v, F, J
+        torch.cuda.empty_cache()
+        out.append(row)
+        print(f"[bench] stencils {shape}: residual {row['residual']['avg_us']:.1f} us, "
+              f"Jv {row['jacobian_action']['avg_us']:.1f} us", file=sys.stderr, flush=True)
+    return out
+
+
 def run_crack(steps):
     """Test C's grid: 4096 x 1024 on [0, 4096 pi/3] x [0, 1024 pi/3], the notched lattice, gamma 1,
     adaptive dt 1..5 (eta 100); FP32 exact-LU subdomain solves on 16 x 64 boxes of 64 x 64 owned
@@ -609,6 +649,8 @@ def main():
     ap.add_argument("--steps-crack", type=int, default=20, help="steps of the 4096x1024 test-C grid (0 skips it)")
     ap.add_argument("--steps-ablation", type=int, default=20,
                     help="steps of each guess x factor precision x lag combination (0 skips the ablation)")
+    ap.add_argument("--no-stencil-sizes", action="store_true",
+                    help="skip the residual / Jacobian-action timings at 1024^2..4096^2 and 128^3")
     ap.add_argument("--no-dt-sweep", action="store_true",
                     help="skip the guess comparison over a dt schedule from 0.01 to 10")
     ap.add_argument("--steps-3d", type=int, default=50)
@@ -662,6 +704,7 @@ def main():
     ablation = run_ablation(args.steps_ablation, net, net_meta, tuned) \
         if args.steps_ablation > 0 and net is not None else None
     dt_sweep = run_dt_sweep(net, net_meta, tuned) if not args.no_dt_sweep and net is not None else None
+    stencil_sizes = None if args.no_stencil_sizes else run_stencil_sizes()
     out = {
         "metric": "PFC time steps/s & HBM GB/s, 2D 1024^2 NKS; learned+FP32-precond vs plain",
         "value": main_res["steps_per_s"],
@@ -714,6 +757,8 @@ def main():
         out["detail"]["ablation_guess_precision_lag"] = ablation
     if dt_sweep is not None:
         out["detail"]["dt_sweep_guess"] = dt_sweep
+    if stencil_sizes is not None:
+        out["detail"]["stencil_sizes"] = stencil_sizes
     print(json.dumps(out), flush=True)
 
 

@@ -205,6 +205,7 @@ inline hipError_t set_dynamic_lds_limit(const void* f) {
 // ---- stencil kernels (stencil.hip) ----
 // Reductions leave per-block partials (device_reduce.h); partial_count gives their number.
 bool fused2d(const pfc_ctx* c);                 // 2-D, M = 1, periodic: the single-kernel stencils
+bool fused3d(const pfc_ctx* c);                 // 3-D, M = 1, periodic: the single-kernel stencils
 int residual_partial_count(const pfc_ctx* c);   // blocks of the residual kernel
 // The 2-D residual kernel outside a context: grid nx x ny with 1/h^2 per axis, on stream s;
 // writes residual2d_blocks(nx, ny) (at most 1024) partial sums of F^2 to norm_part.

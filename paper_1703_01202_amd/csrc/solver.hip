@@ -168,7 +168,7 @@ pfc_status shift_by_sum(pfc_ctx* c, double* x, const double* y, double scale) {
 pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, double dt, const double* src,
                          double* F, double* nrm) {
     int ts;
-    timer_begin(c, 1, &ts, fused2d(c));
+    timer_begin(c, 1, &ts, fused2d(c) || fused3d(c));
     HIPCHK(launch_residual(c, Phi, phi, dt, src, F, nrm ? c->d_hpin + SC_P : nullptr, nullptr));
     timer_end(c, ts);
     if (!nrm) return PFC_OK;
@@ -184,7 +184,7 @@ pfc_status residual_impl(pfc_ctx* c, const double* Phi, const double* phi, doubl
 pfc_status jv_impl(pfc_ctx* c, const double* v, double dt, const double* shift_part, double* shift_out,
                    double* out) {
     int ts;
-    timer_begin(c, 2, &ts, fused2d(c));
+    timer_begin(c, 2, &ts, fused2d(c) || fused3d(c));
     HIPCHK(launch_jv(c, v, c->d_c, dt, shift_part, c->dec.nsub, 1.0 / (double)c->g.N, shift_out, out));
     timer_end(c, ts);
     return PFC_OK;

@@ -566,6 +566,229 @@ __global__ void k_mp_final(const double* a, const double* __restrict__ b,
     out[i] = f;
 }
 
+// ---------------------------------------------------------------------------
+// 3-D fused stencils (M = 1, periodic): a block owns a T3X x T3Y column of cells and marches
+// it through a segment of z-planes.  Each plane entering (with a three-cell halo in x and y)
+// is staged in LDS; the three radius-1 stages of the composite operator follow it one plane
+// behind each other, each stage keeping the last three planes it produced in an LDS ring
+// (the z-neighbours), so every field is read from HBM once per column (plus its x-y halo
+// and the three planes above and below a segment) and the result written once, in one
+// launch instead of four passes through memory.  The next plane's loads are issued into
+// registers before the stages of the current plane run, so their latency overlaps them.
+// ---------------------------------------------------------------------------
+
+constexpr int T3X = 32, T3Y = 8;
+constexpr int H3N = (T3X + 6) * (T3Y + 6);   // halo-3 plane
+constexpr int H2N = (T3X + 4) * (T3Y + 4);   // halo-2
+constexpr int H1N = (T3X + 2) * (T3Y + 2);   // halo-1
+constexpr int H0N = T3X * T3Y;               // the column's own cells
+constexpr int DR3 = 5;                       // ring of own-cell planes (read 3 planes after its load)
+constexpr int PF3 = (H3N + NT - 1) / NT;      // halo-3 cells per thread of a plane
+
+struct Geom3 {
+    int ntx, nty, zseg, nseg, items;
+};
+
+__host__ __device__ inline Geom3 geom3(int nx, int ny, int nz) {
+    Geom3 g;
+    g.ntx = (nx + T3X - 1) / T3X;
+    g.nty = (ny + T3Y - 1) / T3Y;
+    // segments as short as gives ~1024 columns in all, at least 16 planes (6 warm-up planes)
+    const int cols = g.ntx * g.nty;
+    const int want = max(1, 1024 / cols);
+    g.zseg = max(16, (nz + want - 1) / want);
+    g.nseg = (nz + g.zseg - 1) / g.zseg;
+    g.items = cols * g.nseg;
+    return g;
+}
+
+// five-point x-y Laplacian of plane a (width w) at (i, j), plus the z term from planes zm, zp
+__device__ __forceinline__ double lap3(const double* a, const double* zm, const double* zp, int w, int i, int j,
+                                       const P& p) {
+    const int c = j * w + i;
+    const double ac = a[c];
+    return (a[c + 1] + a[c - 1] - 2.0 * ac) * p.ihx2 + (a[c + w] + a[c - w] - 2.0 * ac) * p.ihy2 +
+           (zm[c] + zp[c] - 2.0 * ac) * p.ihz2;
+}
+
+// F = (Phi - phi)/dt - Delta_d mu_d - src with per-block partial sums of F^2 (and Phi^2).
+__global__ __launch_bounds__(NT) void k_residual3d(const double* __restrict__ Phi, const double* __restrict__ phi,
+                                                   const double* __restrict__ src, double* __restrict__ F,
+                                                   double* __restrict__ part, double* __restrict__ xpart, P p) {
+    __shared__ double U[3][H3N];   // u = (Phi + phi)/2, halo 3
+    __shared__ double Q[3][H1N];   // the cubic term, halo 1
+    __shared__ double L[3][H2N];   // Delta_d u, halo 2
+    __shared__ double M[3][H1N];   // mu_d, halo 1
+    __shared__ double D[DR3][H0N]; // Phi - phi, own cells
+    __shared__ double red[NT / 64];
+    const Geom3 G = geom3(p.nx, p.ny, p.nz);
+    const long sxy = (long)p.nx * p.ny;
+    const int tid = threadIdx.x;
+    double acc = 0.0, accx = 0.0;
+    for (int it = blockIdx.x; it < G.items; it += gridDim.x) {
+        const int col = it % (G.ntx * G.nty), sg = it / (G.ntx * G.nty);
+        const int x0 = (col % G.ntx) * T3X, y0 = (col / G.ntx) * T3Y;
+        const int z0 = sg * G.zseg, z1 = min(z0 + G.zseg, p.nz);
+        const int nk = z1 - z0 + 6;
+        double pa[PF3], pb[PF3];   // the next plane's Phi, phi at this thread's halo-3 cells
+        auto fetch = [&](int zin) {
+            const long zoff = (long)wrap(zin, p.nz) * sxy;
+#pragma unroll
+            for (int r = 0; r < PF3; ++r) {
+                const int e = tid + NT * r;
+                if (e < H3N) {
+                    const int i = e % (T3X + 6), j = e / (T3X + 6);
+                    const long gi = zoff + (long)wrap(y0 - 3 + j, p.ny) * p.nx + wrap(x0 - 3 + i, p.nx);
+                    pa[r] = Phi[gi];
+                    pb[r] = phi[gi];
+                }
+            }
+        };
+        fetch(z0 - 3);
+        __syncthreads();   // the previous item's last reads of the rings
+        for (int k = 0; k < nk; ++k) {
+            const int zin = z0 - 3 + k;
+            // A: plane zin enters (from the registers), and the next plane's loads go out
+#pragma unroll
+            for (int r = 0; r < PF3; ++r) {
+                const int e = tid + NT * r;
+                if (e >= H3N) break;
+                const int i = e % (T3X + 6), j = e / (T3X + 6);
+                const double a = pa[r], b = pb[r];
+                U[k % 3][e] = 0.5 * (a + b);
+                if (i >= 2 && i < T3X + 4 && j >= 2 && j < T3Y + 4)
+                    Q[k % 3][(j - 2) * (T3X + 2) + i - 2] = 0.25 * (a * a * a + a * a * b + a * b * b + b * b * b);
+                if (i >= 3 && i < T3X + 3 && j >= 3 && j < T3Y + 3) {
+                    D[k % DR3][(j - 3) * T3X + i - 3] = a - b;
+                    if (xpart && zin >= z0 && zin < z1 && x0 + i - 3 < p.nx && y0 + j - 3 < p.ny) accx += a * a;
+                }
+            }
+            if (k + 1 < nk) fetch(zin + 1);
+            __syncthreads();
+            // B: Lu at plane zin - 1 (halo 2)
+            if (k >= 2)
+                for (int e = tid; e < H2N; e += NT) {
+                    const int i = e % (T3X + 4), j = e / (T3X + 4);
+                    L[(k - 1) % 3][e] = lap3(U[(k - 1) % 3], U[(k - 2) % 3], U[k % 3], T3X + 6, i + 1, j + 1, p);
+                }
+            __syncthreads();
+            // C: mu at plane zin - 2 (halo 1)
+            if (k >= 4)
+                for (int e = tid; e < H1N; e += NT) {
+                    const int i = e % (T3X + 2), j = e / (T3X + 2);
+                    const int c2 = (j + 1) * (T3X + 4) + i + 1;
+                    const double l = L[(k - 2) % 3][c2];
+                    const double ll = lap3(L[(k - 2) % 3], L[(k - 3) % 3], L[(k - 1) % 3], T3X + 4, i + 1, j + 1, p);
+                    M[(k - 2) % 3][e] = (1.0 - p.gamma) * U[(k - 2) % 3][(j + 2) * (T3X + 6) + i + 2] + 2.0 * l + ll +
+                                        Q[(k - 2) % 3][e];
+                }
+            __syncthreads();
+            // D: F at plane zin - 3 (own cells)
+            if (k >= 6)
+                for (int e = tid; e < H0N; e += NT) {
+                    const int i = e % T3X, j = e / T3X;
+                    const int x = x0 + i, y = y0 + j;
+                    if (x >= p.nx || y >= p.ny) continue;
+                    const double lm = lap3(M[(k - 3) % 3], M[(k - 4) % 3], M[(k - 2) % 3], T3X + 2, i + 1, j + 1, p);
+                    const long gi = (long)(zin - 3) * sxy + (long)y * p.nx + x;
+                    double f = D[(k - 3) % DR3][e] * p.inv_dt - lm;
+                    if (src) f -= src[gi];
+                    F[gi] = f;
+                    acc += f * f;
+                }
+        }
+    }
+    if (part) {
+        const double t = block_sum_det(acc, red);
+        if (threadIdx.x == 0) part[blockIdx.x] = t;
+    }
+    if (xpart) {
+        const double t = block_sum_det(accx, red);
+        if (threadIdx.x == 0) xpart[blockIdx.x] = t;
+    }
+}
+
+// Jv = v/dt - Delta_d[(1-gamma)/2 v + Delta_d v + 1/2 Delta_d^2 v + c v] with v shifted by -s
+// (s as in k_jv2d: from shift_part, every block in the same order, block 0 stores it).
+__global__ __launch_bounds__(NT) void k_jv3d(const double* __restrict__ v, const double* __restrict__ cc,
+                                             const double* __restrict__ shift_part, int shift_n, double shift_scale,
+                                             double* __restrict__ shift_out, double* __restrict__ Jv, P p) {
+    __shared__ double V[3][H3N];   // v - s, halo 3
+    __shared__ double C[3][H1N];   // c, halo 1
+    __shared__ double L[3][H2N];   // Delta_d v, halo 2
+    __shared__ double Wr[3][H1N];  // the inner operator, halo 1
+    __shared__ double D[DR3][H0N]; // v - s, own cells
+    __shared__ double red[NT / 64];
+    double sh = 0.0;
+    if (shift_part) {
+        sh = shift_scale * sum_partials_bcast(shift_part, shift_n, red);
+        if (shift_out && threadIdx.x == 0 && blockIdx.x == 0) *shift_out = sh;
+    }
+    const Geom3 G = geom3(p.nx, p.ny, p.nz);
+    const long sxy = (long)p.nx * p.ny;
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < G.items; it += gridDim.x) {
+        const int col = it % (G.ntx * G.nty), sg = it / (G.ntx * G.nty);
+        const int x0 = (col % G.ntx) * T3X, y0 = (col / G.ntx) * T3Y;
+        const int z0 = sg * G.zseg, z1 = min(z0 + G.zseg, p.nz);
+        const int nk = z1 - z0 + 6;
+        double pv[PF3], pc[PF3];   // the next plane's v, c at this thread's halo-3 cells
+        auto fetch = [&](int zin) {
+            const long zoff = (long)wrap(zin, p.nz) * sxy;
+#pragma unroll
+            for (int r = 0; r < PF3; ++r) {
+                const int e = tid + NT * r;
+                if (e < H3N) {
+                    const int i = e % (T3X + 6), j = e / (T3X + 6);
+                    const long gi = zoff + (long)wrap(y0 - 3 + j, p.ny) * p.nx + wrap(x0 - 3 + i, p.nx);
+                    pv[r] = v[gi];
+                    pc[r] = cc[gi];
+                }
+            }
+        };
+        fetch(z0 - 3);
+        __syncthreads();
+        for (int k = 0; k < nk; ++k) {
+            const int zin = z0 - 3 + k;
+#pragma unroll
+            for (int r = 0; r < PF3; ++r) {
+                const int e = tid + NT * r;
+                if (e >= H3N) break;
+                const int i = e % (T3X + 6), j = e / (T3X + 6);
+                const double a = pv[r] - sh;
+                V[k % 3][e] = a;
+                if (i >= 2 && i < T3X + 4 && j >= 2 && j < T3Y + 4) C[k % 3][(j - 2) * (T3X + 2) + i - 2] = pc[r];
+                if (i >= 3 && i < T3X + 3 && j >= 3 && j < T3Y + 3) D[k % DR3][(j - 3) * T3X + i - 3] = a;
+            }
+            if (k + 1 < nk) fetch(zin + 1);
+            __syncthreads();
+            if (k >= 2)
+                for (int e = tid; e < H2N; e += NT) {
+                    const int i = e % (T3X + 4), j = e / (T3X + 4);
+                    L[(k - 1) % 3][e] = lap3(V[(k - 1) % 3], V[(k - 2) % 3], V[k % 3], T3X + 6, i + 1, j + 1, p);
+                }
+            __syncthreads();
+            if (k >= 4)
+                for (int e = tid; e < H1N; e += NT) {
+                    const int i = e % (T3X + 2), j = e / (T3X + 2);
+                    const double l = L[(k - 2) % 3][(j + 1) * (T3X + 4) + i + 1];
+                    const double ll = lap3(L[(k - 2) % 3], L[(k - 3) % 3], L[(k - 1) % 3], T3X + 4, i + 1, j + 1, p);
+                    const double vv = V[(k - 2) % 3][(j + 2) * (T3X + 6) + i + 2];
+                    Wr[(k - 2) % 3][e] = 0.5 * (1.0 - p.gamma) * vv + l + 0.5 * ll + C[(k - 2) % 3][e] * vv;
+                }
+            __syncthreads();
+            if (k >= 6)
+                for (int e = tid; e < H0N; e += NT) {
+                    const int i = e % T3X, j = e / T3X;
+                    const int x = x0 + i, y = y0 + j;
+                    if (x >= p.nx || y >= p.ny) continue;
+                    const double lw = lap3(Wr[(k - 3) % 3], Wr[(k - 4) % 3], Wr[(k - 2) % 3], T3X + 2, i + 1, j + 1, p);
+                    Jv[(long)(zin - 3) * sxy + (long)y * p.nx + x] = D[(k - 3) % DR3][e] * p.inv_dt - lw;
+                }
+        }
+    }
+}
+
 // The last pass with the variable mobility M(u) = 1 - u^2.  Residual (jv = 0, a = Phi, b = phi,
 // m = mu): F = (Phi - phi)/dt - nabla . M nabla mu - src, u = (Phi + phi)/2 at each node.
 // Jacobian action (jv = 1, a = v, m = the inner operator w, u and mu of the iterate given):
@@ -664,7 +887,13 @@ inline unsigned grid2d(int nx, int ny) {
                                    : (long)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
     return (unsigned)(b < 1024 ? b : 1024);
 }
-dim3 residual_grid(const pfc_ctx* c) { return dim3(grid2d(c->g.nx, c->g.ny)); }
+inline unsigned grid3d(int nx, int ny, int nz) {
+    const int b = geom3(nx, ny, nz).items;
+    return (unsigned)(b < 1024 ? b : 1024);
+}
+dim3 residual_grid(const pfc_ctx* c) {
+    return dim3(c->g.dim == 3 ? grid3d(c->g.nx, c->g.ny, c->g.nz) : grid2d(c->g.nx, c->g.ny));
+}
 dim3 mp_grid(const pfc_ctx* c) { return dim3((c->g.nx + 63) / 64, (c->g.ny + 3) / 4, c->g.nz); }
 
 }  // namespace
@@ -673,7 +902,13 @@ bool fused2d(const pfc_ctx* c) {
     return c->g.dim == 2 && c->model.mobility == PFC_MOBILITY_1 && c->model.boundary == PFC_BC_PERIODIC;
 }
 
-int residual_partial_count(const pfc_ctx* c) { return fused2d(c) ? (int)residual_grid(c).x : kRedBlocks; }
+bool fused3d(const pfc_ctx* c) {
+    return c->g.dim == 3 && c->model.mobility == PFC_MOBILITY_1 && c->model.boundary == PFC_BC_PERIODIC;
+}
+
+int residual_partial_count(const pfc_ctx* c) {
+    return fused2d(c) || fused3d(c) ? (int)residual_grid(c).x : kRedBlocks;
+}
 
 int energy_partial_count(const pfc_ctx* c) { return fused2d(c) ? (int)tiles2d(c).x : kRedBlocks; }
 
@@ -686,6 +921,8 @@ hipError_t launch_residual(const pfc_ctx* c, const double* Phi, const double* ph
                    : launch_k(c, k_residual2d_tile, residual_grid(c), dim3(NT), 0, Phi, phi, src, F, norm_part,
                               xnorm_part, p);
     }
+    if (fused3d(c))
+        return launch_k(c, k_residual3d, residual_grid(c), dim3(NT), 0, Phi, phi, src, F, norm_part, xnorm_part, p);
     if (xnorm_part) hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(NT), 0, c->stream, Phi, c->g.N, xnorm_part);
     double* u = c->d_tmp3;
     double* Lu = c->d_tmp3 + c->g.N;
@@ -728,6 +965,9 @@ hipError_t launch_jv(const pfc_ctx* c, const double* v, const double* cbuf, doub
                    : launch_k(c, k_jv2d_tile, residual_grid(c), dim3(NT), 0, v, cbuf, shift_part, shift_n,
                               shift_scale, shift_out, Jv, p);
     }
+    if (fused3d(c))
+        return launch_k(c, k_jv3d, residual_grid(c), dim3(NT), 0, v, cbuf, shift_part, shift_n, shift_scale, shift_out,
+                        Jv, p);
     // the shifted v lives in the output buffer, the inner operator in the scratch vector, and the
     // last pass updates the output in place (it reads the shifted v at the cell only)
     double* w = c->d_tmp3;

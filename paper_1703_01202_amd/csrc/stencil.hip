@@ -75,6 +75,14 @@ __host__ __device__ inline SwGeom sw_geom(int nx, int ny) {
     return g;
 }
 
+// Work items handed out so that the blocks on one XCD (block b runs on XCD b mod 8 when the
+// grid is a multiple of 8 or one item per block) take one contiguous range of items, and
+// neighbouring items share their halo reads in that XCD's L2.  A bijection on [0, items).
+__device__ __forceinline__ int xcd_item(int it, int items) {
+    const int q = items >> 3, rem = items & 7, x = it & 7, r = it >> 3;
+    return x * q + min(x, rem) + r;
+}
+
 // The value of the next (dpp 0x130, wave_shl:1) or previous (0x138, wave_shr:1) lane of the
 // wave, moved by the data-parallel primitives of the vector ALU (no LDS round trip); a lane
 // with no such neighbour keeps its own value.
@@ -101,9 +109,11 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
     __shared__ double red[NT / 64];
     const SwGeom G = sw_geom(p.nx, p.ny);
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), nwave = gridDim.x * (NT / 64);
+    const int ngroups = (G.items + NT / 64 - 1) / (NT / 64);   // items by groups of a block's waves
     double acc = 0.0, accx = 0.0;
-    for (int it = wave; it < G.items; it += nwave) {
+    for (int gb = blockIdx.x; gb < ngroups; gb += gridDim.x) {
+        const int it = xcd_item(gb, ngroups) * (NT / 64) + (threadIdx.x >> 6);
+        if (it >= G.items) continue;
         const int strip = it % G.nstrip, sg = it / G.nstrip;
         const int xo = strip * SW_OUT + lane - 3;                 // this lane's column
         const int x = wrap(xo, p.nx);
@@ -195,8 +205,10 @@ __global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
     }
     const SwGeom G = sw_geom(p.nx, p.ny);
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), nwave = gridDim.x * (NT / 64);
-    for (int it = wave; it < G.items; it += nwave) {
+    const int ngroups = (G.items + NT / 64 - 1) / (NT / 64);
+    for (int gb = blockIdx.x; gb < ngroups; gb += gridDim.x) {
+        const int it = xcd_item(gb, ngroups) * (NT / 64) + (threadIdx.x >> 6);
+        if (it >= G.items) continue;
         const int strip = it % G.nstrip, sg = it / G.nstrip;
         const int xo = strip * SW_OUT + lane - 3;
         const int x = wrap(xo, p.nx);
@@ -625,7 +637,8 @@ __global__ __launch_bounds__(NT) void k_residual3d(const double* __restrict__ Ph
     const long sxy = (long)p.nx * p.ny;
     const int tid = threadIdx.x;
     double acc = 0.0, accx = 0.0;
-    for (int it = blockIdx.x; it < G.items; it += gridDim.x) {
+    for (int ib = blockIdx.x; ib < G.items; ib += gridDim.x) {
+        const int it = xcd_item(ib, G.items);
         const int col = it % (G.ntx * G.nty), sg = it / (G.ntx * G.nty);
         const int x0 = (col % G.ntx) * T3X, y0 = (col / G.ntx) * T3Y;
         const int z0 = sg * G.zseg, z1 = min(z0 + G.zseg, p.nz);
@@ -727,7 +740,8 @@ __global__ __launch_bounds__(NT) void k_jv3d(const double* __restrict__ v, const
     const Geom3 G = geom3(p.nx, p.ny, p.nz);
     const long sxy = (long)p.nx * p.ny;
     const int tid = threadIdx.x;
-    for (int it = blockIdx.x; it < G.items; it += gridDim.x) {
+    for (int ib = blockIdx.x; ib < G.items; ib += gridDim.x) {
+        const int it = xcd_item(ib, G.items);
         const int col = it % (G.ntx * G.nty), sg = it / (G.ntx * G.nty);
         const int x0 = (col % G.ntx) * T3X, y0 = (col / G.ntx) * T3Y;
         const int z0 = sg * G.zseg, z1 = min(z0 + G.zseg, p.nz);

@@ -200,7 +200,8 @@ __device__ __forceinline__ void tile_product(const double* A, const double* B, i
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-#pragma unroll 4
+    constexpr int UNR = WMAX <= 24 ? 2 : 4;   // the W <= 24 kernel runs four workgroups per CU (128 VGPRs)
+#pragma unroll UNR
     for (int m = 0; m < W; ++m) {
         {
             double av[4], bv[4];
@@ -216,16 +217,19 @@ __device__ __forceinline__ void tile_product(const double* A, const double* B, i
     }
 }
 
-// Boxes of width W <= kSmallW: every block of a step is staged in LDS:
-//   G0, G1 (Gauss-Jordan), A(K+1..K+2, K) -> Pa[2], A(K, K+1..K+2) -> Pb[2], Lh -> Pl[2],
-//   Uh -> Pu[2] (10 W^2 doubles).
+// Boxes of width W <= kSmallW: the blocks of a step are staged in LDS:
+//   G0, G1 (Gauss-Jordan; after it the one not holding S^-1 takes Uh(K,K+1)),
+//   A(K+1..K+2, K) -> Pa[2], A(K, K+1..K+2) -> Pu[2] (Uh(K,K+2) then over A(K,K+1)):
+//   6 W^2 doubles, four workgroups per CU at W = 24.  Lh goes from registers straight to the
+//   factors, and the Schur updates take the form A(I,J) -= A(I,K) Uh(K,J) (equal to
+//   Lh(I,K) A(K,J)), so neither Lh nor A(K,J) has to stay in LDS.
 // The blocks at distance 3, A(K+3, K) and A(K, K+3), are diagonal (the stencil reaches three
 // rows only straight up and down) and no elimination step updates them (a step K' updates
 // blocks within distance 3 of K' on both sides).  So Lh(K+3, K) = diag(dA) S^-1 and
 // Uh(K, K+3) = S^-1 diag(dB) are scalings of S^-1, and the Schur terms that involve them are
 // scalings too: 8 dense W x W products per step instead of 15.
 template <typename T, int WMAX>
-__global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restrict__ cc, double* __restrict__ work,
+__global__ __launch_bounds__(256, WMAX <= 24 ? 4 : 3) void k_lu_factor_lds(const double* __restrict__ cc, double* __restrict__ work,
                                                        T* __restrict__ fac, int* __restrict__ flag, LuBox b,
                                                        StencilTable st, const double* __restrict__ uu) {
     extern __shared__ double lds[];
@@ -233,9 +237,7 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
     double* G0 = lds;
     double* G1 = lds + WW;
     double* Pa = lds + 2 * WW;
-    double* Pb = lds + 4 * WW;
-    double* Pl = lds + 6 * WW;
-    double* Pu = lds + 8 * WW;
+    double* Pu = lds + 4 * WW;   // A(K, K+1..K+2) as staged
     const int k = blockIdx.x;
     const int ox = (k % b.subx) * b.ownx - b.ov, oy = (k / b.subx) * b.owny - b.ov;
     double* win = work + (long)k * 16 * WW;
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
         for (int e = tid; e < nd * WW; e += nt) {
             const int bi = e / WW, r = e - bi * WW;
             Pa[bi * WW + r] = slot(win, K + 1 + bi, K, W)[r];
-            Pb[bi * WW + r] = slot(win, K, K + 1 + bi, W)[r];
+            Pu[bi * WW + r] = slot(win, K, K + 1 + bi, W)[r];
         }
         if (nI == 3)
             for (int q = tid; q < W; q += nt) {
@@ -272,84 +274,93 @@ __global__ __launch_bounds__(256, 3) void k_lu_factor_lds(const double* __restri
             }
         __syncthreads();
         const double* Sinv = gauss_jordan(G0, G1, W, flag);
-        // Lh(I,K) = A(I,K) S^-1 -> Pl and Uh(K,J) = S^-1 A(K,J) -> Pu, I, J = K+1, K+2
-        for (int t = tid; t < 2 * nd * ntile; t += nt) {
-            const int blk = t / ntile, tile = t - blk * ntile;
+        // Lh(I,K) = A(I,K) S^-1, I = K+1, K+2, tile by tile to the factors of row I (column
+        // block 2 - bi), with A(I, K+3) -= Lh(I,K) diag(dB) applied from the same registers.
+        // Uh(K,K+1) = S^-1 A(K,K+1) goes to the Gauss-Jordan buffer that does not hold S^-1,
+        // then Uh(K,K+2) = S^-1 A(K,K+2) over A(K,K+1), which is no longer read.
+        double* Uh0 = Sinv == G0 ? G1 : G0;
+        double* Uh1 = Pu;
+        for (int t = tid; t < (nd + 1) * ntile; t += nt) {
+            const int b = t / ntile, tile = t - b * ntile;
             double acc[4][4];
             int p0, q0;
-            double* dst;
-            if (blk < nd) {
-                tile_product<WMAX>(Pa + blk * WW, Sinv, W, tile, acc, &p0, &q0);
-                dst = Pl + blk * WW;
+            if (b < nd) {
+                tile_product<WMAX>(Pa + b * WW, Sinv, W, tile, acc, &p0, &q0);
+                T* dst = out + (long)(K + 1 + b) * 7 * WW + (2 - b) * WW;
+                double* C3 = nI == 3 ? slot(win, K + 1 + b, K + 3, W) : nullptr;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (p0 + a < W && q0 + c < W) {
+                            dst[(q0 + c) * W + p0 + a] = (T)acc[a][c];
+                            if (C3) C3[(p0 + a) * W + q0 + c] -= acc[a][c] * dB[q0 + c];
+                        }
             } else {
-                tile_product<WMAX>(Sinv, Pb + (blk - nd) * WW, W, tile, acc, &p0, &q0);
-                dst = Pu + (blk - nd) * WW;
+                tile_product<WMAX>(Sinv, Pu, W, tile, acc, &p0, &q0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (p0 + a < W && q0 + c < W) Uh0[(p0 + a) * W + q0 + c] = acc[a][c];
             }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (p0 + a < W && q0 + c < W) dst[(p0 + a) * W + q0 + c] = acc[a][c];
         }
         __syncthreads();
+        if (nd == 2)
+            for (int t = tid; t < ntile; t += nt) {
+                double acc[4][4];
+                int p0, q0;
+                tile_product<WMAX>(Sinv, Pu + WW, W, t, acc, &p0, &q0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (p0 + a < W && q0 + c < W) Uh1[(p0 + a) * W + q0 + c] = acc[a][c];
+            }
+        __syncthreads();
+        const double* Uh[2] = {Uh0, Uh1};
         // block row K: S^-1 and -Uh(K, K+1..K+3) (zero past the box; Lh blocks before it zero);
-        // Lh(K+1..K+3, K) into column block 2 - bi of the rows below.  e = q * W + p: coalesced
+        // Lh(K+3, K) = diag(dA) S^-1 into column block 0 of row K+3.  e = q * W + p: coalesced
         // column-major stores.
         for (int e = tid; e < WW; e += nt) {
             const int q = e / W, p = e - q * W, rm = p * W + q;
             const double sv = Sinv[rm];
             rowK[3 * WW + e] = (T)sv;
             for (int bj = 0; bj < 3; ++bj) {
-                const double u = bj < nd ? Pu[bj * WW + rm] : (bj < nI ? sv * dB[q] : 0.0);
+                const double u = bj < nd ? Uh[bj][rm] : (bj < nI ? sv * dB[q] : 0.0);
                 rowK[4 * WW + bj * WW + e] = (T)(-u);
             }
             if (K < 3)
                 for (int cb = 0; cb < 3 - K; ++cb) rowK[cb * WW + e] = (T)0.0;
-            for (int bi = 0; bi < nI; ++bi) {
-                const double l = bi < nd ? Pl[bi * WW + rm] : dA[p] * sv;
-                out[(long)(K + 1 + bi) * 7 * WW + (2 - bi) * WW + e] = (T)l;
-            }
+            if (nI == 3) out[(long)(K + 3) * 7 * WW + e] = (T)(dA[p] * sv);
         }
-        // Schur complement A(I,J) -= Lh(I,K) A(K,J): dense for I, J = K+1, K+2 (the C tile is
-        // loaded before the product so that its global-memory latency overlaps the LDS work) ...
+        // Schur complement A(I,J) -= A(I,K) Uh(K,J): dense for I, J = K+1, K+2.  (The C tile is
+        // read after the product: held through it, beside the product's own tile, it would
+        // not fit the 128 registers of four workgroups per CU.) ...
         const int nsch = nd * nd * ntile;
         for (int t = tid; t < nsch; t += nt) {
             const int blk = t / ntile, tile = t - blk * ntile;
             const int bi = blk / nd, bj = blk - bi * nd;
-            const int tp = 4 * (tile / nq), tq = 4 * (tile - (tile / nq) * nq);
             double* C = slot(win, K + 1 + bi, K + 1 + bj, W);
-            double cv[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) cv[a][c] = C[min(tp + a, W - 1) * W + min(tq + c, W - 1)];
             double acc[4][4];
             int p0, q0;
-            tile_product<WMAX>(Pl + bi * WW, Pb + bj * WW, W, tile, acc, &p0, &q0);
+            tile_product<WMAX>(Pa + bi * WW, Uh[bj], W, tile, acc, &p0, &q0);
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if (p0 + a < W && q0 + c < W) C[(p0 + a) * W + q0 + c] = cv[a][c] - acc[a][c];
+                    if (p0 + a < W && q0 + c < W) C[(p0 + a) * W + q0 + c] -= acc[a][c];
         }
-        // ... and scalings where a distance-3 block takes part:
-        //   A(I, K+3) -= Lh(I,K) diag(dB), A(K+3, J) -= diag(dA) Uh(K,J), A(K+3, K+3) -= diag(dA) S^-1 diag(dB)
+        // ... and the scalings where a distance-3 block takes part (A(I, K+3) -= Lh(I,K) diag(dB)
+        // was applied with Lh above):
+        //   A(K+3, J) -= diag(dA) Uh(K,J), A(K+3, K+3) -= diag(dA) S^-1 diag(dB)
         if (nI == 3)
-            for (int e = tid; e < 5 * WW; e += nt) {
-                const int c5 = e / WW, rm = e - c5 * WW, p = rm / W, q = rm - p * W;
-                double* C;
-                double v;
-                if (c5 < 2) {
-                    C = slot(win, K + 1 + c5, K + 3, W);
-                    v = Pl[c5 * WW + rm] * dB[q];
-                } else if (c5 < 4) {
-                    C = slot(win, K + 3, K + c5 - 1, W);
-                    v = dA[p] * Pu[(c5 - 2) * WW + rm];
-                } else {
-                    C = slot(win, K + 3, K + 3, W);
-                    v = dA[p] * Sinv[rm] * dB[q];
-                }
-                C[rm] -= v;
+            for (int e = tid; e < 3 * WW; e += nt) {
+                const int c3 = e / WW, rm = e - c3 * WW, p = rm / W, q = rm - p * W;
+                if (c3 < 2)
+                    slot(win, K + 3, K + 1 + c3, W)[rm] -= dA[p] * Uh[c3][rm];
+                else
+                    slot(win, K + 3, K + 3, W)[rm] -= dA[p] * Sinv[rm] * dB[q];
             }
         __syncthreads();
         // slide the window: block row and column K + 4 enter
@@ -695,7 +706,7 @@ hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b
 
 }  // namespace
 
-size_t lu_factor_lds_bytes(int W) { return sizeof(double) * (W <= kSmallW ? 10 : 2) * (size_t)W * W; }
+size_t lu_factor_lds_bytes(int W) { return sizeof(double) * (W <= kSmallW ? 6 : 2) * (size_t)W * W; }
 
 size_t lu_work_blocks(int W) { return W <= kSmallW ? 16 : 22; }
 

@@ -6,6 +6,7 @@ summation by parts, mass conservation), complex-step differentiation, a direct
 sparse solve, or a manufactured solution with known convergence order.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -307,6 +308,8 @@ def test_fft_gmres_newton_matches_direct_128():
 
 
 @pytest.mark.slow
+@pytest.mark.skipif(not os.environ.get("PFC_SLOW_TESTS"),
+                    reason="3 minutes of SuperLU at 256^2; set PFC_SLOW_TESTS=1 (the 128^2 case runs by default)")
 def test_fft_gmres_newton_matches_direct_256():
     w = I.crystal_growth(256, (2, 2))
     phi = w.initial()

@@ -529,9 +529,10 @@ def run_stencil_sizes(reps=20):
 
 
 def run_crack(steps):
-    """Test C's grid: 4096 x 1024 on [0, 4096 pi/3] x [0, 1024 pi/3], the notched lattice, gamma 1,
-    adaptive dt 1..5 (eta 100); FP32 exact-LU subdomain solves on 16 x 64 boxes of 64 x 64 owned
-    cells, overlap 3; extrapolated guess, factors lagged up to 20 steps."""
+    """Test C's grid: 4096 x 1024 over the periodic system of 591 x 76 lattice periods (about
+    4096 pi/3 x 1024 pi/3), the notched lattice, gamma 1, adaptive dt 1..5 (eta 100); FP32
+    exact-LU subdomain solves on 16 x 64 boxes of 64 x 64 owned cells, overlap 3; extrapolated
+    guess, factors lagged up to 20 steps."""
     import torch
     import paper_1703_01202_amd as pfc
     import pfc_inputs as I

@@ -10,7 +10,8 @@ Initial conditions follow the paper's experiments (Sec. 5):
 * ``hex_crystallites_ic``  hexagonal crystallites in a liquid (test B, Eqs. (29)-(30));
 * ``smooth_ic``         the smooth sine product used for the accuracy study (Eq. (28));
 * ``bcc_spheres_ic``    BCC crystallite spheres in 3-D (test D, Eqs. (32)-(34));
-* ``crack_ic``          the notched, stretched hexagonal lattice of the crack test (test C).
+* ``crack_ic``          the notched, stretched hexagonal lattice of the crack test (test C),
+                        on the periodic system ``crack_lengths`` gives.
 """
 from __future__ import annotations
 
@@ -29,25 +30,38 @@ def cell_centres(n, L):
     return (np.arange(n) + 0.5) * (L / n)
 
 
+def crack_periods(nx=4096, ny=1024):
+    """Lattice periods of test C's periodic system: the most whole periods (2 pi / q_x along x,
+    2 pi sqrt(3) / q_y along y) that fit in 4096 pi/3 x 1024 pi/3, scaled with the mesh:
+    591 x 76 at 4096 x 1024."""
+    qx = math.sqrt(3) / 2
+    qy = 0.9 * qx
+    px, py = 2 * math.pi / qx, 2 * math.pi * math.sqrt(3) / qy
+    return math.floor(4096 * math.pi / 3 * nx / 4096 / px), math.floor(1024 * math.pi / 3 * ny / 1024 / py)
+
+
+def crack_lengths(nx=4096, ny=1024):
+    """(L_y, L_x) of test C's domain: the periodic system itself (crack_periods periods)."""
+    qx = math.sqrt(3) / 2
+    qy = 0.9 * qx
+    mx, my = crack_periods(nx, ny)
+    return my * 2 * math.pi * math.sqrt(3) / qy, mx * 2 * math.pi / qx
+
+
 def crack_ic(nx=4096, ny=1024, notch=(40, 20), liquid=0.79):
     """Stretched hexagonal lattice with a liquid notch (test C, Sec. 5).
 
-    Domain 4096 pi/3 x 1024 pi/3 on an nx x ny mesh scaled with it (the paper's 4096 x 1024
-    gives dx = dy = pi/3); lattice 0.49 + cos(q_y y / sqrt 3) cos(q_x x) - 0.5 cos(2 q_y y / sqrt 3)
-    with q_x = sqrt(3)/2, q_y = 0.9 q_x, on the largest block of whole periods that fits the
-    domain (591 x 76 periods at the full size, scaled with nx, ny); the strips the block leaves
-    and a notch of notch[0] x notch[1] cells at the centre hold the coexisting liquid.
-    Array axes are (y, x)."""
-    Lx = 4096 * math.pi / 3 * nx / 4096
-    Ly = 1024 * math.pi / 3 * ny / 1024
+    The domain is the periodic system of whole lattice periods that fits in 4096 pi/3 x
+    1024 pi/3 (crack_lengths; 591 x 76 periods at the full size, scaled with nx, ny), on an
+    nx x ny mesh; lattice 0.49 + cos(q_y y / sqrt 3) cos(q_x x) - 0.5 cos(2 q_y y / sqrt 3) with
+    q_x = sqrt(3)/2, q_y = 0.9 q_x over all of it; a notch of notch[0] x notch[1] cells at the
+    centre holds the coexisting liquid.  Array axes are (y, x)."""
+    Ly, Lx = crack_lengths(nx, ny)
     qx = math.sqrt(3) / 2
     qy = 0.9 * qx
-    px, py = 2 * math.pi / qx, 2 * math.pi * math.sqrt(3) / qy          # lattice periods
-    bx, by = math.floor(Lx / px) * px, math.floor(Ly / py) * py          # whole-period block
     x, y = cell_centres(nx, Lx), cell_centres(ny, Ly)
     X, Y = np.meshgrid(x, y, indexing="xy")
     phi = 0.49 + np.cos(qy * Y / math.sqrt(3)) * np.cos(qx * X) - 0.5 * np.cos(2 * qy * Y / math.sqrt(3))
-    phi[(X >= bx) | (Y >= by)] = liquid
     cx, cy = nx // 2, ny // 2
     phi[cy - notch[1] // 2: cy + notch[1] // 2, cx - notch[0] // 2: cx + notch[0] // 2] = liquid
     return phi
@@ -213,9 +227,10 @@ def test_b_variants(n=1024, nsteps=200):
 
 
 def crack_4096x1024():
-    """Test C: 4096 x 1024 mesh on [0, 4096 pi/3] x [0, 1024 pi/3], gamma 1, the notched lattice,
-    adaptive dt 1..5 (eta 100), 16 x 64 boxes (64 x 64 owned), overlap 3 (delta = 1)."""
-    return Workload("pfc2d_crack_4096x1024", (1024, 4096), (1024 * math.pi / 3, 4096 * math.pi / 3), 1.0, 1.0, 5.0,
+    """Test C: 4096 x 1024 mesh on the periodic system of 591 x 76 lattice periods (about
+    4096 pi/3 x 1024 pi/3), gamma 1, the notched lattice, adaptive dt 1..5 (eta 100), 16 x 64
+    boxes (64 x 64 owned), overlap 3 (delta = 1)."""
+    return Workload("pfc2d_crack_4096x1024", (1024, 4096), crack_lengths(4096, 1024), 1.0, 1.0, 5.0,
                     100.0, 200, (16, 64), 3, ic=dict(kind="crack"))
 
 

@@ -81,3 +81,32 @@ def test_autotune_times_candidates_and_skips_rejected_ones():
     assert len(ran) == 2 and best is max(ran, key=lambda r: r["steps_per_s"])
     assert all(r["newton_its"] > 0 for r in ran)
     assert np.isfinite(best["steps_per_s"])
+
+
+def test_benchmark_batch_instances_reach_the_oracle_root(pfc):
+    """The benchmark's 64-instance batch configuration (FP32 exact LU on boxes of 64 x 16 owned
+    cells with overlap 4, extrapolated guess, lagged factors), run as a ragged batch of sampled
+    instances: every 128^2 instance and the first 192^2 one of the set, with the first 256^2
+    one beside them unchecked.  One step from the initial states, Newton to 1e-10; each
+    checked instance's solution is the oracle's Newton root (direct solves) for the same
+    state and step to rel 1e-9."""
+    import pfc_inputs as I
+    from oracle import scheme as S
+    ws = I.batch_instances(64)
+    small = [w for w in ws if w.shape == (128, 128)]
+    pick = small + [next(w for w in ws if w.shape == (192, 192)), next(w for w in ws if w.shape == (256, 256))]
+    insts = [dict(shape=w.shape, lengths=w.lengths, gamma=w.gamma, sub=(w.shape[0] // 64, w.shape[1] // 16),
+                  overlap=4, dt_min=w.dt_min, dt_max=w.dt_max, eta=w.eta, newton_rtol=0.0, newton_atol=1e-10,
+                  lin_rtol=w.lin_rtol, lin_atol=w.lin_atol, sub_solver="lu", precond_fp32=True, guess="extrap",
+                  precond_lag=20) for w in pick]
+    batch = pfc.Batch(insts, workers=4)
+    phi0 = [w.initial() for w in pick]
+    phis = [torch.from_numpy(p).cuda() for p in phi0]
+    st = batch.step(phis)
+    for k, w in enumerate(pick[:-1]):
+        h = S.spacing(w.shape, w.lengths)
+        ref = S.newton_solve(phi0[k], st[k]["dt"], w.gamma, h)
+        assert ref.converged
+        got = phis[k].cpu().numpy()
+        assert S.rel_l2(got, ref.Phi) <= 1e-9, (k, w.shape, S.rel_l2(got, ref.Phi))
+    batch.close()

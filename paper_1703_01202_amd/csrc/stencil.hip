@@ -85,13 +85,13 @@ __device__ __forceinline__ int xcd_item(int it, int items) {
 
 // The value of the next (dpp 0x130, wave_shl:1) or previous (0x138, wave_shr:1) lane of the
 // wave, moved by the data-parallel primitives of the vector ALU (no LDS round trip); a lane
-// with no such neighbour keeps its own value.
+// with no such neighbour reads zero (bound_ctrl), so the move needs no copy of its old value.
 template <int CTRL>
 __device__ __forceinline__ double lane_move(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-    const int rl = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-    const int rh = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    const int rl = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+    const int rh = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)rh << 32) | (unsigned int)rl);
 }
 
@@ -109,10 +109,13 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
     __shared__ double red[NT / 64];
     const SwGeom G = sw_geom(p.nx, p.ny);
     const int lane = threadIdx.x & 63;
+    // the wave's index is the same in all its lanes: taken as a scalar, every row, segment and
+    // loop bound below is scalar too, and the loop's branches are uniform
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ngroups = (G.items + NT / 64 - 1) / (NT / 64);   // items by groups of a block's waves
     double acc = 0.0, accx = 0.0;
     for (int gb = blockIdx.x; gb < ngroups; gb += gridDim.x) {
-        const int it = xcd_item(gb, ngroups) * (NT / 64) + (threadIdx.x >> 6);
+        const int it = xcd_item(gb, ngroups) * (NT / 64) + wave;
         if (it >= G.items) continue;
         const int strip = it % G.nstrip, sg = it / G.nstrip;
         const int xo = strip * SW_OUT + lane - 3;                 // this lane's column
@@ -120,15 +123,24 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
         const bool out = lane >= 3 && lane < 3 + SW_OUT && xo < p.nx;
         const int y0 = sg * G.seg, y1 = min(y0 + G.seg, p.ny);
         // rows y0-3 .. y1+2 enter; F of row r-3 leaves when row r has entered
-        double pa[SW_PF], pb[SW_PF];
+        const int nrow = y1 - y0 + 6;
         int yl = wrap(y0 - 3, p.ny);                               // row of the next load
+        // Two sets of SW_PF prefetch slots: while one set's rows are consumed the other is
+        // refilled, so a slot's old value is dead before its new load is issued and both
+        // share one register; no copy (and so no wait) follows a load.  Past the segment's
+        // last row that row is loaded again (in bounds, from the cache), so no branch stands
+        // around a load either.
+        // addresses: a scalar row base plus the lane's column offset, fixed for the sweep
+        const unsigned ux = x, uxo = out ? xo : 0;
+        auto load = [&](double& A, double& B, int k) {
+            const long rb = (long)yl * p.nx;
+            A = (Phi + rb)[ux];
+            B = (phi + rb)[ux];
+            if (k + 1 < nrow) yl = yl + 1 == p.ny ? 0 : yl + 1;
+        };
+        double pa[SW_PF], pb[SW_PF], qa[SW_PF], qb[SW_PF];
 #pragma unroll
-        for (int k = 0; k < SW_PF; ++k) {
-            const long gi = (long)yl * p.nx + x;
-            pa[k] = Phi[gi];
-            pb[k] = phi[gi];
-            yl = yl + 1 == p.ny ? 0 : yl + 1;
-        }
+        for (int k = 0; k < SW_PF; ++k) load(pa[k], pb[k], k);
         // windows at the top of iteration k (row r = y0 - 3 + k entering):
         double u0 = 0, u1 = 0;                  // u at rows r-1, r-2
         double q1 = 0, q2 = 0;                  // q at rows r-1, r-2
@@ -136,45 +148,43 @@ __global__ __launch_bounds__(NT) void k_residual2d(const double* __restrict__ Ph
         double m2 = 0, m3 = 0;                  // mu at rows r-3, r-4
         double d1 = 0, d2 = 0, d3 = 0;          // Phi - phi at rows r-1, r-2, r-3
         double a1 = 0, a2 = 0, a3 = 0;          // Phi at rows r-1, r-2, r-3
-        const int nrow = y1 - y0 + 6;
-        // unrolled by SW_PF so that every prefetch slot is a fixed register: a slot is read
-        // only when its row is consumed and refilled right after, so up to SW_PF rows stay in
-        // flight (rotating the slots would read, and so wait for, every pending load)
-        for (int k0 = 0; k0 < nrow; k0 += SW_PF) {
+        auto row = [&](double a, double bb, int k) {
+            const double un = 0.5 * (a + bb);
+            const double qn = 0.25 * (a * a * a + a * a * bb + a * bb * bb + bb * bb * bb);
+            // Lu at row r-1, mu at row r-2, F at row r-3
+            const double ln = lapx(u0, p.ihx2) + (un + u1 - 2.0 * u0) * p.ihy2;
+            const double mn =
+                (1.0 - p.gamma) * u1 + 2.0 * l1 + lapx(l1, p.ihx2) + (ln + l2 - 2.0 * l1) * p.ihy2 + q2;
+            const double lm = lapx(m2, p.ihx2) + (mn + m3 - 2.0 * m2) * p.ihy2;
+            if (k >= 6 && k < nrow && out) {
+                double f = d3 * p.inv_dt - lm;
+                const long rb = (long)(y0 - 6 + k) * p.nx;
+                if (src) f -= (src + rb)[uxo];
+                (F + rb)[uxo] = f;
+                acc += f * f;
+                accx += a3 * a3;
+            }
+            // shift the windows by one row
+            m3 = m2; m2 = mn;
+            l2 = l1; l1 = ln;
+            q2 = q1; q1 = qn;
+            u1 = u0; u0 = un;
+            a3 = a2; a2 = a1; a1 = a;
+            d3 = d2; d2 = d1; d1 = a - bb;
+        };
+        // iterations past the last row (up to 2 SW_PF - 1) store nothing
+        for (int k0 = 0; k0 < nrow; k0 += 2 * SW_PF) {
 #pragma unroll
             for (int j = 0; j < SW_PF; ++j) {
-                const int k = k0 + j;
-                if (k >= nrow) break;
-                const int r = y0 - 3 + k;
                 const double a = pa[j], bb = pb[j];
-                if (k + SW_PF < nrow) {
-                    const long gi = (long)yl * p.nx + x;
-                    pa[j] = Phi[gi];
-                    pb[j] = phi[gi];
-                    yl = yl + 1 == p.ny ? 0 : yl + 1;
-                }
-                const double un = 0.5 * (a + bb);
-                const double qn = 0.25 * (a * a * a + a * a * bb + a * bb * bb + bb * bb * bb);
-                // Lu at row r-1, mu at row r-2, F at row r-3
-                const double ln = lapx(u0, p.ihx2) + (un + u1 - 2.0 * u0) * p.ihy2;
-                const double mn =
-                    (1.0 - p.gamma) * u1 + 2.0 * l1 + lapx(l1, p.ihx2) + (ln + l2 - 2.0 * l1) * p.ihy2 + q2;
-                const double lm = lapx(m2, p.ihx2) + (mn + m3 - 2.0 * m2) * p.ihy2;
-                if (k >= 6 && out) {
-                    double f = d3 * p.inv_dt - lm;
-                    const long gi = (long)(r - 3) * p.nx + xo;
-                    if (src) f -= src[gi];
-                    F[gi] = f;
-                    acc += f * f;
-                    accx += a3 * a3;
-                }
-                // shift the windows by one row
-                m3 = m2; m2 = mn;
-                l2 = l1; l1 = ln;
-                q2 = q1; q1 = qn;
-                u1 = u0; u0 = un;
-                a3 = a2; a2 = a1; a1 = a;
-                d3 = d2; d2 = d1; d1 = a - bb;
+                load(qa[j], qb[j], k0 + SW_PF + j);
+                row(a, bb, k0 + j);
+            }
+#pragma unroll
+            for (int j = 0; j < SW_PF; ++j) {
+                const double a = qa[j], bb = qb[j];
+                load(pa[j], pb[j], k0 + 2 * SW_PF + j);
+                row(a, bb, k0 + SW_PF + j);
             }
         }
     }
@@ -205,52 +215,58 @@ __global__ __launch_bounds__(NT) void k_jv2d(const double* __restrict__ v,
     }
     const SwGeom G = sw_geom(p.nx, p.ny);
     const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // scalar, as in k_residual2d
     const int ngroups = (G.items + NT / 64 - 1) / (NT / 64);
     for (int gb = blockIdx.x; gb < ngroups; gb += gridDim.x) {
-        const int it = xcd_item(gb, ngroups) * (NT / 64) + (threadIdx.x >> 6);
+        const int it = xcd_item(gb, ngroups) * (NT / 64) + wave;
         if (it >= G.items) continue;
         const int strip = it % G.nstrip, sg = it / G.nstrip;
         const int xo = strip * SW_OUT + lane - 3;
         const int x = wrap(xo, p.nx);
         const bool out = lane >= 3 && lane < 3 + SW_OUT && xo < p.nx;
         const int y0 = sg * G.seg, y1 = min(y0 + G.seg, p.ny);
-        double pv[SW_PF], pc[SW_PF];
+        const int nrow = y1 - y0 + 6;
         int yl = wrap(y0 - 3, p.ny);                               // row of the next load
+        // two sets of prefetch slots, refilled with no branch, as in k_residual2d
+        const unsigned ux = x, uxo = out ? xo : 0;
+        auto load = [&](double& A, double& B, int k) {
+            const long rb = (long)yl * p.nx;
+            A = (v + rb)[ux];
+            B = (cc + rb)[ux];
+            if (k + 1 < nrow) yl = yl + 1 == p.ny ? 0 : yl + 1;
+        };
+        double pv[SW_PF], pc[SW_PF], qv[SW_PF], qc[SW_PF];
 #pragma unroll
-        for (int k = 0; k < SW_PF; ++k) {
-            const long gi = (long)yl * p.nx + x;
-            pv[k] = v[gi];
-            pc[k] = cc[gi];
-            yl = yl + 1 == p.ny ? 0 : yl + 1;
-        }
+        for (int k = 0; k < SW_PF; ++k) load(pv[k], pc[k], k);
         // windows at the top of iteration k (row r = y0 - 3 + k entering):
         double v0 = 0, v1 = 0, v2 = 0;          // v at rows r-1, r-2, r-3
         double c1 = 0, c2 = 0;                   // c at rows r-1, r-2
         double l1 = 0, l2 = 0;                   // Lv at rows r-2, r-3
         double w2 = 0, w3 = 0;                   // inner operator at rows r-3, r-4
-        const int nrow = y1 - y0 + 6;
-        for (int k0 = 0; k0 < nrow; k0 += SW_PF) {   // unrolled as in k_residual2d
+        auto row = [&](double vr, double cn, int k) {
+            const double vn = vr - sh;
+            const double ln = lapx(v0, p.ihx2) + (vn + v1 - 2.0 * v0) * p.ihy2;
+            const double wn = 0.5 * (1.0 - p.gamma) * v1 + l1 +
+                              0.5 * (lapx(l1, p.ihx2) + (ln + l2 - 2.0 * l1) * p.ihy2) + c2 * v1;
+            const double lw = lapx(w2, p.ihx2) + (wn + w3 - 2.0 * w2) * p.ihy2;
+            if (k >= 6 && k < nrow && out) (Jv + (long)(y0 - 6 + k) * p.nx)[uxo] = v2 * p.inv_dt - lw;
+            w3 = w2; w2 = wn;
+            l2 = l1; l1 = ln;
+            c2 = c1; c1 = cn;
+            v2 = v1; v1 = v0; v0 = vn;
+        };
+        for (int k0 = 0; k0 < nrow; k0 += 2 * SW_PF) {
 #pragma unroll
             for (int j = 0; j < SW_PF; ++j) {
-                const int k = k0 + j;
-                if (k >= nrow) break;
-                const int r = y0 - 3 + k;
-                const double vn = pv[j] - sh, cn = pc[j];
-                if (k + SW_PF < nrow) {
-                    const long gi = (long)yl * p.nx + x;
-                    pv[j] = v[gi];
-                    pc[j] = cc[gi];
-                    yl = yl + 1 == p.ny ? 0 : yl + 1;
-                }
-                const double ln = lapx(v0, p.ihx2) + (vn + v1 - 2.0 * v0) * p.ihy2;
-                const double wn = 0.5 * (1.0 - p.gamma) * v1 + l1 +
-                                  0.5 * (lapx(l1, p.ihx2) + (ln + l2 - 2.0 * l1) * p.ihy2) + c2 * v1;
-                const double lw = lapx(w2, p.ihx2) + (wn + w3 - 2.0 * w2) * p.ihy2;
-                if (k >= 6 && out) Jv[(long)(r - 3) * p.nx + xo] = v2 * p.inv_dt - lw;
-                w3 = w2; w2 = wn;
-                l2 = l1; l1 = ln;
-                c2 = c1; c1 = cn;
-                v2 = v1; v1 = v0; v0 = vn;
+                const double a = pv[j], b = pc[j];
+                load(qv[j], qc[j], k0 + SW_PF + j);
+                row(a, b, k0 + j);
+            }
+#pragma unroll
+            for (int j = 0; j < SW_PF; ++j) {
+                const double a = qv[j], b = qc[j];
+                load(pv[j], pc[j], k0 + 2 * SW_PF + j);
+                row(a, b, k0 + SW_PF + j);
             }
         }
     }

@@ -601,8 +601,8 @@ __global__ void k_mp_final(const double* a, const double* __restrict__ b,
 // behind each other, each stage keeping the last three planes it produced in an LDS ring
 // (the z-neighbours), so every field is read from HBM once per column (plus its x-y halo
 // and the three planes above and below a segment) and the result written once, in one
-// launch instead of four passes through memory.  The next plane's loads are issued into
-// registers before the stages of the current plane run, so their latency overlaps them.
+// launch instead of four passes through memory.  Each plane's loads are issued into
+// registers two planes ahead, so the stages of the two planes before it cover their latency.
 // ---------------------------------------------------------------------------
 
 constexpr int T3X = 32, T3Y = 8;
@@ -628,6 +628,18 @@ __host__ __device__ inline Geom3 geom3(int nx, int ny, int nz) {
     g.nseg = (nz + g.zseg - 1) / g.zseg;
     g.items = cols * g.nseg;
     return g;
+}
+
+// In-plane offsets of the halo-3 cells that this thread stages for the column at (x0, y0):
+// cell tid + NT r of the (T3X + 6) x (T3Y + 6) plane, wrapped periodically; slots past the
+// plane's last cell take that cell's offset (loaded, never stored).
+__device__ __forceinline__ void halo3_offsets(int (&go)[PF3], int x0, int y0, const P& p) {
+#pragma unroll
+    for (int r = 0; r < PF3; ++r) {
+        const int e = min((int)threadIdx.x + NT * r, H3N - 1);
+        const int i = e % (T3X + 6), j = e / (T3X + 6);
+        go[r] = wrap(y0 - 3 + j, p.ny) * p.nx + wrap(x0 - 3 + i, p.nx);
+    }
 }
 
 // five-point x-y Laplacian of plane a (width w) at (i, j), plus the z term from planes zm, zp
@@ -659,31 +671,30 @@ __global__ __launch_bounds__(NT) void k_residual3d(const double* __restrict__ Ph
         const int x0 = (col % G.ntx) * T3X, y0 = (col / G.ntx) * T3Y;
         const int z0 = sg * G.zseg, z1 = min(z0 + G.zseg, p.nz);
         const int nk = z1 - z0 + 6;
-        double pa[PF3], pb[PF3];   // the next plane's Phi, phi at this thread's halo-3 cells
-        auto fetch = [&](int zin) {
-            const long zoff = (long)wrap(zin, p.nz) * sxy;
+        int go[PF3];   // in-plane offsets of this thread's halo-3 cells
+        halo3_offsets(go, x0, y0, p);
+        // Three sets of slots, plane k in set k mod 3, loaded two planes ahead into the set whose
+        // plane has just been consumed: no copy and no early wait follows a load, and two planes
+        // of stage work cover its latency.  Past the segment's last plane that plane is loaded
+        // again (in bounds, from the cache).
+        auto fetch = [&](int k, double (&A)[PF3], double (&B)[PF3]) {
+            const long zoff = (long)wrap(z0 - 3 + min(k, nk - 1), p.nz) * sxy;
 #pragma unroll
             for (int r = 0; r < PF3; ++r) {
-                const int e = tid + NT * r;
-                if (e < H3N) {
-                    const int i = e % (T3X + 6), j = e / (T3X + 6);
-                    const long gi = zoff + (long)wrap(y0 - 3 + j, p.ny) * p.nx + wrap(x0 - 3 + i, p.nx);
-                    pa[r] = Phi[gi];
-                    pb[r] = phi[gi];
-                }
+                A[r] = Phi[zoff + go[r]];
+                B[r] = phi[zoff + go[r]];
             }
         };
-        fetch(z0 - 3);
-        __syncthreads();   // the previous item's last reads of the rings
-        for (int k = 0; k < nk; ++k) {
+        auto step = [&](int k, const double (&A)[PF3], const double (&B)[PF3], double (&NA)[PF3],
+                        double (&NB)[PF3]) {
             const int zin = z0 - 3 + k;
-            // A: plane zin enters (from the registers), and the next plane's loads go out
+            // A: plane zin enters (from the registers), and plane zin + 2's loads go out
 #pragma unroll
             for (int r = 0; r < PF3; ++r) {
                 const int e = tid + NT * r;
                 if (e >= H3N) break;
                 const int i = e % (T3X + 6), j = e / (T3X + 6);
-                const double a = pa[r], b = pb[r];
+                const double a = A[r], b = B[r];
                 U[k % 3][e] = 0.5 * (a + b);
                 if (i >= 2 && i < T3X + 4 && j >= 2 && j < T3Y + 4)
                     Q[k % 3][(j - 2) * (T3X + 2) + i - 2] = 0.25 * (a * a * a + a * a * b + a * b * b + b * b * b);
@@ -692,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_residual3d(const double* __restrict__ Ph
                     if (xpart && zin >= z0 && zin < z1 && x0 + i - 3 < p.nx && y0 + j - 3 < p.ny) accx += a * a;
                 }
             }
-            if (k + 1 < nk) fetch(zin + 1);
+            fetch(k + 2, NA, NB);
             __syncthreads();
             // B: Lu at plane zin - 1 (halo 2)
             if (k >= 2)
@@ -725,6 +736,17 @@ __global__ __launch_bounds__(NT) void k_residual3d(const double* __restrict__ Ph
                     F[gi] = f;
                     acc += f * f;
                 }
+        };
+        double s0a[PF3], s0b[PF3], s1a[PF3], s1b[PF3], s2a[PF3], s2b[PF3];
+        fetch(0, s0a, s0b);
+        fetch(1, s1a, s1b);
+        __syncthreads();   // the previous item's last reads of the rings
+        for (int k0 = 0; k0 < nk; k0 += 3) {
+            step(k0, s0a, s0b, s2a, s2b);
+            if (k0 + 1 >= nk) break;
+            step(k0 + 1, s1a, s1b, s0a, s0b);
+            if (k0 + 2 >= nk) break;
+            step(k0 + 2, s2a, s2b, s1a, s1b);
         }
     }
     if (part) {
@@ -762,35 +784,31 @@ __global__ __launch_bounds__(NT) void k_jv3d(const double* __restrict__ v, const
         const int x0 = (col % G.ntx) * T3X, y0 = (col / G.ntx) * T3Y;
         const int z0 = sg * G.zseg, z1 = min(z0 + G.zseg, p.nz);
         const int nk = z1 - z0 + 6;
-        double pv[PF3], pc[PF3];   // the next plane's v, c at this thread's halo-3 cells
-        auto fetch = [&](int zin) {
-            const long zoff = (long)wrap(zin, p.nz) * sxy;
+        int go[PF3];
+        halo3_offsets(go, x0, y0, p);
+        // three sets of slots loaded two planes ahead, as in k_residual3d
+        auto fetch = [&](int k, double (&A)[PF3], double (&B)[PF3]) {
+            const long zoff = (long)wrap(z0 - 3 + min(k, nk - 1), p.nz) * sxy;
 #pragma unroll
             for (int r = 0; r < PF3; ++r) {
-                const int e = tid + NT * r;
-                if (e < H3N) {
-                    const int i = e % (T3X + 6), j = e / (T3X + 6);
-                    const long gi = zoff + (long)wrap(y0 - 3 + j, p.ny) * p.nx + wrap(x0 - 3 + i, p.nx);
-                    pv[r] = v[gi];
-                    pc[r] = cc[gi];
-                }
+                A[r] = v[zoff + go[r]];
+                B[r] = cc[zoff + go[r]];
             }
         };
-        fetch(z0 - 3);
-        __syncthreads();
-        for (int k = 0; k < nk; ++k) {
+        auto step = [&](int k, const double (&A)[PF3], const double (&B)[PF3], double (&NA)[PF3],
+                        double (&NB)[PF3]) {
             const int zin = z0 - 3 + k;
 #pragma unroll
             for (int r = 0; r < PF3; ++r) {
                 const int e = tid + NT * r;
                 if (e >= H3N) break;
                 const int i = e % (T3X + 6), j = e / (T3X + 6);
-                const double a = pv[r] - sh;
+                const double a = A[r] - sh;
                 V[k % 3][e] = a;
-                if (i >= 2 && i < T3X + 4 && j >= 2 && j < T3Y + 4) C[k % 3][(j - 2) * (T3X + 2) + i - 2] = pc[r];
+                if (i >= 2 && i < T3X + 4 && j >= 2 && j < T3Y + 4) C[k % 3][(j - 2) * (T3X + 2) + i - 2] = B[r];
                 if (i >= 3 && i < T3X + 3 && j >= 3 && j < T3Y + 3) D[k % DR3][(j - 3) * T3X + i - 3] = a;
             }
-            if (k + 1 < nk) fetch(zin + 1);
+            fetch(k + 2, NA, NB);
             __syncthreads();
             if (k >= 2)
                 for (int e = tid; e < H2N; e += NT) {
@@ -815,6 +833,17 @@ __global__ __launch_bounds__(NT) void k_jv3d(const double* __restrict__ v, const
                     const double lw = lap3(Wr[(k - 3) % 3], Wr[(k - 4) % 3], Wr[(k - 2) % 3], T3X + 2, i + 1, j + 1, p);
                     Jv[(long)(zin - 3) * sxy + (long)y * p.nx + x] = D[(k - 3) % DR3][e] * p.inv_dt - lw;
                 }
+        };
+        double s0a[PF3], s0b[PF3], s1a[PF3], s1b[PF3], s2a[PF3], s2b[PF3];
+        fetch(0, s0a, s0b);
+        fetch(1, s1a, s1b);
+        __syncthreads();
+        for (int k0 = 0; k0 < nk; k0 += 3) {
+            step(k0, s0a, s0b, s2a, s2b);
+            if (k0 + 1 >= nk) break;
+            step(k0 + 1, s1a, s1b, s0a, s0b);
+            if (k0 + 2 >= nk) break;
+            step(k0 + 2, s2a, s2b, s1a, s1b);
         }
     }
 }

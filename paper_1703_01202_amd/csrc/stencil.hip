@@ -621,10 +621,11 @@ __host__ __device__ inline Geom3 geom3(int nx, int ny, int nz) {
     Geom3 g;
     g.ntx = (nx + T3X - 1) / T3X;
     g.nty = (ny + T3Y - 1) / T3Y;
-    // segments as short as gives ~1024 columns in all, at least 16 planes (6 warm-up planes)
+    // segments as short as gives ~768 items (three resident blocks on each of 256 CUs, as
+    // LDS allows), so that the items run in one round, but at least 8 planes (6 warm-up planes)
     const int cols = g.ntx * g.nty;
-    const int want = max(1, 1024 / cols);
-    g.zseg = max(16, (nz + want - 1) / want);
+    const int want = max(1, 768 / cols);
+    g.zseg = max(8, (nz + want - 1) / want);
     g.nseg = (nz + g.zseg - 1) / g.zseg;
     g.items = cols * g.nseg;
     return g;

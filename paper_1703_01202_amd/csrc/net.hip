@@ -81,10 +81,12 @@ __device__ __forceinline__ uint4* grp(float* base, long g, long HW, long p) {
     return reinterpret_cast<uint4*>(base) + g * HW + p;
 }
 
-// tanh from one exponential: sign(z) (1 - 2 / (exp(2|z|) + 1)); absolute error ~1e-7
+// tanh from one exponential: sign(z) (1 - 2 / (exp(2|z|) + 1)), the reciprocal taken by the
+// hardware's approximate v_rcp_f32 (about 1 ulp) instead of a correctly rounded division;
+// absolute error ~2e-7.  exp overflowing to inf gives 1 exactly.
 __device__ __forceinline__ float tanh_fast(float z) {
     const float e = __expf(2.f * fabsf(z));
-    return copysignf(1.f - __fdividef(2.f, e + 1.f), z);
+    return copysignf(1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f), z);
 }
 
 __device__ __forceinline__ bool is_weight_index(int i) {
@@ -411,9 +413,10 @@ __device__ __forceinline__ bf16x8 pk8(const float (&b)[8]) {
 }
 
 // a1 = tanh(conv(x; W1) + b1) on the halo tile, into sm; wave wv takes chunks wv, wv + 4, ...
-// of 32 halo cells in row-major order (the last chunk is partial)
+// of 32 halo cells in row-major order (the last chunk is partial).  bl holds this lane's 16
+// bias values, b1[4 (2 q4 + half) + e] at 4 q4 + e, loaded once per kernel.
 __device__ __forceinline__ void layer1_to_lds(uint4 (*sm)[NG][CT_C], const f32x2 (*xs)[XS_C],
-                                              const bf16x8 (&A1)[2], const float* __restrict__ b1) {
+                                              const bf16x8 (&A1)[2], const float (&bl)[16]) {
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31, wv = threadIdx.x >> 6;
     for (int k = wv; k < L1_CHUNKS; k += 4) {
         const int q0 = 32 * k + col;
@@ -456,7 +459,7 @@ __device__ __forceinline__ void layer1_to_lds(uint4 (*sm)[NG][CT_C], const f32x2
             const int cg = 2 * q4 + half;
             float v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = tanh_fast(d[4 * q4 + e] + b1[4 * cg + e]);
+            for (int e = 0; e < 4; ++e) v[e] = tanh_fast(d[4 * q4 + e] + bl[4 * q4 + e]);
             if (ok) sm[r][cg][c] = split4(v[0], v[1], v[2], v[3]);
         }
     }
@@ -480,6 +483,11 @@ __global__ __launch_bounds__(256, CONV_OCC) void k_conv12_fwd(const float* __res
     for (int s = 0; s < KSTEPS; ++s) A[s] = pack[s * 64 + lane];
     const bf16x8 A1[2] = {pack1[lane], pack1[64 + lane]};
     const bf16x8 A4[2] = {};
+    float bl[16];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bl[4 * q4 + e] = b1[4 * (2 * q4 + (lane >> 5)) + e];
     f32x2 pre[XS_IT];
     if ((int)blockIdx.x < ntiles) {
         const int ty = blockIdx.x / ntx;
@@ -500,7 +508,7 @@ __global__ __launch_bounds__(256, CONV_OCC) void k_conv12_fwd(const float* __res
             const int ty1 = t1 / ntx;
             xs_load(pre, x, HW, ny, nx, ty1 * CT_Y, (t1 - ty1 * ntx) * CT_X);
         }
-        layer1_to_lds(sm, xs, A1, b1);
+        layer1_to_lds(sm, xs, A1, bl);
         __syncthreads();
         conv_tile<0>(sm, A, A4, b2, nullptr, out, HW, ny, nx, x0, y0);
     }

@@ -90,10 +90,12 @@ __device__ void load_c_row(double* ring, int J, const LuBox& b, const double* __
 // Inverse of the W x W block in G0 by Gauss-Jordan elimination without pivoting, taking
 // the pivots four at a time: for the pivot block K = {k0..k0+3} with P = a(K,K),
 //     a'(K,K) = P^-1,            a'(K,j) = P^-1 a(K,j),
-//     a'(i,K) = -a(i,K) P^-1,    a'(i,j) = a(i,j) - a(i,K) P^-1 a(K,j)      (i, j not in K),
-// which is four scalar Gauss-Jordan steps done at once.  Every thread inverts the 4 x 4
-// pivot block in registers (scalar Gauss-Jordan, same pivots); the matrix is double-
-// buffered through G1 with one barrier per block.  A last block narrower than four is
+//     a'(i,K) = -a(i,K) P^-1,    a'(i,j) = a(i,j) - a(i,K) a'(K,j)      (i, j not in K),
+// which is four scalar Gauss-Jordan steps done at once.  First the threads of the first W
+// columns each invert the 4 x 4 pivot block in registers (scalar Gauss-Jordan, same pivots)
+// and write their column of the new pivot rows a'(K, :); after a barrier every other entry
+// takes four products with those rows (a'(i,K) = -a(i,K) a'(K,K)).  The matrix is double-
+// buffered through G1, two barriers per pivot block.  A last block narrower than four is
 // padded with the identity.  Returns the buffer holding the inverse.
 __device__ double* gauss_jordan(double* G0, double* G1, int W, int* flag) {
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -101,77 +103,61 @@ __device__ double* gauss_jordan(double* G0, double* G1, int W, int* flag) {
     double* o = G1;
     for (int k0 = 0; k0 < W; k0 += 4) {
         const int bs = min(4, W - k0);
-        double P[4][4];
+        if (tid < W) {                               // column j = tid of the pivot rows
+            double P[4][4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                P[r][c] = (r < bs && c < bs) ? a[(k0 + r) * W + k0 + c] : (r == c ? 1.0 : 0.0);
+                for (int c = 0; c < 4; ++c)
+                    P[r][c] = (r < bs && c < bs) ? a[(k0 + r) * W + k0 + c] : (r == c ? 1.0 : 0.0);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {           // in-register Gauss-Jordan of P
-            const double piv = P[kk][kk];
-            if (tid == 0 && (!(piv != 0.0) || !isfinite(piv))) *flag = 1;
-            const double ip = 1.0 / piv;
-            double rowk[4];
+            for (int kk = 0; kk < 4; ++kk) {         // in-register Gauss-Jordan of P
+                const double piv = P[kk][kk];
+                if (tid == 0 && (!(piv != 0.0) || !isfinite(piv))) *flag = 1;
+                const double ip = 1.0 / piv;
+                double rowk[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rowk[c] = (c == kk) ? ip : P[kk][c] * ip;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (r == kk) continue;
-                const double f = P[r][kk];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) P[r][c] = (c == kk ? 0.0 : P[r][c]) - f * rowk[c];
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) P[kk][c] = rowk[c];
-        }
-        for (int e = tid; e < W * W; e += nt) {
-            const int i = e / W, j = e - i * W;
-            const int ri = i - k0, cj = j - k0;
-            const bool iK = ri >= 0 && ri < bs, jK = cj >= 0 && cj < bs;
-            double aiK[4], aKj[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                aiK[s] = (s < bs) ? a[i * W + k0 + s] : 0.0;
-                aKj[s] = (s < bs) ? a[(k0 + s) * W + j] : 0.0;
-            }
-            double v;
-            if (iK && jK) {
-                v = 0.0;
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        if (r == ri && c == cj) v = P[r][c];
-            } else if (iK) {
-                v = 0.0;
+                for (int c = 0; c < 4; ++c) rowk[c] = (c == kk) ? ip : P[kk][c] * ip;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    double t = 0.0;
+                    if (r == kk) continue;
+                    const double f = P[r][kk];
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) t += P[r][s] * aKj[s];
-                    if (r == ri) v = t;
+                    for (int c = 0; c < 4; ++c) P[r][c] = (c == kk ? 0.0 : P[r][c]) - f * rowk[c];
                 }
-            } else {
-                double w[4];                        // a(i,K) P^-1
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double t = 0.0;
+                for (int c = 0; c < 4; ++c) P[kk][c] = rowk[c];
+            }
+            const int j = tid, cj = j - k0;
+            double aKj[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) t += aiK[r] * P[r][c];
-                    w[c] = t;
-                }
-                if (jK) {
+            for (int s = 0; s < 4; ++s) aKj[s] = (s < bs) ? a[(k0 + s) * W + j] : 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r >= bs) break;
+                double v;
+                if (cj >= 0 && cj < bs) {            // a'(K,K) = P^-1
                     v = 0.0;
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
-                        if (c == cj) v = -w[c];
-                } else {
-                    v = a[e];
+                        if (c == cj) v = P[r][c];
+                } else {                             // a'(K,j) = P^-1 a(K,j)
+                    v = 0.0;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) v -= w[s] * aKj[s];
+                    for (int s = 0; s < 4; ++s) v += P[r][s] * aKj[s];
                 }
+                o[(k0 + r) * W + j] = v;
             }
+        }
+        __syncthreads();
+        for (int e = tid; e < W * W; e += nt) {
+            const int i = e / W, j = e - i * W;
+            if (i >= k0 && i < k0 + bs) continue;    // the pivot rows, written above
+            const bool jK = j >= k0 && j < k0 + bs;
+            double v = jK ? 0.0 : a[e];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (s < bs) v -= a[i * W + k0 + s] * o[(k0 + s) * W + j];
             o[e] = v;
         }
         __syncthreads();

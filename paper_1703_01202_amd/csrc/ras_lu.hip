@@ -205,8 +205,8 @@ __device__ __forceinline__ void tile_product(const double* A, const double* B, i
 
 // Boxes of width W <= kSmallW: the blocks of a step are staged in LDS:
 //   G0, G1 (Gauss-Jordan; after it the one not holding S^-1 takes Uh(K,K+1)),
-//   A(K+1..K+2, K) -> Pa[2], A(K, K+1..K+2) -> Pu[2] (Uh(K,K+2) then over A(K,K+1)):
-//   6 W^2 doubles, four workgroups per CU at W = 24.  Lh goes from registers straight to the
+//   A(K+1..K+2, K) -> Pa[2], A(K, K+1..K+2) -> Pu[2], and Uh(K,K+2):
+//   7 W^2 doubles, four workgroups per CU at W = 24.  Lh goes from registers straight to the
 //   factors, and the Schur updates take the form A(I,J) -= A(I,K) Uh(K,J) (equal to
 //   Lh(I,K) A(K,J)), so neither Lh nor A(K,J) has to stay in LDS.
 // The blocks at distance 3, A(K+3, K) and A(K, K+3), are diagonal (the stencil reaches three
@@ -263,10 +263,11 @@ __global__ __launch_bounds__(256, WMAX <= 24 ? 4 : 3) void k_lu_factor_lds(const
         // Lh(I,K) = A(I,K) S^-1, I = K+1, K+2, tile by tile to the factors of row I (column
         // block 2 - bi), with A(I, K+3) -= Lh(I,K) diag(dB) applied from the same registers.
         // Uh(K,K+1) = S^-1 A(K,K+1) goes to the Gauss-Jordan buffer that does not hold S^-1,
-        // then Uh(K,K+2) = S^-1 A(K,K+2) over A(K,K+1), which is no longer read.
+        // Uh(K,K+2) = S^-1 A(K,K+2) to a buffer of its own, both in the same pass as Lh.
         double* Uh0 = Sinv == G0 ? G1 : G0;
-        double* Uh1 = Pu;
-        for (int t = tid; t < (nd + 1) * ntile; t += nt) {
+        double* Uh1 = lds + 6 * WW;
+        const int nprod = nd + 1 + (nd == 2 ? 1 : 0);
+        for (int t = tid; t < nprod * ntile; t += nt) {
             const int b = t / ntile, tile = t - b * ntile;
             double acc[4][4];
             int p0, q0;
@@ -283,26 +284,16 @@ __global__ __launch_bounds__(256, WMAX <= 24 ? 4 : 3) void k_lu_factor_lds(const
                             if (C3) C3[(p0 + a) * W + q0 + c] -= acc[a][c] * dB[q0 + c];
                         }
             } else {
-                tile_product<WMAX>(Sinv, Pu, W, tile, acc, &p0, &q0);
+                const int bj = b - nd;                 // Uh(K, K+1+bj)
+                double* U = bj == 0 ? Uh0 : Uh1;
+                tile_product<WMAX>(Sinv, Pu + bj * WW, W, tile, acc, &p0, &q0);
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
-                        if (p0 + a < W && q0 + c < W) Uh0[(p0 + a) * W + q0 + c] = acc[a][c];
+                        if (p0 + a < W && q0 + c < W) U[(p0 + a) * W + q0 + c] = acc[a][c];
             }
         }
-        __syncthreads();
-        if (nd == 2)
-            for (int t = tid; t < ntile; t += nt) {
-                double acc[4][4];
-                int p0, q0;
-                tile_product<WMAX>(Sinv, Pu + WW, W, t, acc, &p0, &q0);
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        if (p0 + a < W && q0 + c < W) Uh1[(p0 + a) * W + q0 + c] = acc[a][c];
-            }
         __syncthreads();
         const double* Uh[2] = {Uh0, Uh1};
         // block row K: S^-1 and -Uh(K, K+1..K+3) (zero past the box; Lh blocks before it zero);
@@ -692,7 +683,7 @@ hipError_t launch_apply_t(pfc_ctx* c, const double* r, double* z, const LuBox& b
 
 }  // namespace
 
-size_t lu_factor_lds_bytes(int W) { return sizeof(double) * (W <= kSmallW ? 6 : 2) * (size_t)W * W; }
+size_t lu_factor_lds_bytes(int W) { return sizeof(double) * (W <= kSmallW ? 7 : 2) * (size_t)W * W; }
 
 size_t lu_work_blocks(int W) { return W <= kSmallW ? 16 : 22; }
 

@@ -59,12 +59,18 @@ __device__ void stage_stencil(LdsStencil* t, const LuBox& b, const StencilTable&
 
 // Block (I, J) of A_k into dst (row-major).  crow holds c along box row J (W values).  With a
 // variable mobility (uu: u = (Phi + phi)/2, else null) the spatial part of row (I, p) is scaled
-// by its node mobility 1 - u^2, as subdomain_entry says.
+// by its node mobility 1 - u^2, as subdomain_entry says.  Entries first, first + stride, ...
+// (by default every thread of the block).
 __device__ void assemble_block(double* dst, int I, int J, const LuBox& b, const LdsStencil* t,
-                               const double* crow, const double* __restrict__ uu, int ox, int oy, double inv_dt) {
+                               const double* crow, const double* __restrict__ uu, int ox, int oy, double inv_dt,
+                               int first = -1, int stride = 0) {
     const int W = b.W, dy = J - I;
     const long grow = (long)wrapg(oy + I, b.ny) * b.nx;
-    for (int e = threadIdx.x; e < W * W; e += blockDim.x) {
+    if (first < 0) {
+        first = threadIdx.x;
+        stride = blockDim.x;
+    }
+    for (int e = first; e < W * W; e += stride) {
         const int p = e / W, q = e - p * W;
         const int dx = q - p;
         double v = 0.0;
@@ -267,6 +273,12 @@ __global__ __launch_bounds__(256, WMAX <= 24 ? 4 : 3) void k_lu_factor_lds(const
         double* Uh0 = Sinv == G0 ? G1 : G0;
         double* Uh1 = lds + 6 * WW;
         const int nprod = nd + 1 + (nd == 2 ? 1 : 0);
+        // Block row and column K + 4 enter the window in the slots of row and column K, which
+        // are staged and no longer read: the threads past the last product tile assemble them
+        // during this pass (at the end of the step if too few are left over).
+        const int N4 = K + 4;
+        const int idle0 = nprod * ntile;
+        const bool early = N4 < H && idle0 + 64 <= nt;
         for (int t = tid; t < nprod * ntile; t += nt) {
             const int b = t / ntile, tile = t - b * ntile;
             double acc[4][4];
@@ -293,6 +305,14 @@ __global__ __launch_bounds__(256, WMAX <= 24 ? 4 : 3) void k_lu_factor_lds(const
                     for (int c = 0; c < 4; ++c)
                         if (p0 + a < W && q0 + c < W) U[(p0 + a) * W + q0 + c] = acc[a][c];
             }
+        }
+        if (early && tid >= idle0) {
+            for (int J = K + 1; J <= N4; ++J)
+                assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy, st.inv_dt,
+                               tid - idle0, nt - idle0);
+            for (int I = K + 1; I < N4; ++I)
+                assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72, uu, ox, oy, st.inv_dt,
+                               tid - idle0, nt - idle0);
         }
         __syncthreads();
         const double* Uh[2] = {Uh0, Uh1};
@@ -340,9 +360,8 @@ __global__ __launch_bounds__(256, WMAX <= 24 ? 4 : 3) void k_lu_factor_lds(const
                     slot(win, K + 3, K + 3, W)[rm] -= dA[p] * Sinv[rm] * dB[q];
             }
         __syncthreads();
-        // slide the window: block row and column K + 4 enter
-        const int N4 = K + 4;
-        if (N4 < H) {
+        // slide the window: block row and column K + 4 enter (unless assembled above)
+        if (N4 < H && !early) {
             for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy,
                                                      st.inv_dt);
             for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72, uu, ox, oy,

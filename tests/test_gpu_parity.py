@@ -279,6 +279,8 @@ def test_ras_ilu0_3d_levels_wider_than_a_wave(shape, ext):
     (256, 100.0, (4, 32), 2, 10.0, True, 1e-4),
     (256, 100.0, (2, 16), 3, 10.0, False, 1e-9),       # 22-wide boxes, odd overlap, 134 rows
     (256, 100.0, (2, 16), 3, 10.0, True, 1e-4),
+    (256, 100.0, (4, 16), 7, 10.0, False, 1e-9),       # 30-wide boxes: the up-to-36 kernel, last pivot block of 2
+    (256, 100.0, (4, 16), 7, 10.0, True, 1e-4),
     (256, 100.0, (4, 4), 4, 10.0, True, 1e-4),         # FP32 on 72-wide boxes (the wide-box kernels)
     (256, 100.0, (4, 4), 3, 1.0, True, 1e-4),          # FP32 on 70-wide boxes, the crack workload's width
 ])

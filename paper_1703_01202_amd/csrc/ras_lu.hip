@@ -87,6 +87,30 @@ __device__ void assemble_block(double* dst, int I, int J, const LuBox& b, const 
     }
 }
 
+// As assemble_block, with c read from the field cc itself (box row J) instead of an LDS row.
+__device__ void assemble_block_field(double* dst, int I, int J, const LuBox& b, const LdsStencil* t,
+                                     const double* __restrict__ cc, const double* __restrict__ uu, int ox, int oy,
+                                     double inv_dt) {
+    const int W = b.W, dy = J - I;
+    const long grow = (long)wrapg(oy + I, b.ny) * b.nx;
+    const long crow = (long)wrapg(oy + J, b.ny) * b.nx;
+    for (int e = threadIdx.x; e < W * W; e += blockDim.x) {
+        const int p = e / W, q = e - p * W;
+        const int dx = q - p;
+        double v = 0.0;
+        if (abs(dx) + abs(dy) <= 3) {
+            const int o = (dy + 3) * 7 + dx + 3;
+            v = t->k[o] - t->d1[o] * cc[crow + wrapg(ox + q, b.nx)];
+            if (uu) {
+                const double u = uu[grow + wrapg(ox + p, b.nx)];
+                const double d = o == 24 ? inv_dt : 0.0;
+                v = d + (1.0 - u * u) * (v - d);
+            }
+        }
+        dst[e] = v;
+    }
+}
+
 // c along box row J into the LDS ring slot J % 8 (W <= 72 values per slot).
 __device__ void load_c_row(double* ring, int J, const LuBox& b, const double* __restrict__ cc, int ox, int oy) {
     const long row = (long)wrapg(oy + J, b.ny) * b.nx;
@@ -450,16 +474,16 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
     double* win = work + (long)k * 22 * WW;
     T* out = fac + (long)k * H * 7 * WW;
     const int tid = threadIdx.x, nt = blockDim.x;
+    // c is read from the field when a block is assembled (no LDS ring), which keeps a 70-wide
+    // box within half the LDS of a CU: two workgroups per CU instead of one
     __shared__ LdsStencil sst;
-    __shared__ double cring[8 * 72];        // c along the box rows entering the window
     __shared__ double dA[72], dB[72];       // diagonals of A(K+3, K) and A(K, K+3)
     stage_stencil(&sst, b, st);
-    for (int J = 0; J < 5 && J < H; ++J) load_c_row(cring, J, b, cc, ox, oy);
     __syncthreads();
 
     for (int I = 0; I < 4 && I < H; ++I)
         for (int J = 0; J < 4 && J < H; ++J)
-            assemble_block(slot(win, I, J, W), I, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy, st.inv_dt);
+            assemble_block_field(slot(win, I, J, W), I, J, b, &sst, cc, uu, ox, oy, st.inv_dt);
     __syncthreads();
 
     for (int K = 0; K < H; ++K) {
@@ -525,12 +549,11 @@ __global__ __launch_bounds__(256) void k_lu_factor_wide(const double* __restrict
         __syncthreads();
         const int N4 = K + 4;
         if (N4 < H) {
-            for (int J = K + 1; J <= N4; ++J) assemble_block(slot(win, N4, J, W), N4, J, b, &sst, cring + (J & 7) * 72, uu, ox, oy,
-                                                     st.inv_dt);
-            for (int I = K + 1; I < N4; ++I) assemble_block(slot(win, I, N4, W), I, N4, b, &sst, cring + (N4 & 7) * 72, uu, ox, oy,
-                                                     st.inv_dt);
+            for (int J = K + 1; J <= N4; ++J)
+                assemble_block_field(slot(win, N4, J, W), N4, J, b, &sst, cc, uu, ox, oy, st.inv_dt);
+            for (int I = K + 1; I < N4; ++I)
+                assemble_block_field(slot(win, I, N4, W), I, N4, b, &sst, cc, uu, ox, oy, st.inv_dt);
         }
-        if (N4 + 1 < H) load_c_row(cring, N4 + 1, b, cc, ox, oy);   // ring slot of row K-3, no longer read
         __syncthreads();
     }
 }

@@ -397,8 +397,11 @@ __global__ __launch_bounds__(256, WMAX <= 24 ? 4 : 3) void k_lu_factor_lds(const
 }
 
 // C (+)= sign * A B for W x W blocks with A streamed by rows from global memory and B in
-// LDS.  Thread t owns row p = t / TPR and the columns q = (t % TPR) + TPR * i; it keeps a
-// chunk of 8 entries of its row of A in registers, so A is read once per output row.
+// LDS.  Thread t owns row p = t / TPR and the columns q = (t % TPR) + TPR * i; it keeps
+// chunks of 8 entries of its row of A in registers, so A is read once per output row.  Two
+// chunk buffers alternate: the next chunk's loads are in flight while the current one is
+// used, and they are unconditional (index clamped; entries past the row count as zero when
+// used), so no select follows a load.
 template <int QMAX>
 __device__ void gemm_rows(double* C, const double* __restrict__ A, const double* B, int W, double sign,
                           bool accumulate) {
@@ -408,19 +411,29 @@ __device__ void gemm_rows(double* C, const double* __restrict__ A, const double*
     double acc[QMAX];
 #pragma unroll
     for (int i = 0; i < QMAX; ++i) acc[i] = 0.0;
-    for (int m0 = 0; m0 < W; m0 += 8) {
-        double a[8];
+    auto load = [&](double (&a)[8], int m0) {
 #pragma unroll
-        for (int mm = 0; mm < 8; ++mm) a[mm] = (m0 + mm < W) ? A[p * W + m0 + mm] : 0.0;
+        for (int mm = 0; mm < 8; ++mm) a[mm] = A[p * W + min(m0 + mm, W - 1)];
+    };
+    auto use = [&](const double (&a)[8], int m0) {
 #pragma unroll
         for (int i = 0; i < QMAX; ++i) {
             const int q = min(q0 + TPR * i, W - 1);     // clamped: tail lanes compute a discarded duplicate
 #pragma unroll
             for (int mm = 0; mm < 8; ++mm) {
-                const int m = min(m0 + mm, W - 1);       // a[mm] = 0 past the end
-                acc[i] += a[mm] * B[m * W + q];
+                const int m = min(m0 + mm, W - 1);
+                acc[i] += (m0 + mm < W ? a[mm] : 0.0) * B[m * W + q];
             }
         }
+    };
+    double a0[8], a1[8];
+    load(a0, 0);
+    for (int m0 = 0; m0 < W; m0 += 16) {
+        load(a1, m0 + 8);
+        use(a0, m0);
+        if (m0 + 8 >= W) break;
+        load(a0, m0 + 16);
+        use(a1, m0 + 8);
     }
 #pragma unroll
     for (int i = 0; i < QMAX; ++i) {
@@ -438,19 +451,30 @@ __device__ void gemm_cols(double* C, const double* A, const double* __restrict__
     double acc[PMAX];
 #pragma unroll
     for (int i = 0; i < PMAX; ++i) acc[i] = 0.0;
-    for (int m0 = 0; m0 < W; m0 += 8) {
-        double bcol[8];
+    // two alternating chunk buffers with unconditional loads, as in gemm_rows
+    auto load = [&](double (&bc)[8], int m0) {
 #pragma unroll
-        for (int mm = 0; mm < 8; ++mm) bcol[mm] = (m0 + mm < W) ? B[(m0 + mm) * W + q] : 0.0;
+        for (int mm = 0; mm < 8; ++mm) bc[mm] = B[min(m0 + mm, W - 1) * W + q];
+    };
+    auto use = [&](const double (&bc)[8], int m0) {
 #pragma unroll
         for (int i = 0; i < PMAX; ++i) {
             const int p = min(p0 + TPC * i, W - 1);
 #pragma unroll
             for (int mm = 0; mm < 8; ++mm) {
-                const int m = min(m0 + mm, W - 1);      // bcol[mm] = 0 past the end
-                acc[i] += A[p * W + m] * bcol[mm];
+                const int m = min(m0 + mm, W - 1);
+                acc[i] += A[p * W + m] * (m0 + mm < W ? bc[mm] : 0.0);
             }
         }
+    };
+    double b0[8], b1[8];
+    load(b0, 0);
+    for (int m0 = 0; m0 < W; m0 += 16) {
+        load(b1, m0 + 8);
+        use(b0, m0);
+        if (m0 + 8 >= W) break;
+        load(b0, m0 + 16);
+        use(b1, m0 + 8);
     }
 #pragma unroll
     for (int i = 0; i < PMAX; ++i) {
